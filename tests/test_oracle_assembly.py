@@ -1,0 +1,82 @@
+"""Pins for the oracle's Nedelec assembly (eq. (5), eq. (8), Sec. 2.1)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.assemble import Discretisation
+
+
+@pytest.fixture(scope="module")
+def d4():
+    return Discretisation(4, 2.0)
+
+
+def test_curl_grad_is_zero(d4):
+    """curl o grad = 0: the discrete gradients of interior hat functions lie
+    in the kernel of K."""
+    G = d4.discrete_gradient()
+    KG = (d4.K @ G).toarray()
+    assert np.abs(KG).max() <= 1e-13 * abs(d4.K).max()
+    assert G.shape == (316, 27)
+
+
+def test_symmetry_and_spd(d4):
+    for M in (d4.K, d4.M, d4.A):
+        assert abs(M - M.T).max() <= 1e-14 * abs(M).max()
+    np.linalg.cholesky(d4.M.toarray())                  # M is SPD
+
+
+def test_rank_of_curl_curl(d4):
+    """rank K = #interior edges - #interior vertices (exact discrete sequence
+    on the cube)."""
+    assert np.linalg.matrix_rank(d4.K.toarray()) == 316 - 27
+
+
+def test_inertia(d4):
+    """kappa^2 = 4 lies below the first positive discrete curl-curl
+    eigenvalue, so A = K - 4 M is negative exactly on the gradients:
+    (n - 1)^3 = 27 negative eigenvalues."""
+    ev = np.linalg.eigvalsh(d4.A.toarray())
+    assert int(np.sum(ev < 0)) == 27
+    assert np.min(np.abs(ev)) > 1e-8
+
+
+def _closed_form_mass(a, b):
+    """int over the unit cube of |a + b x x|^2."""
+    S = np.full((3, 3), 0.25) + np.eye(3) * (1.0 / 3.0 - 0.25)
+    xbar = np.full(3, 0.5)
+    return a @ a + 2 * a @ np.cross(b, xbar) + b @ b - b @ S @ b
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_linear_fields_exact(n):
+    """For E = a + b x x (in N_0 on every element) with edge values
+    u_e = E(mid_e) . (p_head - p_tail): u^T K u = |curl E|^2 = 4 |b|^2 and
+    u^T M u = int |E|^2, both exactly."""
+    d = Discretisation(n, 1.0)
+    rng = np.random.default_rng(n)
+    m = d.mesh
+    p = m.coords.astype(np.float64) / n
+    tail, head = p[m.edges[:, 0]], p[m.edges[:, 1]]
+    mid = 0.5 * (tail + head)
+    for _ in range(3):
+        a, b = rng.standard_normal(3), rng.standard_normal(3)
+        E = a + np.cross(b, mid)
+        u = np.einsum("ij,ij->i", E, head - tail)
+        assert abs(u @ (d.K_full @ u) - 4 * b @ b) <= 1e-12 * (1 + b @ b)
+        ref = _closed_form_mass(a, b)
+        assert abs(u @ (d.M_full @ u) - ref) <= 1e-12 * ref
+
+
+def test_cavity_eigenvalue_convergence():
+    """The smallest positive Maxwell eigenvalue of the unit cube with perfect
+    conductor walls is 2 pi^2 (triple); the discrete one converges at O(h^2)."""
+    errs = []
+    for n in (4, 8):
+        d = Discretisation(n, 0.0)
+        vals = sla.eigh(d.K.toarray(), d.M.toarray(), eigvals_only=True,
+                        subset_by_value=(1.0, 40.0))
+        pos = np.sort(vals)[:3]
+        errs.append(np.max(np.abs(pos - 2 * np.pi ** 2)) / (2 * np.pi ** 2))
+    assert errs[1] < 0.05
+    assert errs[0] / errs[1] > 3.0

@@ -1,0 +1,101 @@
+"""Pins for the oracle's mesh and sparsity pattern (mesh of Example 1, Sec. 4)."""
+import json
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+from oracle.assemble import Discretisation
+from oracle.mesh import KuhnMesh
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def e_total(n):
+    return 7 * n ** 3 + 9 * n ** 2 + 3 * n
+
+
+def e_int(n):
+    return 7 * n ** 3 - 9 * n ** 2 + 3 * n
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_counts_closed_form(n):
+    m = KuhnMesh(n)
+    assert len(m.tets) == 6 * n ** 3
+    assert len(m.edges) == e_total(n)
+    assert m.num_dofs == e_int(n)
+    assert len(m.interior_vertices()) == (n - 1) ** 3
+    # Euler characteristic of the ball: V - E + F - T = 1
+    faces = set()
+    for t in m.tets:
+        for f in combinations(sorted(int(v) for v in t), 3):
+            faces.add(f)
+    assert (n + 1) ** 3 - len(m.edges) + len(faces) - len(m.tets) == 1
+
+
+def test_table1_ndof_rows():
+    """Total edge counts against the N_dof column the paper prints."""
+    g = json.load(open(os.path.join(GOLDEN, "table1_ndof.json")))
+    for k in g["exact_rows"]:
+        assert e_total(2 ** (k - 1)) == g["printed"][str(k)]
+    for k in (2, 3):                      # small enough to build the mesh
+        assert len(KuhnMesh(2 ** (k - 1)).edges) == g["printed"][str(k)]
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_volumes_sum_to_one(n):
+    d = Discretisation(n, 1.0)
+    assert abs(d.volumes.sum() - 1.0) < 1e-14
+    assert np.all(d.volumes > 0)
+    assert np.allclose(d.volumes, 1.0 / (6 * n ** 3), rtol=0, atol=1e-15)
+
+
+def _in_one_kuhn_tet(points):
+    """Brute-force characterisation independent of the tet list: a point set
+    lies in one Kuhn tetrahedron iff it is a chain for the componentwise
+    order whose extent is at most one cell in every direction."""
+    pts = sorted({tuple(p) for p in points}, key=lambda p: (sum(p), p))
+    for a, b in zip(pts, pts[1:]):
+        if any(x > y for x, y in zip(a, b)):
+            return False
+    lo, hi = np.array(pts[0]), np.array(pts[-1])
+    return bool(np.all(hi - lo <= 1))
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_pattern_brute_force(n):
+    m = KuhnMesh(n)
+    d = Discretisation(n, 1.0)
+    e = m.interior_edges
+    c = m.coords
+    N = len(e)
+    dense = np.zeros((N, N), dtype=bool)
+    for i in range(N):
+        for j in range(N):
+            dense[i, j] = _in_one_kuhn_tet([c[e[i, 0]], c[e[i, 1]], c[e[j, 0]], c[e[j, 1]]])
+    pat = d.A.copy()
+    pat.data[:] = 1
+    assert np.array_equal(pat.toarray().astype(bool), dense)
+
+
+def test_pattern_counts():
+    # nnz per mesh size (counted independently by a separate throwaway
+    # enumeration when the workloads were sized): n=4: 3,916; n=8: 43,688.
+    assert Discretisation(4, 1.0).A.nnz == 3916
+    assert Discretisation(8, 1.0).A.nnz == 43688
+
+
+def test_edge_orientation_and_order():
+    m = KuhnMesh(3)
+    e = m.edges
+    assert np.all(e[:, 0] < e[:, 1])
+    assert np.all(np.diff(e[:, 0] * 10 ** 6 + e[:, 1]) > 0)
+    # every edge direction is one of the 7 Kuhn directions
+    d = m.coords[e[:, 1]] - m.coords[e[:, 0]]
+    assert np.all((d == 0) | (d == 1))
+    assert np.all(d.sum(axis=1) >= 1)
+    # midpoints are unique
+    mid = m.midpoints2()
+    assert len({tuple(x) for x in mid}) == len(mid)
