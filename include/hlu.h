@@ -1,0 +1,213 @@
+/*
+ * hlu.h -- C ABI of libhlu: H-LU preconditioned GMRES for the lowest-order
+ * Nedelec discretisation of the time-harmonic Maxwell equations on MI355X
+ * (gfx950).
+ *
+ * Method: Parvizi, Khodadadian, Beuchler, Wick, "Hierarchical LU
+ * preconditioning for the time-harmonic Maxwell equations" (arXiv 2211.11303).
+ *   - Galerkin matrix A = K - kappa^2 M of the Nedelec edge element
+ *     (Sec. 2.1, eq. (5) and eq. (8)); the paper's kappa is kappa^2 here.
+ *   - H-matrix on an eta-admissible block partition (Sec. 3, Definition 1),
+ *     eta = 2 and a geometric cluster tree (Sec. 4).
+ *   - H-LU factorisation (Algorithm 1, step II) with truncated SVD
+ *     recompression of the low-rank blocks (Sec. 4).
+ *   - Preconditioner application U^{-1}(L^{-1} r) (Algorithm 1, step III)
+ *     inside restarted GMRES (Sec. 4, Example 1).
+ *
+ * Conventions for every call:
+ *   - Every call returns an hlu_status.  No call aborts, throws or prints.
+ *     On failure hlu_last_error() returns a message for the calling thread.
+ *   - Pointers named d_* or documented as "device" are HIP device pointers;
+ *     all others are host pointers.  Inputs are borrowed: the library copies
+ *     what it keeps and never frees caller memory.
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *     Work is stream-ordered; calls that must report a device-side result
+ *     (hlu_factor, gmres_solve) synchronise that stream before returning.
+ *   - Dense vectors and blocks of vectors are column-major: nrhs columns of
+ *     length N with leading dimension ld >= N, in the natural (mesh) order of
+ *     the unknowns.
+ *   - On error a handle's state is unchanged.
+ */
+#ifndef HLU_H
+#define HLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HLU_OK = 0,
+  HLU_ERR_INVALID_ARG = -1,    /* a size, pointer or option is invalid        */
+  HLU_ERR_OUT_OF_MEMORY = -2,  /* a host or device allocation failed, or the
+                                  bound workspace is too small               */
+  HLU_ERR_DEVICE = -3,         /* a HIP runtime call failed                   */
+  HLU_ERR_ZERO_PIVOT = -4,     /* unpivoted LU met an exact zero pivot        */
+  HLU_ERR_NOT_CONVERGED = -5,  /* GMRES stopped at max_iters above tol        */
+  HLU_ERR_STATE = -6,          /* call out of order (e.g. solve before factor)*/
+  HLU_ERR_RANK_OVERFLOW = -7,  /* a truncated rank exceeded the block's
+                                  storage capacity (result kept at capacity)  */
+  HLU_ERR_UNSUPPORTED = -8     /* input outside what this build handles       */
+} hlu_status;
+
+typedef enum { HLU_FP64 = 0, HLU_FP32 = 1 } hlu_precision;
+
+typedef struct hlu_spmat_s* hlu_spmat;  /* device CSR of A, for y = A x      */
+typedef struct hlu_s* hlu_handle;       /* structure + H-LU of one problem    */
+
+/* Host CSR, 0-based, columns sorted ascending within each row. */
+typedef struct {
+  int32_t n;              /* rows = columns                                   */
+  int64_t nnz;
+  const int32_t* row_ptr; /* n + 1 entries                                    */
+  const int32_t* col;     /* nnz entries                                      */
+  const double* val;      /* nnz entries                                      */
+} hlu_csr;
+
+/* Truncation of every low-rank addition (Sec. 4): keep singular values
+ * sigma_i > eps * sigma_1, at most max_rank of them.
+ *   eps >= 0; eps == 0 keeps every non-zero triplet (no truncation);
+ *   max_rank > 0 caps the rank (the paper's fixed-rank mode) and sizes the
+ *   low-rank storage; max_rank == 0 means no cap, storage sized to
+ *   min(rows, cols, 64) per block and HLU_ERR_RANK_OVERFLOW if exceeded.
+ * prec: arithmetic and storage type of the factors (FP32 or FP64). */
+typedef struct {
+  double eps;
+  int32_t max_rank;
+  int32_t prec; /* hlu_precision */
+} hlu_factor_opts;
+
+typedef struct {
+  int32_t restart;   /* Krylov basis size per cycle, >= 1                    */
+  int32_t max_iters; /* total Arnoldi steps per right-hand side, >= 1        */
+  double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2               */
+} hlu_gmres_opts;
+
+typedef struct {
+  int32_t iters;     /* Arnoldi steps (= preconditioner applications)        */
+  int32_t converged; /* 1 if the true relative residual reached tol          */
+  double relres;     /* ||b - A x||_2 / ||b||_2 at exit (true residual)      */
+  double abs_res;    /* ||A x - b||_2, the "error" of Algorithm 1, step IV   */
+} hlu_gmres_info;
+
+typedef struct {
+  int64_t n;
+  int64_t num_clusters, num_leaf_clusters, depth;
+  int64_t num_admissible, num_dense;
+  int64_t dense_entries;         /* entries stored in dense leaves            */
+  int64_t lowrank_rows_plus_cols;/* sum over admissible blocks of (m + n)     */
+  int64_t workspace_bytes;       /* bound workspace needed by hlu_factor      */
+  int64_t factor_waves;          /* dependency levels of the factor schedule  */
+  int64_t factor_tasks;          /* primitive tasks in the factor schedule    */
+  int64_t solve_waves;           /* dependency levels of one forward+backward sweep */
+  int32_t max_rank;              /* largest rank after the factorisation      */
+  int32_t capped_blocks;         /* blocks whose eps-rank exceeded capacity   */
+  double mean_rank;              /* mean rank over admissible blocks          */
+  double lowrank_entries;        /* sum over admissible blocks of (m+n) rank  */
+  double min_abs_pivot, max_abs_pivot; /* over all diagonal leaves            */
+  double factor_flops;           /* nominal flops of the executed tasks       */
+} hlu_stats;
+
+/* ---------------------------------------------------------------- problem
+ * The Kuhn-split unit cube (Example 1, Sec. 4): n^3 cubes, each cut into six
+ * tetrahedra; unknowns are the N = 7n^3 - 9n^2 + 3n interior edges
+ * (perfect-conductor boundary, Sec. 2.1), ordered lexicographically by
+ * (tail vertex id, head vertex id) with vertex (i,j,k) -> i + (n+1)(j + (n+1)k)
+ * and edges oriented from the lower to the higher id. */
+
+/* N and nnz(A) for n >= 1. */
+hlu_status hlu_kuhn_sizes(int32_t n, int32_t* N, int64_t* nnz);
+
+/* Assemble A = K - kappa^2 M (exact element integrals of the Whitney edge
+ * basis) into caller-allocated host arrays: row_ptr[N+1], col[nnz],
+ * val[nnz]; and mid2[3N], the doubled lattice coordinates
+ * p_tail + p_head of each edge midpoint (row-major N x 3). */
+hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col,
+                             double* val, int32_t* mid2);
+
+/* ----------------------------------------------------------- sparse matrix
+ * Wraps a device CSR (borrowed: the caller keeps d_row_ptr[n+1], d_col[nnz],
+ * d_val[nnz] alive until hlu_spmat_destroy). */
+hlu_status hlu_spmat_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                            const int32_t* d_col, const double* d_val, hlu_spmat* out);
+void hlu_spmat_destroy(hlu_spmat A);
+
+/* Y = alpha A X + beta Y for nrhs device columns (ld >= n).  beta == 0
+ * ignores the input content of Y.  X and Y must not overlap. */
+hlu_status hlu_spmv(hlu_spmat A, const double* d_x, double* d_y, int32_t nrhs, int64_t ld,
+                    double alpha, double beta, void* stream);
+
+/* ------------------------------------------------------------- H-LU handle
+ * Algorithm 1, step I + the cluster and block trees of Sec. 3/4 (host work
+ * only).  A: host CSR; mid2: host N x 3 doubled midpoint coordinates, from
+ * which the geometric cluster tree is built (leaf clusters hold at most
+ * leaf_size indices); eta: admissibility parameter (min diam <= eta dist). */
+hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t leaf_size,
+                     hlu_handle* out);
+void hlu_destroy(hlu_handle h);
+
+/* Device bytes hlu_factor needs for these options (plans the schedule). */
+hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
+
+/* Hands the library a caller-owned device buffer of at least the bytes
+ * reported above (256-byte aligned).  It stays in use until re-bound or the
+ * handle is destroyed. */
+hlu_status hlu_bind_workspace(hlu_handle h, void* d_work, size_t bytes);
+
+/* Algorithm 1, step II: copies A into the H-matrix and computes L (unit
+ * lower) and U in H-arithmetic, in place, on the GPU.  Synchronises the
+ * stream and returns HLU_ERR_ZERO_PIVOT / HLU_ERR_RANK_OVERFLOW if the
+ * device reported them (after a zero pivot the handle is unfactored). */
+hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream);
+
+/* x = (L U)^{-1} b in the natural order, i.e. x = P^T U^{-1} L^{-1} P b
+ * (Algorithm 1, step III).  d_b, d_x: device, nrhs columns, leading
+ * dimension ld; d_x may alias d_b.  Stream-ordered, no synchronisation. */
+hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                     void* stream);
+
+/* y = P^T L U P v (the product of the computed factors), for checking the
+ * factor error; same layout rules as hlu_solve (no aliasing). */
+hlu_status hlu_apply_lu(hlu_handle h, const double* d_v, double* d_y, int32_t nrhs, int64_t ld,
+                        void* stream);
+
+/* Restarted right-preconditioned flexible GMRES (Sec. 4), x0 = 0, modified
+ * Gram-Schmidt, FP64 throughout; precond may be NULL.  Each of the nrhs
+ * columns is solved independently (iterations batched across columns).
+ * info: host array of nrhs entries.  d_work: caller-owned device buffer of
+ * gmres_workspace_bytes(n, nrhs, restart) bytes.  Synchronises the stream.
+ * Returns HLU_ERR_NOT_CONVERGED if any column missed tol (x then holds the
+ * last iterate). */
+size_t gmres_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart);
+hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                       hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info,
+                       void* d_work, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------ inspection */
+/* Sizes of the structure arrays, then a copy of them into caller-allocated
+ * host arrays (any pointer may be NULL to skip it):
+ *   perm[N]: natural index of the i-th index in cluster order;
+ *   clusters: begin[C], end[C], level[C], son0[C], son1[C] (-1 for leaves),
+ *             pre-order;
+ *   blocks (leaves of the block tree, pre-order): brow[B], bcol[B] (cluster
+ *             ids), bkind[B] (0 dense, 1 low-rank). */
+hlu_status hlu_structure_sizes(hlu_handle h, int32_t* N, int32_t* num_clusters,
+                               int32_t* num_blocks);
+hlu_status hlu_export_structure(hlu_handle h, int32_t* perm, int32_t* begin, int32_t* end,
+                                int32_t* level, int32_t* son0, int32_t* son1, int32_t* brow,
+                                int32_t* bcol, int32_t* bkind);
+
+/* Ranks of the admissible blocks (in block pre-order, B entries, -1 for
+ * dense blocks) after hlu_factor. Synchronous. */
+hlu_status hlu_get_ranks(hlu_handle h, int32_t* ranks);
+hlu_status hlu_get_stats(hlu_handle h, hlu_stats* out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hlu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLU_H */

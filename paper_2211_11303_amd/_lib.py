@@ -1,0 +1,109 @@
+"""ctypes declarations of the C ABI in include/hlu.h (argument marshalling
+only).  Loading fails loudly if libhlu.so has not been built."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhlu.so")
+
+c_int32 = ctypes.c_int32
+c_int64 = ctypes.c_int64
+c_double = ctypes.c_double
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+P_i32 = ctypes.POINTER(ctypes.c_int32)
+P_f64 = ctypes.POINTER(ctypes.c_double)
+
+HLU_OK = 0
+STATUS = {
+    0: "HLU_OK", -1: "HLU_ERR_INVALID_ARG", -2: "HLU_ERR_OUT_OF_MEMORY", -3: "HLU_ERR_DEVICE",
+    -4: "HLU_ERR_ZERO_PIVOT", -5: "HLU_ERR_NOT_CONVERGED", -6: "HLU_ERR_STATE",
+    -7: "HLU_ERR_RANK_OVERFLOW", -8: "HLU_ERR_UNSUPPORTED",
+}
+HLU_FP64, HLU_FP32 = 0, 1
+
+
+class HluCsr(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("nnz", c_int64), ("row_ptr", P_i32), ("col", P_i32), ("val", P_f64)]
+
+
+class FactorOpts(ctypes.Structure):
+    _fields_ = [("eps", c_double), ("max_rank", c_int32), ("prec", c_int32)]
+
+
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("restart", c_int32), ("max_iters", c_int32), ("tol", c_double)]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("converged", c_int32), ("relres", c_double), ("abs_res", c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int64), ("num_clusters", c_int64), ("num_leaf_clusters", c_int64), ("depth", c_int64),
+        ("num_admissible", c_int64), ("num_dense", c_int64), ("dense_entries", c_int64),
+        ("lowrank_rows_plus_cols", c_int64), ("workspace_bytes", c_int64), ("factor_waves", c_int64),
+        ("factor_tasks", c_int64), ("solve_waves", c_int64), ("max_rank", c_int32),
+        ("capped_blocks", c_int32), ("mean_rank", c_double), ("lowrank_entries", c_double),
+        ("min_abs_pivot", c_double), ("max_abs_pivot", c_double), ("factor_flops", c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "hlu_last_error": (ctypes.c_char_p, []),
+    "hlu_kuhn_sizes": (c_int32, [c_int32, P_i32, ctypes.POINTER(c_int64)]),
+    "hlu_kuhn_assemble": (c_int32, [c_int32, c_double, P_i32, P_i32, P_f64, P_i32]),
+    "hlu_spmat_create": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "hlu_spmat_destroy": (None, [c_void_p]),
+    "hlu_spmv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_double, c_double, c_void_p]),
+    "hlu_build": (c_int32, [ctypes.POINTER(HluCsr), P_i32, c_double, c_int32, ctypes.POINTER(c_void_p)]),
+    "hlu_destroy": (None, [c_void_p]),
+    "hlu_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
+    "hlu_bind_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "hlu_factor": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), c_void_p]),
+    "hlu_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p]),
+    "hlu_apply_lu": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p]),
+    "gmres_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "gmres_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
+                              ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), c_void_p, c_size_t,
+                              c_void_p]),
+    "hlu_structure_sizes": (c_int32, [c_void_p, P_i32, P_i32, P_i32]),
+    "hlu_export_structure": (c_int32, [c_void_p, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32,
+                                       P_i32]),
+    "hlu_get_ranks": (c_int32, [c_void_p, P_i32]),
+    "hlu_get_stats": (c_int32, [c_void_p, ctypes.POINTER(Stats)]),
+}
+
+_lib = None
+
+
+class HluError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded library (raises if libhlu.so is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libhlu.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != HLU_OK:
+        raise HluError(status, lib().hlu_last_error().decode())
+    return status

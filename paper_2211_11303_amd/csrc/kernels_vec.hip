@@ -1,0 +1,292 @@
+// Vector kernels: CSR SpMV of A (FP64), permutation/cast between the natural
+// and the cluster order, scatter of A into the H-matrix arena, and the
+// reductions and updates of GMRES (FP64).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hlu {
+namespace dev {
+
+// Y = alpha A X + beta Y, nrhs columns.  One 64-lane wavefront per row
+// group: each lane takes one nonzero, the row sum is a wavefront reduction;
+// rows with more than 64 entries loop.
+template <int RHS>
+__global__ void __launch_bounds__(256) spmv_kernel(int32_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ ci,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ x, double* __restrict__ y,
+                                                   int32_t nrhs, int64_t ld, double alpha, double beta) {
+  // 4 rows per wavefront: 16 lanes per row (rows hold 7..27 entries)
+  const int lane = threadIdx.x & 15;
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  if (row >= n) return;
+  const int p0 = rp[row], p1 = rp[row + 1];
+  for (int c0 = 0; c0 < nrhs; c0 += RHS) {
+    double s[RHS];
+#pragma unroll
+    for (int c = 0; c < RHS; ++c) s[c] = 0.0;
+    for (int p = p0 + lane; p < p1; p += 16) {
+      const double a = val[p];
+      const int j = ci[p];
+#pragma unroll
+      for (int c = 0; c < RHS; ++c)
+        if (c0 + c < nrhs) s[c] += a * x[j + (int64_t)(c0 + c) * ld];
+    }
+#pragma unroll
+    for (int c = 0; c < RHS; ++c) {
+      double v = s[c];
+      v += __shfl_xor(v, 8, 16);
+      v += __shfl_xor(v, 4, 16);
+      v += __shfl_xor(v, 2, 16);
+      v += __shfl_xor(v, 1, 16);
+      s[c] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < RHS; ++c)
+        if (c0 + c < nrhs) {
+          double* yy = y + row + (int64_t)(c0 + c) * ld;
+          *yy = (beta == 0.0 ? 0.0 : beta * *yy) + alpha * s[c];
+        }
+    }
+  }
+}
+
+// dst[i + c*ldd] = T(src[perm[i] + c*lds])  (natural -> cluster order)
+template <class T>
+__global__ void gather_kernel(int32_t n, int32_t nrhs, const int32_t* __restrict__ perm,
+                              const double* __restrict__ src, int64_t lds, T* __restrict__ dst, int64_t ldd) {
+  const int64_t total = (int64_t)n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    dst[i + c * ldd] = T(src[perm[i] + c * lds]);
+  }
+}
+
+// dst[perm[i] + c*ldd] = double(src[i + c*lds])  (cluster -> natural order)
+template <class T>
+__global__ void scatter_perm_kernel(int32_t n, int32_t nrhs, const int32_t* __restrict__ perm,
+                                    const T* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                                    int64_t ldd) {
+  const int64_t total = (int64_t)n * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    dst[perm[i] + c * ldd] = double(src[i + c * lds]);
+  }
+}
+
+// arena[target[e]] = T(val[e]) for every stored entry of A
+template <class T>
+__global__ void scatter_values_kernel(int64_t nnz, const int64_t* __restrict__ target,
+                                      const double* __restrict__ val, T* __restrict__ arena) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+    arena[target[e]] = T(val[e]);
+}
+
+template <class T>
+__global__ void zero_kernel(T* __restrict__ p, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = T(0);
+}
+
+template <class T>
+__global__ void identity_kernel(T* __restrict__ p, int32_t n) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x)
+    p[e] = (e % n == e / n) ? T(1) : T(0);
+}
+
+__global__ void set_int_kernel(int32_t* p, int32_t v) { *p = v; }
+
+__global__ void zero_int_kernel(int32_t* p, int32_t n) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) p[e] = 0;
+}
+
+// ---------------------------------------------------------------- GMRES
+// Partial dot products: for each column c < nrhs and each basis vector
+// i < nv: part[blk][i][c] = sum over this block's rows of V_i[:, c] w[:, c].
+// V_i is the block at V + i * vstride; columns have leading dimension N.
+constexpr int kDotBlocks = 256;
+
+__global__ void __launch_bounds__(256) multidot_kernel(int32_t N, int32_t nrhs, int32_t nv,
+                                                       const double* __restrict__ V, int64_t vstride,
+                                                       const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per, r1 = min((int64_t)N, r0 + per);
+  for (int i = 0; i < nv; ++i)
+    for (int c = 0; c < nrhs; ++c) {
+      const double* v = V + i * vstride + (int64_t)c * N;
+      const double* ww = w + (int64_t)c * N;
+      double s = 0.0;
+      for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) s += v[r] * ww[r];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        part[((int64_t)blockIdx.x * nv + i) * nrhs + c] = red[0] + red[1] + red[2] + red[3];
+      __syncthreads();
+    }
+}
+
+// out[i][c] = sum over blocks of part[blk][i][c], fixed order (deterministic)
+__global__ void finish_dot_kernel(int32_t nblk, int32_t nv, int32_t nrhs, const double* __restrict__ part,
+                                  double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nv * nrhs) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nv * nrhs + e];
+  out[e] = s;
+}
+
+// w[:, c] -= sum_i h[i][c] V_i[:, c]
+__global__ void orth_update_kernel(int32_t N, int32_t nrhs, int32_t nv, const double* __restrict__ V,
+                                   int64_t vstride, const double* __restrict__ h, double* __restrict__ w) {
+  const int64_t total = (int64_t)N * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / N);
+    double s = w[e];
+    for (int i = 0; i < nv; ++i) s -= h[i * nrhs + c] * V[i * vstride + e];
+    w[e] = s;
+  }
+}
+
+// dst[:, c] = scale[c] * src[:, c]   (scale read on the device)
+__global__ void scale_cols_kernel(int32_t N, int32_t nrhs, const double* __restrict__ src,
+                                  const double* __restrict__ scale, double* __restrict__ dst) {
+  const int64_t total = (int64_t)N * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = scale[e / N] * src[e];
+}
+
+// x[:, c] (ld) += sum_i y[i][c] Z_i[:, c]
+__global__ void combine_kernel(int32_t N, int32_t nrhs, int32_t nz, const double* __restrict__ Z, int64_t zstride,
+                               const double* __restrict__ y, double* __restrict__ x, int64_t ldx) {
+  const int64_t total = (int64_t)N * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / N), r = (int)(e % N);
+    double s = 0.0;
+    for (int i = 0; i < nz; ++i) s += y[i * nrhs + c] * Z[i * zstride + e];
+    x[r + c * ldx] += s;
+  }
+}
+
+// r[:, c] = b[:, c] - r[:, c]  (r holds A x on entry); b has leading dim ldb
+__global__ void residual_kernel(int32_t N, int32_t nrhs, const double* __restrict__ b, int64_t ldb,
+                                double* __restrict__ r) {
+  const int64_t total = (int64_t)N * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / N), i = (int)(e % N);
+    r[e] = b[i + c * ldb] - r[e];
+  }
+}
+
+__global__ void copy_cols_kernel(int32_t N, int32_t nrhs, const double* __restrict__ src, int64_t lds,
+                                 double* __restrict__ dst, int64_t ldd) {
+  const int64_t total = (int64_t)N * nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / N), i = (int)(e % N);
+    dst[i + c * ldd] = src[i + c * lds];
+  }
+}
+
+}  // namespace dev
+
+static inline int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+hipError_t spmv_launch(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
+                       double* y, int32_t nrhs, int64_t ld, double alpha, double beta, hipStream_t s) {
+  const int rows_per_block = 256 / 16;
+  const int grid = (n + rows_per_block - 1) / rows_per_block;
+  if (nrhs >= 4)
+    dev::spmv_kernel<4><<<grid, 256, 0, s>>>(n, rp, ci, val, x, y, nrhs, ld, alpha, beta);
+  else
+    dev::spmv_kernel<1><<<grid, 256, 0, s>>>(n, rp, ci, val, x, y, nrhs, ld, alpha, beta);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t gather_launch(int32_t n, int32_t nrhs, const int32_t* perm, const double* src, int64_t lds, T* dst,
+                         int64_t ldd, hipStream_t s) {
+  dev::gather_kernel<T><<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(n, nrhs, perm, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t scatter_perm_launch(int32_t n, int32_t nrhs, const int32_t* perm, const T* src, int64_t lds,
+                               double* dst, int64_t ldd, hipStream_t s) {
+  dev::scatter_perm_kernel<T><<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(n, nrhs, perm, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t scatter_values_launch(int64_t nnz, const int64_t* target, const double* val, T* arena, hipStream_t s) {
+  dev::scatter_values_kernel<T><<<grid_for(nnz), 256, 0, s>>>(nnz, target, val, arena);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t zero_launch(T* p, int64_t n, hipStream_t s) {
+  dev::zero_kernel<T><<<grid_for(n), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t identity_launch(T* p, int32_t n, hipStream_t s) {
+  dev::identity_kernel<T><<<grid_for((int64_t)n * n), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+hipError_t set_int_launch(int32_t* p, int32_t v, hipStream_t s) {
+  dev::set_int_kernel<<<1, 1, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+hipError_t zero_int_launch(int32_t* p, int32_t n, hipStream_t s) {
+  dev::zero_int_kernel<<<grid_for(n), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                          \
+  template hipError_t gather_launch<T>(int32_t, int32_t, const int32_t*, const double*, int64_t, T*, int64_t, \
+                                       hipStream_t);                                                     \
+  template hipError_t scatter_perm_launch<T>(int32_t, int32_t, const int32_t*, const T*, int64_t, double*,  \
+                                             int64_t, hipStream_t);                                      \
+  template hipError_t scatter_values_launch<T>(int64_t, const int64_t*, const double*, T*, hipStream_t);  \
+  template hipError_t zero_launch<T>(T*, int64_t, hipStream_t);                                          \
+  template hipError_t identity_launch<T>(T*, int32_t, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+// GMRES helpers
+hipError_t multidot_launch(int32_t N, int32_t nrhs, int32_t nv, const double* V, int64_t vstride, const double* w,
+                           double* part, double* out, hipStream_t s) {
+  dev::multidot_kernel<<<dev::kDotBlocks, 256, 0, s>>>(N, nrhs, nv, V, vstride, w, part);
+  const int e = nv * nrhs;
+  dev::finish_dot_kernel<<<(e + 255) / 256, 256, 0, s>>>(dev::kDotBlocks, nv, nrhs, part, out);
+  return hipGetLastError();
+}
+hipError_t orth_update_launch(int32_t N, int32_t nrhs, int32_t nv, const double* V, int64_t vstride, const double* h,
+                              double* w, hipStream_t s) {
+  dev::orth_update_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, nv, V, vstride, h, w);
+  return hipGetLastError();
+}
+hipError_t scale_cols_launch(int32_t N, int32_t nrhs, const double* src, const double* scale, double* dst,
+                             hipStream_t s) {
+  dev::scale_cols_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, src, scale, dst);
+  return hipGetLastError();
+}
+hipError_t combine_launch(int32_t N, int32_t nrhs, int32_t nz, const double* Z, int64_t zstride, const double* y,
+                          double* x, int64_t ldx, hipStream_t s) {
+  dev::combine_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, nz, Z, zstride, y, x, ldx);
+  return hipGetLastError();
+}
+hipError_t residual_launch(int32_t N, int32_t nrhs, const double* b, int64_t ldb, double* r, hipStream_t s) {
+  dev::residual_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, b, ldb, r);
+  return hipGetLastError();
+}
+hipError_t copy_cols_launch(int32_t N, int32_t nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,
+                            hipStream_t s) {
+  dev::copy_cols_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+}  // namespace hlu

@@ -1,0 +1,189 @@
+// Kuhn-split cube mesh and the lowest-order Nedelec Galerkin matrix
+// A = K - kappa^2 M (Sec. 2.1, eq. (5), eq. (8)) on its interior edges.
+//
+// Every cube (i,j,k) of the n^3 grid is cut into the six tetrahedra
+// {c, c+e_p0, c+e_p0+e_p1, c+(1,1,1)}, one per axis permutation p.  Edges
+// run from the lower vertex id to the higher; an edge is interior unless both
+// ends lie in one boundary face plane.  The Whitney function of edge (a,b) is
+// lambda_a grad(lambda_b) - lambda_b grad(lambda_a); its curl is
+// 2 grad(lambda_a) x grad(lambda_b), and the mass integrals use
+// int_T lambda_x lambda_y = |T| (1 + delta_xy) / 20, so both element
+// matrices are exact.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace hlu {
+namespace {
+
+// The seven edge directions of the Kuhn mesh, ordered by the id offset they
+// add (so that the outgoing edges of a vertex come in increasing head id).
+const int kDir[7][3] = {{1, 0, 0}, {0, 1, 0}, {1, 1, 0}, {0, 0, 1},
+                        {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
+
+int dir_index(int dx, int dy, int dz) {
+  for (int d = 0; d < 7; ++d)
+    if (kDir[d][0] == dx && kDir[d][1] == dy && kDir[d][2] == dz) return d;
+  return -1;
+}
+
+struct KuhnDofs {
+  int n;
+  int64_t nv;
+  std::vector<int32_t> dof;  // [vertex * 7 + dir] -> interior dof or -1
+  int32_t N = 0;
+
+  explicit KuhnDofs(int n_) : n(n_), nv((int64_t)(n_ + 1) * (n_ + 1) * (n_ + 1)) {
+    dof.assign(nv * 7, -1);
+    for (int64_t v = 0; v < nv; ++v) {
+      int p[3] = {int(v % (n + 1)), int((v / (n + 1)) % (n + 1)), int(v / ((int64_t)(n + 1) * (n + 1)))};
+      for (int d = 0; d < 7; ++d) {
+        bool inside = true, boundary = false;
+        for (int a = 0; a < 3; ++a) {
+          int q = p[a] + kDir[d][a];
+          if (q > n) inside = false;
+          if (kDir[d][a] == 0 && (p[a] == 0 || p[a] == n)) boundary = true;
+        }
+        if (inside && !boundary) dof[v * 7 + d] = N++;
+      }
+    }
+  }
+  int64_t vid(int i, int j, int k) const { return i + (int64_t)(n + 1) * (j + (int64_t)(n + 1) * k); }
+};
+
+void cross(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+const int kLocalEdge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+// Local K and M of one tetrahedron with vertex coordinates x[4][3].
+void element(const double x[4][3], double Kl[6][6], double Ml[6][6]) {
+  double J[3][3];  // columns x1-x0, x2-x0, x3-x0
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) J[r][c] = x[c + 1][r] - x[0][r];
+  double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+               J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  double vol = std::fabs(det) / 6.0;
+  // rows of J^{-1} are the gradients of lambda_1..lambda_3
+  double inv[3][3];
+  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  double g[4][3];
+  for (int a = 0; a < 3; ++a) {
+    g[a + 1][0] = inv[a][0];
+    g[a + 1][1] = inv[a][1];
+    g[a + 1][2] = inv[a][2];
+  }
+  for (int c = 0; c < 3; ++c) g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
+  auto I = [&](int p, int q) { return vol * (p == q ? 2.0 : 1.0) / 20.0; };
+  for (int e = 0; e < 6; ++e) {
+    int a = kLocalEdge[e][0], b = kLocalEdge[e][1];
+    double ce[3];
+    cross(g[a], g[b], ce);
+    for (int f = 0; f < 6; ++f) {
+      int c = kLocalEdge[f][0], d = kLocalEdge[f][1];
+      double cf[3];
+      cross(g[c], g[d], cf);
+      Kl[e][f] = 4.0 * vol * dot3(ce, cf);
+      Ml[e][f] = dot3(g[b], g[d]) * I(a, c) - dot3(g[b], g[c]) * I(a, d) -
+                 dot3(g[a], g[d]) * I(b, c) + dot3(g[a], g[c]) * I(b, d);
+    }
+  }
+}
+
+struct Triplet {
+  int32_t r, c;
+  double v;
+};
+
+void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
+              std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* Nout) {
+  KuhnDofs D(n);
+  const int N = D.N;
+  const double k2 = kappa * kappa;
+  std::vector<Triplet> trip;
+  trip.reserve((size_t)6 * n * n * n * 36);
+  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        for (int p = 0; p < 6; ++p) {
+          int v[4][3];
+          v[0][0] = i; v[0][1] = j; v[0][2] = k;
+          for (int s = 0; s < 3; ++s) {
+            for (int a = 0; a < 3; ++a) v[s + 1][a] = v[s][a];
+            v[s + 1][perms[p][s]] += 1;
+          }
+          double x[4][3];
+          for (int s = 0; s < 4; ++s)
+            for (int a = 0; a < 3; ++a) x[s][a] = double(v[s][a]) / n;
+          double Kl[6][6], Ml[6][6];
+          element(x, Kl, Ml);
+          int32_t ld[6];
+          for (int e = 0; e < 6; ++e) {
+            const int* va = v[kLocalEdge[e][0]];
+            const int* vb = v[kLocalEdge[e][1]];
+            int d = dir_index(vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]);
+            ld[e] = D.dof[D.vid(va[0], va[1], va[2]) * 7 + d];
+          }
+          for (int e = 0; e < 6; ++e) {
+            if (ld[e] < 0) continue;
+            for (int f = 0; f < 6; ++f) {
+              if (ld[f] < 0) continue;
+              trip.push_back({ld[e], ld[f], Kl[e][f] - k2 * Ml[e][f]});
+            }
+          }
+        }
+  std::sort(trip.begin(), trip.end(), [](const Triplet& a, const Triplet& b) {
+    return a.r != b.r ? a.r < b.r : a.c < b.c;
+  });
+  row_ptr->assign(N + 1, 0);
+  col->clear();
+  val->clear();
+  for (size_t t = 0; t < trip.size();) {
+    size_t u = t;
+    double s = 0.0;
+    // sum duplicates in the order the elements were visited
+    while (u < trip.size() && trip[u].r == trip[t].r && trip[u].c == trip[t].c) s += trip[u++].v;
+    col->push_back(trip[t].c);
+    val->push_back(s);
+    (*row_ptr)[trip[t].r + 1]++;
+    t = u;
+  }
+  for (int r = 0; r < N; ++r) (*row_ptr)[r + 1] += (*row_ptr)[r];
+  if (mid2) {
+    mid2->assign((size_t)3 * N, 0);
+    for (int64_t vtx = 0; vtx < D.nv; ++vtx)
+      for (int d = 0; d < 7; ++d) {
+        int32_t q = D.dof[vtx * 7 + d];
+        if (q < 0) continue;
+        int p[3] = {int(vtx % (n + 1)), int((vtx / (n + 1)) % (n + 1)), int(vtx / ((int64_t)(n + 1) * (n + 1)))};
+        for (int a = 0; a < 3; ++a) (*mid2)[3 * q + a] = 2 * p[a] + kDir[d][a];
+      }
+  }
+  *Nout = N;
+}
+
+}  // namespace
+
+void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
+                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N) {
+  assemble(n, kappa, row_ptr, col, val, mid2, N);
+}
+
+}  // namespace hlu

@@ -1,0 +1,942 @@
+// Planner: unrolls the recursive H-LU (Algorithm 1, step II, in the 2 x 2
+// block form L11 U11 = A11, U12 = L11^{-1} A12, L21 = A21 U11^{-1},
+// A22 <- A22 - L21 U12, then the same on A22), the H-triangular solves of
+// Algorithm 1, step III, and the product L U into lists of primitive tasks:
+//
+//   GETRF  unpivoted LU of a dense diagonal leaf
+//   TRI    triangular solve / multiply with a dense diagonal leaf
+//   GEMM   C = beta C + sum_t alpha_t A_t B_t  (one output tile list)
+//   TRUNC  low-rank C <- best approximation of C + sum_p alpha_p X_p Y_p^T
+//          within the block's rank rule (truncated SVD, Sec. 4)
+//   FILL   constant fill
+//
+// Tasks are emitted in the order of the sequential recursion.  Each task
+// records which memory segments it reads and writes (a segment is the part
+// of a buffer that belongs to one leaf cluster in each spatial dimension);
+// it is placed in the earliest wave after every earlier task it conflicts
+// with (read-after-write, write-after-read, write-after-write).  Tasks of
+// one wave touch disjoint data and run as batched launches, so executing the
+// waves in order gives exactly the sequential result.
+//
+// Products of H-blocks with blocks of vectors (H-matrix times matrix) are
+// emitted in two phases: first T_l = Y_l^T V for every low-rank leaf l, then
+// one GEMM task per leaf-cluster segment of the output that sums all dense
+// leaf products D V and low-rank products X_l T_l landing there.
+#include "plan.h"
+
+#include <algorithm>
+#include <climits>
+#include <map>
+#include <queue>
+
+#include "common.h"
+
+namespace hlu {
+namespace {
+
+constexpr int kTile = 64;
+
+struct Buf {
+  int32_t rl0, nrl;   // first leaf ordinal and count along buffer rows (nrl = 0: not spatial)
+  int32_t cl0, ncl;   // same along buffer columns
+  int64_t seg0;
+};
+
+struct View {
+  int64_t off;
+  int32_t rs, cs;
+  int32_t rows, cols;       // logical dim codes
+  int32_t rows_s, cols_s;   // logical static extents (capacities)
+  int32_t r0, c0;           // logical absolute positions of row/col 0 (-1: not spatial)
+  int32_t buf;              // -1: constant data, not tracked
+  bool tr;                  // logical = transpose of the buffer orientation
+  MatRef ref() const { return MatRef{off, rs, cs, rows, cols}; }
+};
+
+View transpose(View v) {
+  std::swap(v.rs, v.cs);
+  std::swap(v.rows, v.cols);
+  std::swap(v.rows_s, v.cols_s);
+  std::swap(v.r0, v.c0);
+  v.tr = !v.tr;
+  return v;
+}
+
+View sub_rows(View v, int32_t a0, int32_t a1) {
+  HLU_REQUIRE(v.r0 >= 0 && a0 >= v.r0 && a1 <= v.r0 + v.rows_s && a0 < a1, HLU_ERR_INVALID_ARG,
+              "planner: bad row restriction");
+  v.off += (int64_t)(a0 - v.r0) * v.rs;
+  v.rows = v.rows_s = a1 - a0;
+  v.r0 = a0;
+  return v;
+}
+
+View sub_cols(View v, int32_t a0, int32_t a1) {
+  HLU_REQUIRE(v.c0 >= 0 && a0 >= v.c0 && a1 <= v.c0 + v.cols_s && a0 < a1, HLU_ERR_INVALID_ARG,
+              "planner: bad column restriction");
+  v.off += (int64_t)(a0 - v.c0) * v.cs;
+  v.cols = v.cols_s = a1 - a0;
+  v.c0 = a0;
+  return v;
+}
+
+int32_t dyn(int32_t slot) { return -(slot + 1); }
+
+// H-block handle: a node of the block tree or a temporary low-rank block.
+struct HB {
+  BlockKind kind;
+  int32_t node;      // block-tree node id (-1 for temporaries)
+  int32_t r0, r1, c0, c1;
+  View D, X, Y;      // storage of leaves
+  int32_t slot = -1, cap = 0;
+};
+
+struct Access {
+  View v;
+  bool write;
+};
+
+class Planner {
+ public:
+  Planner(const Structure& S, StoragePlan& st) : S_(S), st_(st) {
+    leaf_of_pos_.resize(S.N);
+    for (size_t l = 0; l < S.leaf_clusters.size(); ++l) {
+      const ClusterNode& c = S.clusters[S.leaf_clusters[l]];
+      for (int32_t p = c.begin; p < c.end; ++p) leaf_of_pos_[p] = (int32_t)l;
+    }
+  }
+
+  // ------------------------------------------------------------ storage
+  void layout(int32_t kcap, const std::vector<int32_t>& nz_adm, std::vector<InitBlock>* inits) {
+    const int32_t nleaf = (int32_t)S_.leaves.size();
+    st_.off.assign(nleaf, -1);
+    st_.yoff.assign(nleaf, -1);
+    st_.cap.assign(nleaf, 0);
+    st_.slot.assign(nleaf, -1);
+    int64_t top = 0;
+    int32_t slots = 0;
+    leaf_buf_.assign(nleaf, -1);
+    leaf_ybuf_.assign(nleaf, -1);
+    int32_t maxleaf = 1;
+    for (int32_t c : S_.leaf_clusters) maxleaf = std::max(maxleaf, S_.clusters[c].size());
+    for (int32_t l : nz_adm) {
+      const BlockNode& b = S_.blocks[S_.leaves[l]];
+      maxleaf = std::max(maxleaf, std::min(S_.clusters[b.row].size(), S_.clusters[b.col].size()));
+    }
+    st_.identity_n = maxleaf;
+    st_.identity_off = top;
+    top += align((int64_t)maxleaf * maxleaf);
+    for (int32_t l = 0; l < nleaf; ++l) {
+      const BlockNode& b = S_.blocks[S_.leaves[l]];
+      const ClusterNode& rc = S_.clusters[b.row];
+      const ClusterNode& cc = S_.clusters[b.col];
+      const int32_t m = rc.size(), n = cc.size();
+      if (b.kind == kDense) {
+        st_.off[l] = top;
+        top += align((int64_t)m * n);
+        leaf_buf_[l] = new_buf(rc.leaf_first, rc.leaf_last - rc.leaf_first, cc.leaf_first,
+                               cc.leaf_last - cc.leaf_first);
+      } else {
+        const int32_t cap = std::max(1, std::min(std::min(m, n), kcap));
+        st_.cap[l] = cap;
+        st_.slot[l] = slots++;
+        st_.off[l] = top;
+        top += align((int64_t)m * cap);
+        st_.yoff[l] = top;
+        top += align((int64_t)n * cap);
+        leaf_buf_[l] = new_buf(rc.leaf_first, rc.leaf_last - rc.leaf_first, 0, 0);
+        leaf_ybuf_[l] = new_buf(cc.leaf_first, cc.leaf_last - cc.leaf_first, 0, 0);
+      }
+    }
+    for (int32_t l : nz_adm) {
+      const BlockNode& b = S_.blocks[S_.leaves[l]];
+      HLU_REQUIRE(b.kind == kLowRank, HLU_ERR_INVALID_ARG, "planner: init block is not admissible");
+      const ClusterNode& rc = S_.clusters[b.row];
+      const ClusterNode& cc = S_.clusters[b.col];
+      InitBlock ib{l, top};
+      top += align((int64_t)rc.size() * cc.size());
+      inits->push_back(ib);
+      init_buf_.push_back(new_buf(rc.leaf_first, rc.leaf_last - rc.leaf_first, cc.leaf_first,
+                                  cc.leaf_last - cc.leaf_first));
+    }
+    st_.data_elems = top;
+    st_.num_slots = slots;
+    persistent_bufs_ = (int32_t)bufs_.size();
+    persistent_segs_ = nseg_;
+  }
+
+  HB block(int32_t node) const {
+    const BlockNode& b = S_.blocks[node];
+    const ClusterNode& rc = S_.clusters[b.row];
+    const ClusterNode& cc = S_.clusters[b.col];
+    HB h;
+    h.kind = b.kind;
+    h.node = node;
+    h.r0 = rc.begin;
+    h.r1 = rc.end;
+    h.c0 = cc.begin;
+    h.c1 = cc.end;
+    const int32_t m = rc.size(), n = cc.size();
+    if (b.kind == kDense) {
+      const int32_t l = b.leaf_id;
+      h.D = View{st_.off[l], 1, m, m, n, m, n, rc.begin, cc.begin, leaf_buf_[l], false};
+    } else if (b.kind == kLowRank) {
+      const int32_t l = b.leaf_id;
+      h.slot = st_.slot[l];
+      h.cap = st_.cap[l];
+      h.X = View{st_.off[l], 1, m, m, dyn(h.slot), m, h.cap, rc.begin, -1, leaf_buf_[l], false};
+      h.Y = View{st_.yoff[l], 1, n, n, dyn(h.slot), n, h.cap, cc.begin, -1, leaf_ybuf_[l], false};
+    }
+    return h;
+  }
+
+  HB son(const HB& h, int i, int j) const { return block(S_.blocks[h.node].son[2 * i + j]); }
+
+  View identity(int32_t n) const {
+    return View{st_.identity_off, 1, st_.identity_n, n, n, n, n, -1, -1, -1, false};
+  }
+
+  // --------------------------------------------------------- plan control
+  void begin_plan(Plan* P, int64_t temp_base) {
+    P_ = P;
+    bufs_.resize(persistent_bufs_);
+    nseg_ = persistent_segs_;
+    last_w_.assign(nseg_, -1);
+    last_r_.assign(nseg_, -1);
+    temp_base_ = temp_base;
+    temp_top_ = temp_base;
+    temps_.clear();
+    temp_of_buf_.clear();
+    max_peak_ = 0;
+    ops_.clear();
+    max_wave_ = -1;
+  }
+
+  // Sort the emitted tasks into waves and fill the plan arrays.
+  void end_plan() {
+    Plan& P = *P_;
+    temp_peak_ = assign_temps();
+    remap_plan(P);
+    // bucket the tasks by (wave, kind), keeping program order inside a bucket
+    const int32_t nw = max_wave_ + 1;
+    std::vector<int64_t> start((size_t)nw * kNumKinds + 1, 0);
+    for (const Rec& r : ops_) start[(size_t)r.wave * kNumKinds + r.kind + 1]++;
+    for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+    std::vector<int32_t> sorted(ops_.size());
+    {
+      std::vector<int64_t> fillp(start.begin(), start.end() - 1);
+      for (size_t i = 0; i < ops_.size(); ++i) {
+        const Rec& r = ops_[i];
+        sorted[fillp[(size_t)r.wave * kNumKinds + r.kind]++] = (int32_t)i;
+      }
+    }
+    std::vector<GetrfOp> getrf;
+    std::vector<TriOp> tri;
+    std::vector<GemmOp> gemm;
+    std::vector<TruncOp> trunc;
+    std::vector<FillOp> fill;
+    getrf.reserve(P.getrf.size());
+    tri.reserve(P.tri.size());
+    gemm.reserve(P.gemm.size());
+    trunc.reserve(P.trunc.size());
+    fill.reserve(P.fill.size());
+    P.waves.assign(nw, Wave{});
+    for (int32_t w = 0; w < nw; ++w) {
+      Wave& W = P.waves[w];
+      W.gemm_tiles = 0;
+      for (int k = 0; k < kNumKinds; ++k) {
+        const int64_t b0 = start[(size_t)w * kNumKinds + k], b1 = start[(size_t)w * kNumKinds + k + 1];
+        switch (k) {
+          case kGetrf: W.begin[k] = (int32_t)getrf.size(); break;
+          case kTri: W.begin[k] = (int32_t)tri.size(); break;
+          case kGemm: W.begin[k] = (int32_t)gemm.size(); break;
+          case kTrunc: W.begin[k] = (int32_t)trunc.size(); break;
+          default: W.begin[k] = (int32_t)fill.size(); break;
+        }
+        W.count[k] = (int32_t)(b1 - b0);
+        for (int64_t q = b0; q < b1; ++q) {
+          const Rec& r = ops_[sorted[q]];
+          switch (k) {
+            case kGetrf: getrf.push_back(P.getrf[r.idx]); break;
+            case kTri: tri.push_back(P.tri[r.idx]); break;
+            case kGemm: {
+              const GemmOp& g = P.gemm[r.idx];
+              const int32_t gi = (int32_t)gemm.size();
+              gemm.push_back(g);
+              const int32_t rs = cap_of(g.C.rows, r.rows_s), cs = cap_of(g.C.cols, r.cols_s);
+              const int32_t ti = (rs + kTile - 1) / kTile, tj = (cs + kTile - 1) / kTile;
+              for (int32_t a = 0; a < ti; ++a)
+                for (int32_t b = 0; b < tj; ++b) {
+                  P.gemm_tile_op.push_back(gi);
+                  P.gemm_tile_ij.push_back((a << 16) | b);
+                }
+              W.gemm_tiles += ti * tj;
+              break;
+            }
+            case kTrunc: trunc.push_back(P.trunc[r.idx]); break;
+            default: fill.push_back(P.fill[r.idx]); break;
+          }
+        }
+      }
+    }
+    P.getrf.swap(getrf);
+    P.tri.swap(tri);
+    P.gemm.swap(gemm);
+    P.trunc.swap(trunc);
+    P.fill.swap(fill);
+    P.num_tasks = (int64_t)ops_.size();
+  }
+
+  int64_t temp_used() const { return temp_peak_; }
+
+  // ----------------------------------------------------- the factorisation
+  // Algorithm 1, step I for admissible blocks holding matrix entries: the
+  // staged dense block S becomes S I^T (or I S^T^T), truncated.
+  void init_lowrank(const std::vector<InitBlock>& inits) {
+    for (size_t i = 0; i < inits.size(); ++i) {
+      const BlockNode& b = S_.blocks[S_.leaves[inits[i].leaf]];
+      HB C = block(S_.leaves[inits[i].leaf]);
+      const int32_t m = C.r1 - C.r0, n = C.c1 - C.c0;
+      View Sv{inits[i].off, 1, m, m, n, m, n, C.r0, C.c0, init_buf_[i], false};
+      (void)b;
+      if (n <= m) trunc_op(C, {{Sv, identity(n), 0, 0, 1.0}});
+      else trunc_op(C, {{identity(m), transpose(Sv), 0, 0, 1.0}});
+    }
+  }
+
+  void hlu(const HB& D) {
+    if (D.kind == kDense) {
+      GetrfOp g{D.D.off, D.D.rows, D.D.cs, S_.blocks[D.node].leaf_id, 0};
+      emit(kGetrf, (int32_t)P_->getrf.size(), {{D.D, true}}, 0, 0);
+      P_->getrf.push_back(g);
+      return;
+    }
+    HB D00 = son(D, 0, 0), D01 = son(D, 0, 1), D10 = son(D, 1, 0), D11 = son(D, 1, 1);
+    hlu(D00);
+    trsm_lower(D00, D01);
+    trsm_upper(D00, D10);
+    gemm(D11, D10, D01);
+    hlu(D11);
+  }
+
+  void trsm_lower(const HB& Ld, const HB& B) {
+    if (B.kind == kLowRank) {
+      hsolve_lower(Ld, B.X);
+    } else if (B.kind == kDense) {
+      hsolve_lower(Ld, B.D);
+    } else {
+      HB L00 = son(Ld, 0, 0), L10 = son(Ld, 1, 0), L11 = son(Ld, 1, 1);
+      for (int j = 0; j < 2; ++j) {
+        HB B0 = son(B, 0, j), B1 = son(B, 1, j);
+        trsm_lower(L00, B0);
+        gemm(B1, L10, B0);
+        trsm_lower(L11, B1);
+      }
+    }
+  }
+
+  void trsm_upper(const HB& Ud, const HB& B) {
+    if (B.kind == kLowRank) {
+      hsolve_upper_T(Ud, B.Y);
+    } else if (B.kind == kDense) {
+      hsolve_upper_T(Ud, transpose(B.D));
+    } else {
+      HB U00 = son(Ud, 0, 0), U01 = son(Ud, 0, 1), U11 = son(Ud, 1, 1);
+      for (int i = 0; i < 2; ++i) {
+        HB B0 = son(B, i, 0), B1 = son(B, i, 1);
+        trsm_upper(U00, B0);
+        gemm(B1, B0, U01);
+        trsm_upper(U11, B1);
+      }
+    }
+  }
+
+  // V := L^{-1} V in place (V's rows = the diagonal block's rows)
+  void hsolve_lower(const HB& Ld, const View& V) {
+    if (Ld.kind == kDense) {
+      tri_op(kSolveUnitLower, Ld, V, V);
+      return;
+    }
+    HB L00 = son(Ld, 0, 0), L10 = son(Ld, 1, 0), L11 = son(Ld, 1, 1);
+    View V0 = sub_rows(V, L00.r0, L00.r1), V1 = sub_rows(V, L11.r0, L11.r1);
+    hsolve_lower(L00, V0);
+    hmv(L10, false, V0, V1, -1.0, 1.0);
+    hsolve_lower(L11, V1);
+  }
+
+  // V := U^{-T} V in place
+  void hsolve_upper_T(const HB& Ud, const View& V) {
+    if (Ud.kind == kDense) {
+      tri_op(kSolveUpperT, Ud, V, V);
+      return;
+    }
+    HB U00 = son(Ud, 0, 0), U01 = son(Ud, 0, 1), U11 = son(Ud, 1, 1);
+    View V0 = sub_rows(V, U00.r0, U00.r1), V1 = sub_rows(V, U11.r0, U11.r1);
+    hsolve_upper_T(U00, V0);
+    hmv(U01, true, V0, V1, -1.0, 1.0);
+    hsolve_upper_T(U11, V1);
+  }
+
+  // V := U^{-1} V in place
+  void hsolve_upper(const HB& Ud, const View& V) {
+    if (Ud.kind == kDense) {
+      tri_op(kSolveUpper, Ud, V, V);
+      return;
+    }
+    HB U00 = son(Ud, 0, 0), U01 = son(Ud, 0, 1), U11 = son(Ud, 1, 1);
+    View V0 = sub_rows(V, U00.r0, U00.r1), V1 = sub_rows(V, U11.r0, U11.r1);
+    hsolve_upper(U11, V1);
+    hmv(U01, false, V1, V0, -1.0, 1.0);
+    hsolve_upper(U00, V0);
+  }
+
+  // W := U V (upper triangle of the diagonal block, diagonal included)
+  void apply_upper(const HB& Ud, const View& V, const View& W) {
+    if (Ud.kind == kDense) {
+      tri_op(kMulUpper, Ud, V, W);
+      return;
+    }
+    HB U00 = son(Ud, 0, 0), U01 = son(Ud, 0, 1), U11 = son(Ud, 1, 1);
+    apply_upper(U00, sub_rows(V, U00.r0, U00.r1), sub_rows(W, U00.r0, U00.r1));
+    hmv(U01, false, sub_rows(V, U11.r0, U11.r1), sub_rows(W, U00.r0, U00.r1), 1.0, 1.0);
+    apply_upper(U11, sub_rows(V, U11.r0, U11.r1), sub_rows(W, U11.r0, U11.r1));
+  }
+
+  // W := L V (unit lower triangle of the diagonal block)
+  void apply_lower(const HB& Ld, const View& V, const View& W) {
+    if (Ld.kind == kDense) {
+      tri_op(kMulUnitLower, Ld, V, W);
+      return;
+    }
+    HB L00 = son(Ld, 0, 0), L10 = son(Ld, 1, 0), L11 = son(Ld, 1, 1);
+    apply_lower(L00, sub_rows(V, L00.r0, L00.r1), sub_rows(W, L00.r0, L00.r1));
+    apply_lower(L11, sub_rows(V, L11.r0, L11.r1), sub_rows(W, L11.r0, L11.r1));
+    hmv(L10, false, sub_rows(V, L00.r0, L00.r1), sub_rows(W, L11.r0, L11.r1), 1.0, 1.0);
+  }
+
+  // C -= A B in H-arithmetic.
+  void gemm(const HB& C, const HB& A, const HB& B) {
+    if (A.kind == kLowRank) {
+      View W = temp_spatial(C.c0, C.c1 - C.c0, A.X.cols, A.cap);
+      hmv(B, true, A.Y, W, 1.0, 0.0);
+      add_lowrank(C, A.X, W, -1.0);
+    } else if (B.kind == kLowRank) {
+      View W = temp_spatial(C.r0, C.r1 - C.r0, B.X.cols, B.cap);
+      hmv(A, false, B.X, W, 1.0, 0.0);
+      add_lowrank(C, W, B.Y, -1.0);
+    } else if (A.kind == kDense && B.kind == kDense) {
+      if (C.kind == kDense) {
+        gemm_op(C.D, 1.0, {{A.D, B.D, -1.0}});
+      } else {
+        add_lowrank(C, A.D, transpose(B.D), -1.0);
+      }
+    } else if (A.kind == kDense) {  // B subdivided: rows of C form a leaf cluster
+      if (C.kind == kDense) {
+        hmv(B, true, transpose(A.D), transpose(C.D), -1.0, 1.0);
+      } else {
+        View W = temp_spatial(C.c0, C.c1 - C.c0, A.D.rows, A.D.rows_s);
+        hmv(B, true, transpose(A.D), W, 1.0, 0.0);
+        add_lowrank(C, identity(A.D.rows), W, -1.0);
+      }
+    } else if (B.kind == kDense) {  // A subdivided: cols of C form a leaf cluster
+      if (C.kind == kDense) {
+        hmv(A, false, B.D, C.D, -1.0, 1.0);
+      } else {
+        View W = temp_spatial(C.r0, C.r1 - C.r0, B.D.cols, B.D.cols_s);
+        hmv(A, false, B.D, W, 1.0, 0.0);
+        add_lowrank(C, W, identity(B.D.cols), -1.0);
+      }
+    } else if (C.kind == kSub) {
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int k = 0; k < 2; ++k) gemm(son(C, i, j), son(A, i, k), son(B, k, j));
+    } else if (C.kind == kLowRank) {
+      // both factors subdivided, low-rank target: accumulate the product on
+      // the four quadrants as temporary low-rank blocks, then add them to C
+      // with one truncation.
+      std::vector<PartSpec> parts;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          HB Ai0 = son(A, i, 0), B0j = son(B, 0, j);
+          HB Q = temp_lowrank(Ai0.r0, Ai0.r1, B0j.c0, B0j.c1);
+          for (int k = 0; k < 2; ++k) gemm(Q, son(A, i, k), son(B, k, j));
+          parts.push_back({Q.X, Q.Y, Q.r0 - C.r0, Q.c0 - C.c0, 1.0});
+        }
+      trunc_op(C, parts);
+    } else {
+      fail(HLU_ERR_INVALID_ARG, "planner: dense target with two subdivided factors");
+    }
+  }
+
+  // C += alpha X Y^T, truncating in every low-rank leaf of C.
+  void add_lowrank(const HB& C, const View& X, const View& Y, double alpha) {
+    if (C.kind == kDense) {
+      gemm_op(C.D, 1.0, {{X, transpose(Y), alpha}});
+    } else if (C.kind == kLowRank) {
+      trunc_op(C, {{X, Y, 0, 0, alpha}});
+    } else {
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          HB s = son(C, i, j);
+          add_lowrank(s, rows_of(X, C.r0, s.r0, s.r1), rows_of(Y, C.c0, s.c0, s.c1), alpha);
+        }
+    }
+  }
+
+  // W = beta W + alpha op(B) V, op(B) = B or B^T, for an H-block B.
+  void hmv(const HB& B, bool trans, const View& V, const View& W, double alpha, double beta) {
+    std::vector<HB> lv;
+    collect_leaves(B, &lv);
+    const int32_t out0 = trans ? B.c0 : B.r0, out1 = trans ? B.c1 : B.r1;
+    const int32_t in0 = trans ? B.r0 : B.c0;
+    const int32_t lf0 = leaf_of_pos_[out0], lf1 = leaf_of_pos_[out1 - 1] + 1;
+    std::vector<std::vector<TermSpec>> seg_terms(lf1 - lf0);
+    // V rows are indexed by in-positions; W rows by out-positions
+    auto Vin = [&](int32_t a0, int32_t a1) { return rows_of(V, in0, a0, a1); };
+    for (const HB& l : lv) {
+      const int32_t lo0 = trans ? l.c0 : l.r0, lo1 = trans ? l.c1 : l.r1;
+      const int32_t li0 = trans ? l.r0 : l.c0, li1 = trans ? l.r1 : l.c1;
+      if (l.kind == kDense) {
+        View A = trans ? transpose(l.D) : l.D;   // rows = out positions
+        View Vl = Vin(li0, li1);
+        for (int32_t f = leaf_of_pos_[lo0]; f <= leaf_of_pos_[lo1 - 1]; ++f) {
+          const ClusterNode& c = S_.clusters[S_.leaf_clusters[f]];
+          seg_terms[f - lf0].push_back({sub_rows(A, c.begin, c.end), Vl, alpha});
+        }
+      } else {
+        // phase 1: T = (trans ? X : Y)^T V_l   (rank x p)
+        View F = trans ? l.X : l.Y;   // rows = in positions
+        View G = trans ? l.Y : l.X;   // rows = out positions
+        View T = temp_plain(F.cols, l.cap, V.cols, V.cols_s);
+        gemm_op(T, 0.0, {{transpose(F), Vin(li0, li1), 1.0}});
+        for (int32_t f = leaf_of_pos_[lo0]; f <= leaf_of_pos_[lo1 - 1]; ++f) {
+          const ClusterNode& c = S_.clusters[S_.leaf_clusters[f]];
+          seg_terms[f - lf0].push_back({sub_rows(G, c.begin, c.end), T, alpha});
+        }
+      }
+    }
+    // phase 2: one task per output segment
+    for (int32_t f = lf0; f < lf1; ++f) {
+      const ClusterNode& c = S_.clusters[S_.leaf_clusters[f]];
+      gemm_op(rows_of(W, out0, c.begin, c.end), beta, seg_terms[f - lf0]);
+    }
+  }
+
+ private:
+  struct TermSpec {
+    View A, B;
+    double alpha;
+  };
+  struct PartSpec {
+    View X, Y;
+    int32_t row_off, col_off;
+    double alpha;
+  };
+  struct Rec {
+    int32_t kind, idx, wave;
+    int32_t rows_s, cols_s;
+  };
+
+  static int64_t align(int64_t e) { return (e + 31) & ~int64_t(31); }
+
+  static int32_t cap_of(int32_t code, int32_t s) { return code >= 0 ? code : s; }
+
+  // restriction of a view whose row 0 sits at absolute position base
+  View rows_of(const View& v, int32_t base, int32_t a0, int32_t a1) const {
+    if (v.r0 >= 0) return sub_rows(v, a0, a1);
+    // a non-spatial view (identity): plain row offset
+    View w = v;
+    w.off += (int64_t)(a0 - base) * v.rs;
+    w.rows = w.rows_s = a1 - a0;
+    return w;
+  }
+
+  void collect_leaves(const HB& B, std::vector<HB>* out) const {
+    if (B.kind != kSub) {
+      out->push_back(B);
+      return;
+    }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) collect_leaves(son(B, i, j), out);
+  }
+
+  int32_t new_buf(int32_t rl0, int32_t nrl, int32_t cl0, int32_t ncl) {
+    Buf b{rl0, nrl, cl0, ncl, nseg_};
+    nseg_ += (int64_t)std::max(nrl, 1) * std::max(ncl, 1);
+    bufs_.push_back(b);
+    return (int32_t)bufs_.size() - 1;
+  }
+
+  // temporary with spatial rows [pos0, pos0 + m) and `cols` columns
+  View temp_spatial(int32_t pos0, int32_t m, int32_t cols, int32_t cols_s) {
+    const int32_t lf0 = leaf_of_pos_[pos0], lf1 = leaf_of_pos_[pos0 + m - 1] + 1;
+    int32_t b = new_buf(lf0, lf1 - lf0, 0, 0);
+    grow_segments();
+    View v{temp_top_, 1, m, m, cols, m, cols_s, pos0, -1, b, false};
+    add_temp(b, align((int64_t)m * std::max(cols_s, 1)));
+    return v;
+  }
+
+  View temp_plain(int32_t rows, int32_t rows_s, int32_t cols, int32_t cols_s) {
+    int32_t b = new_buf(0, 0, 0, 0);
+    grow_segments();
+    const int32_t ld = std::max(rows_s, 1);
+    View v{temp_top_, 1, ld, rows, cols, rows_s, cols_s, -1, -1, b, false};
+    add_temp(b, align((int64_t)ld * std::max(cols_s, 1)));
+    return v;
+  }
+
+  struct Temp {
+    int64_t vbegin, size;
+    int32_t first = INT32_MAX, last = -1;
+    int64_t phys = -1;
+  };
+
+  void add_temp(int32_t buf, int64_t size) {
+    if ((int32_t)temp_of_buf_.size() <= buf) temp_of_buf_.resize(buf + 1, -1);
+    temp_of_buf_[buf] = (int32_t)temps_.size();
+    temps_.push_back(Temp{temp_top_, size});
+    temp_top_ += size;
+  }
+
+  // Give every temporary physical memory, reusing space of temporaries whose
+  // last task ran in an earlier wave (best fit, coalescing free ranges);
+  // returns the peak size.
+  int64_t assign_temps() {
+    std::vector<int32_t> order;
+    order.reserve(temps_.size());
+    for (size_t i = 0; i < temps_.size(); ++i) {
+      if (temps_[i].last < 0) temps_[i].phys = 0;   // never touched
+      else order.push_back((int32_t)i);
+    }
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return temps_[a].first != temps_[b].first ? temps_[a].first < temps_[b].first : a < b;
+    });
+    std::map<int64_t, int64_t> by_off;                 // free ranges: offset -> size
+    std::multimap<int64_t, int64_t> by_size;           // size -> offset
+    auto erase_size = [&](int64_t off, int64_t size) {
+      auto r = by_size.equal_range(size);
+      for (auto it = r.first; it != r.second; ++it)
+        if (it->second == off) {
+          by_size.erase(it);
+          return;
+        }
+    };
+    int64_t peak = 0;
+    auto release = [&](int64_t off, int64_t size) {
+      auto next = by_off.lower_bound(off);
+      if (next != by_off.end() && next->first == off + size) {
+        size += next->second;
+        erase_size(next->first, next->second);
+        next = by_off.erase(next);
+      }
+      if (next != by_off.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+          erase_size(prev->first, prev->second);
+          off = prev->first;
+          size += prev->second;
+          by_off.erase(prev);
+        }
+      }
+      if (off + size == peak) {   // give it back to the top
+        peak = off;
+        return;
+      }
+      by_off[off] = size;
+      by_size.insert({size, off});
+    };
+    using Ev = std::pair<int32_t, int32_t>;   // (last wave, temp)
+    std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> live;
+    for (int32_t t : order) {
+      Temp& T = temps_[t];
+      while (!live.empty() && live.top().first < T.first) {
+        const Temp& L = temps_[live.top().second];
+        release(L.phys, L.size);
+        live.pop();
+      }
+      auto it = by_size.lower_bound(T.size);
+      if (it != by_size.end()) {
+        const int64_t off = it->second, size = it->first;
+        by_size.erase(it);
+        by_off.erase(off);
+        T.phys = off;
+        if (size > T.size) {
+          by_off[off + T.size] = size - T.size;
+          by_size.insert({size - T.size, off + T.size});
+        }
+      } else {
+        T.phys = peak;
+        peak += T.size;
+      }
+      max_peak_ = std::max(max_peak_, peak);
+      live.push({T.last, t});
+    }
+    return max_peak_;
+  }
+
+  int64_t remap(int64_t off) const {
+    if (off < temp_base_ || off >= temp_top_ || temps_.empty()) return off;
+    size_t lo = 0, hi = temps_.size();
+    while (hi - lo > 1) {
+      size_t mid = (lo + hi) / 2;
+      if (temps_[mid].vbegin <= off) lo = mid;
+      else hi = mid;
+    }
+    return temp_base_ + temps_[lo].phys + (off - temps_[lo].vbegin);
+  }
+
+  void remap_plan(Plan& P) const {
+    auto R = [&](MatRef& m) { m.off = remap(m.off); };
+    for (auto& g : P.gemm) R(g.C);
+    for (auto& t : P.terms) {
+      R(t.A);
+      R(t.B);
+    }
+    for (auto& t : P.tri) {
+      R(t.V);
+      R(t.W);
+    }
+    for (auto& t : P.trunc) {
+      t.xoff = remap(t.xoff);
+      t.yoff = remap(t.yoff);
+    }
+    for (auto& p : P.parts) {
+      R(p.X);
+      R(p.Y);
+    }
+    for (auto& f : P.fill) R(f.M);
+  }
+
+  HB temp_lowrank(int32_t r0, int32_t r1, int32_t c0, int32_t c1) {
+    HB h;
+    h.kind = kLowRank;
+    h.node = -1;
+    h.r0 = r0;
+    h.r1 = r1;
+    h.c0 = c0;
+    h.c1 = c1;
+    const int32_t m = r1 - r0, n = c1 - c0;
+    h.cap = std::max(1, std::min(std::min(m, n), kcap_));
+    h.slot = st_.num_slots++;
+    View X = temp_spatial(r0, m, dyn(h.slot), h.cap);
+    View Y = temp_spatial(c0, n, dyn(h.slot), h.cap);
+    h.X = X;
+    h.Y = Y;
+    return h;
+  }
+
+  void grow_segments() {
+    if ((int64_t)last_w_.size() < nseg_) {
+      last_w_.resize(nseg_, -1);
+      last_r_.resize(nseg_, -1);
+    }
+  }
+
+  template <class F>
+  void for_segments(const View& v, F f) const {
+    if (v.buf < 0) return;
+    const Buf& b = bufs_[v.buf];
+    // buffer orientation
+    const int32_t br0 = v.tr ? v.c0 : v.r0, brs = v.tr ? v.cols_s : v.rows_s;
+    const int32_t bc0 = v.tr ? v.r0 : v.c0, bcs = v.tr ? v.rows_s : v.cols_s;
+    int32_t rlo = 0, rhi = 1, clo = 0, chi = 1;
+    if (b.nrl > 0) {
+      if (br0 >= 0) {
+        rlo = leaf_of_pos_[br0] - b.rl0;
+        rhi = leaf_of_pos_[br0 + brs - 1] - b.rl0 + 1;
+      } else {
+        rhi = b.nrl;
+      }
+    }
+    if (b.ncl > 0) {
+      if (bc0 >= 0) {
+        clo = leaf_of_pos_[bc0] - b.cl0;
+        chi = leaf_of_pos_[bc0 + bcs - 1] - b.cl0 + 1;
+      } else {
+        chi = b.ncl;
+      }
+    }
+    const int32_t ncl = std::max(b.ncl, 1);
+    for (int32_t r = rlo; r < rhi; ++r)
+      for (int32_t c = clo; c < chi; ++c) f(b.seg0 + (int64_t)r * ncl + c);
+  }
+
+  void emit(int32_t kind, int32_t idx, std::initializer_list<Access> acc, int32_t rows_s, int32_t cols_s) {
+    std::vector<Access> v(acc);
+    emit_v(kind, idx, v, rows_s, cols_s);
+  }
+
+  void emit_v(int32_t kind, int32_t idx, const std::vector<Access>& acc, int32_t rows_s, int32_t cols_s) {
+    int32_t w = 0;
+    for (const Access& a : acc)
+      for_segments(a.v, [&](int64_t s) {
+        w = std::max(w, last_w_[s] + 1);
+        if (a.write) w = std::max(w, last_r_[s] + 1);
+      });
+    for (const Access& a : acc) {
+      for_segments(a.v, [&](int64_t s) {
+        if (a.write) last_w_[s] = w;
+        else last_r_[s] = std::max(last_r_[s], w);
+      });
+      if (a.v.buf >= 0 && a.v.buf < (int32_t)temp_of_buf_.size() && temp_of_buf_[a.v.buf] >= 0) {
+        Temp& T = temps_[temp_of_buf_[a.v.buf]];
+        T.first = std::min(T.first, w);
+        T.last = std::max(T.last, w);
+      }
+    }
+    ops_.push_back(Rec{kind, idx, w, rows_s, cols_s});
+    max_wave_ = std::max(max_wave_, w);
+  }
+
+  void tri_op(int32_t mode, const HB& Dg, const View& V, const View& W) {
+    TriOp t;
+    t.tri = Dg.D.off;
+    t.ld = Dg.D.cs;
+    t.m = Dg.D.rows;
+    t.mode = mode;
+    t.pad = 0;
+    t.V = V.ref();
+    t.W = W.ref();
+    std::vector<Access> acc;
+    acc.push_back({Dg.D, false});
+    if (mode == kMulUpper || mode == kMulUnitLower) {
+      acc.push_back({V, false});
+      acc.push_back({W, true});
+    } else {
+      acc.push_back({V, true});
+    }
+    emit_v(kTri, (int32_t)P_->tri.size(), acc, 0, 0);
+    P_->tri.push_back(t);
+  }
+
+  void gemm_op(const View& C, double beta, const std::vector<TermSpec>& terms) {
+    GemmOp g;
+    g.C = C.ref();
+    g.beta = beta;
+    g.t0 = (int32_t)P_->terms.size();
+    g.nt = (int32_t)terms.size();
+    std::vector<Access> acc;
+    acc.push_back({C, true});
+    for (const TermSpec& t : terms) {
+      P_->terms.push_back(GemmTerm{t.A.ref(), t.B.ref(), t.alpha});
+      acc.push_back({t.A, false});
+      acc.push_back({t.B, false});
+    }
+    emit_v(kGemm, (int32_t)P_->gemm.size(), acc, C.rows_s, C.cols_s);
+    P_->gemm.push_back(g);
+  }
+
+  void trunc_op(const HB& C, const std::vector<PartSpec>& parts) {
+    TruncOp t;
+    t.xoff = C.X.off;
+    t.yoff = C.Y.off;
+    t.m = C.r1 - C.r0;
+    t.n = C.c1 - C.c0;
+    t.ldx = C.X.cs;
+    t.ldy = C.Y.cs;
+    t.slot = C.slot;
+    t.cap = C.cap;
+    t.p0 = (int32_t)P_->parts.size();
+    t.np = (int32_t)parts.size();
+    std::vector<Access> acc;
+    acc.push_back({C.X, true});
+    acc.push_back({C.Y, true});
+    for (const PartSpec& p : parts) {
+      P_->parts.push_back(TruncPart{p.X.ref(), p.Y.ref(), p.row_off, p.col_off, p.alpha});
+      acc.push_back({p.X, false});
+      acc.push_back({p.Y, false});
+    }
+    emit_v(kTrunc, (int32_t)P_->trunc.size(), acc, 0, 0);
+    P_->trunc.push_back(t);
+  }
+
+ public:
+  int32_t kcap_ = 64;
+
+  View vector_view(int64_t off, int32_t max_rhs, int32_t nrhs_slot, int32_t buf) const {
+    return View{off, 1, S_.N, S_.N, dyn(nrhs_slot), S_.N, max_rhs, 0, -1, buf, false};
+  }
+  int32_t vector_buf() {
+    int32_t b = new_buf(0, (int32_t)S_.leaf_clusters.size(), 0, 0);
+    grow_segments();
+    return b;
+  }
+
+ private:
+  const Structure& S_;
+  StoragePlan& st_;
+  Plan* P_ = nullptr;
+  std::vector<int32_t> leaf_of_pos_;
+  std::vector<int32_t> leaf_buf_, leaf_ybuf_, init_buf_;
+  std::vector<Temp> temps_;
+  std::vector<int32_t> temp_of_buf_;
+  int64_t temp_peak_ = 0;
+  int64_t max_peak_ = 0;
+  std::vector<Buf> bufs_;
+  int32_t persistent_bufs_ = 0;
+  int64_t persistent_segs_ = 0;
+  int64_t nseg_ = 0;
+  std::vector<int32_t> last_w_, last_r_;
+  int64_t temp_base_ = 0, temp_top_ = 0;
+  std::vector<Rec> ops_;
+  int32_t max_wave_ = -1;
+};
+
+}  // namespace
+
+void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
+                 const std::vector<int32_t>& nonzero_admissible, PlanSet* out) {
+  HLU_REQUIRE(kcap >= 1 && max_rhs >= 1, HLU_ERR_INVALID_ARG, "build_plans: bad capacity");
+  PlanSet& ps = *out;
+  ps = PlanSet{};
+  ps.kcap = kcap;
+  StoragePlan& st = ps.store;
+  Planner pl(S, st);
+  pl.kcap_ = kcap;
+  pl.layout(kcap, nonzero_admissible, &ps.init_blocks);
+
+  // factorisation plan; temporaries follow the data
+  const int64_t temp_base = st.data_elems;
+  pl.begin_plan(&ps.factor, temp_base);
+  pl.init_lowrank(ps.init_blocks);
+  pl.hlu(pl.block(0));
+  pl.end_plan();
+  st.temp_elems = pl.temp_used();
+
+  // solve plans: vectors and their temporaries after the factor temporaries
+  st.max_rhs = max_rhs;
+  st.nrhs_slot = st.num_slots++;
+  int64_t top = temp_base + st.temp_elems;
+  st.vec_off = top;
+  top += ((int64_t)S.N * max_rhs + 31) & ~int64_t(31);
+  st.vec2_off = top;
+  top += ((int64_t)S.N * max_rhs + 31) & ~int64_t(31);
+  const int64_t solve_base = top;
+
+  pl.begin_plan(&ps.fwd_bwd, solve_base);
+  {
+    int32_t vb = pl.vector_buf();
+    auto V = pl.vector_view(st.vec_off, max_rhs, st.nrhs_slot, vb);
+    pl.hsolve_lower(pl.block(0), V);
+    pl.hsolve_upper(pl.block(0), V);
+  }
+  pl.end_plan();
+  int64_t solve_used = pl.temp_used();
+
+  pl.begin_plan(&ps.apply, solve_base);
+  {
+    int32_t vb = pl.vector_buf();
+    int32_t wb = pl.vector_buf();
+    auto V = pl.vector_view(st.vec_off, max_rhs, st.nrhs_slot, vb);
+    auto W = pl.vector_view(st.vec2_off, max_rhs, st.nrhs_slot, wb);
+    pl.apply_upper(pl.block(0), V, W);   // W = U V
+    pl.apply_lower(pl.block(0), W, V);   // V = L W
+  }
+  pl.end_plan();
+  solve_used = std::max(solve_used, pl.temp_used());
+  st.solve_temp_elems = solve_used;
+  st.total_elems = solve_base + solve_used;
+}
+
+}  // namespace hlu

@@ -1,0 +1,142 @@
+// Task plans for the H-LU factorisation, the H-triangular solves and the
+// product L U, built on the host from the block tree and executed on the GPU
+// as batched waves of independent tasks.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "structure.h"
+
+namespace hlu {
+
+// ------------------------------------------------------- device descriptors
+// A strided matrix in the arena: element (i, j) at arena[off + i*rs + j*cs].
+// rows/cols >= 0 are static extents; a negative value -(s+1) means the
+// extent is dims[s], a rank known only on the device.
+struct MatRef {
+  int64_t off;
+  int32_t rs, cs;
+  int32_t rows, cols;
+};
+
+struct GemmTerm {  // C += alpha * A (m x k) * B (k x n)
+  MatRef A, B;
+  double alpha;
+};
+struct GemmOp {    // C = beta * C + sum of terms
+  MatRef C;
+  double beta;
+  int32_t t0, nt;
+};
+
+enum TriMode : int32_t {
+  kSolveUnitLower = 0,  // V := L^{-1} V, L = unit lower triangle of T
+  kSolveUpperT = 1,     // V := U^{-T} V, U = upper triangle of T
+  kSolveUpper = 2,      // V := U^{-1} V
+  kMulUpper = 3,        // W := U V
+  kMulUnitLower = 4     // W := L V
+};
+struct TriOp {
+  int64_t tri;         // dense diagonal leaf (column-major, leading dim ld)
+  int32_t ld, m, mode, pad;
+  MatRef V, W;         // W used by the multiply modes only
+};
+
+struct GetrfOp {
+  int64_t off;
+  int32_t m, ld, leaf, pad;
+};
+
+struct TruncPart {   // adds alpha * Xp Yp^T, Xp placed at row_off, Yp at col_off
+  MatRef X, Y;
+  int32_t row_off, col_off;
+  double alpha;
+};
+struct TruncOp {     // low-rank C (X: m x cap, Y: n x cap, rank dims[slot])
+  int64_t xoff, yoff;
+  int32_t m, n, ldx, ldy, slot, cap, p0, np;
+};
+
+struct FillOp {
+  MatRef M;
+  double value;
+};
+
+enum OpKind : int32_t { kGetrf = 0, kTri = 1, kGemm = 2, kTrunc = 3, kFill = 4, kNumKinds = 5 };
+
+// One wave: for each kind, a range of ops in the kind's array.
+struct Wave {
+  int32_t begin[kNumKinds];
+  int32_t count[kNumKinds];
+  int32_t gemm_tiles;          // sum of tiles of the wave's GEMM ops
+};
+
+struct Plan {
+  std::vector<GetrfOp> getrf;
+  std::vector<TriOp> tri;
+  std::vector<GemmOp> gemm;
+  std::vector<GemmTerm> terms;
+  std::vector<TruncOp> trunc;
+  std::vector<TruncPart> parts;
+  std::vector<FillOp> fill;
+  std::vector<int32_t> gemm_tile_op;   // per tile: gemm op index
+  std::vector<int32_t> gemm_tile_ij;   // per tile: (tile_i << 16) | tile_j
+  std::vector<Wave> waves;
+  int64_t num_tasks = 0;
+};
+
+// Device copies of a plan's task arrays.
+struct DevPlan {
+  const GetrfOp* getrf;
+  const TriOp* tri;
+  const GemmOp* gemm;
+  const GemmTerm* terms;
+  const TruncOp* trunc;
+  const TruncPart* parts;
+  const FillOp* fill;
+  const int32_t* tile_op;
+  const int32_t* tile_ij;
+};
+
+// ------------------------------------------------------------ the planner
+struct StoragePlan {
+  // per block-tree leaf (indexed by leaf ordinal)
+  std::vector<int64_t> off;     // dense: block; low-rank: X
+  std::vector<int64_t> yoff;    // low-rank: Y
+  std::vector<int32_t> cap;     // low-rank capacity
+  std::vector<int32_t> slot;    // low-rank rank slot
+  int64_t identity_off = 0;     // kIdentity x kIdentity identity matrix
+  int32_t identity_n = 0;
+  int64_t data_elems = 0;       // dense + low-rank + identity
+  int64_t temp_elems = 0;       // factor temporaries
+  int64_t solve_temp_elems = 0; // temporaries of the solve/apply plans (per rhs capacity)
+  int32_t num_slots = 0;        // ranks of leaves and temporaries
+  int32_t nrhs_slot = 0;        // dims slot holding the solve's column count
+  int64_t vec_off = 0;          // solve vector block (N x max_rhs) in cluster order
+  int64_t vec2_off = 0;         // second vector block (apply L U)
+  int32_t max_rhs = 0;
+  int64_t total_elems = 0;
+};
+
+// Admissible leaves that hold entries of the sparse matrix (only possible
+// for small leaf clusters) start from a dense staging block that the first
+// task of the factor plan truncates into low-rank form.
+struct InitBlock {
+  int32_t leaf;       // block-tree leaf ordinal
+  int64_t off;        // staging block (m x n, column-major) in the arena
+};
+
+struct PlanSet {
+  StoragePlan store;
+  std::vector<InitBlock> init_blocks;
+  Plan factor, fwd_bwd, apply;
+  int32_t kcap = 64;
+};
+
+// Builds storage and the three plans.  kcap: rank capacity per block
+// (capped at min(m, n)); max_rhs: column capacity of the solve plans;
+// nonzero_admissible: leaf ordinals of admissible blocks holding entries.
+void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
+                 const std::vector<int32_t>& nonzero_admissible, PlanSet* out);
+
+}  // namespace hlu

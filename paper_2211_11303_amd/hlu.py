@@ -1,0 +1,221 @@
+"""Python binding of libhlu with the names of the C ABI (include/hlu.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  torch provides device memory and the stream.  Blocks of
+vectors are torch tensors of shape (nrhs, N) (contiguous), i.e. the
+column-major N x nrhs layout of the C ABI with leading dimension N.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+PREC = {"fp64": L.HLU_FP64, "fp32": L.HLU_FP32}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dev_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _as_block(t, N):
+    """(N,) or (nrhs, N) float64 CUDA tensor -> (2-D view, nrhs)."""
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 CUDA tensor")
+    t2 = t.reshape(1, -1) if t.dim() == 1 else t
+    if t2.shape[-1] != N or not t2.is_contiguous():
+        raise ValueError(f"expected a contiguous (nrhs, {N}) tensor")
+    return t2, t2.shape[0]
+
+
+# ------------------------------------------------------------------ problem
+def hlu_kuhn_sizes(n):
+    N = ctypes.c_int32()
+    nnz = ctypes.c_int64()
+    L.check(L.lib().hlu_kuhn_sizes(n, ctypes.byref(N), ctypes.byref(nnz)))
+    return N.value, nnz.value
+
+
+def hlu_kuhn_assemble(n, kappa):
+    """A = K - kappa^2 M on the Kuhn cube with n^3 cubes: (row_ptr, col, val,
+    mid2) as numpy arrays (host)."""
+    N, nnz = hlu_kuhn_sizes(n)
+    rp = np.empty(N + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    va = np.empty(nnz, np.float64)
+    mid = np.empty((N, 3), np.int32)
+    L.check(L.lib().hlu_kuhn_assemble(n, float(kappa), _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32),
+                                      _ptr(va, ctypes.c_double), _ptr(mid, ctypes.c_int32)))
+    return rp, ci, va, mid
+
+
+# ------------------------------------------------------------ sparse matrix
+class SpMat:
+    """Device CSR of A (hlu_spmat)."""
+
+    def __init__(self, row_ptr, col, val, device="cuda"):
+        torch = _torch()
+        self.n = len(row_ptr) - 1
+        self.nnz = len(col)
+        self.rp = torch.as_tensor(np.ascontiguousarray(row_ptr, np.int32)).to(device)
+        self.ci = torch.as_tensor(np.ascontiguousarray(col, np.int32)).to(device)
+        self.val = torch.as_tensor(np.ascontiguousarray(val, np.float64)).to(device)
+        h = ctypes.c_void_p()
+        L.check(L.lib().hlu_spmat_create(self.n, self.nnz, _dev_ptr(self.rp), _dev_ptr(self.ci),
+                                         _dev_ptr(self.val), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            L.lib().hlu_spmat_destroy(self.handle)
+            self.handle = None
+
+    def hlu_spmv(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
+        torch = _torch()
+        x2, nrhs = _as_block(x, self.n)
+        if y is None:
+            y = torch.zeros_like(x)
+        y2, _ = _as_block(y, self.n)
+        L.check(L.lib().hlu_spmv(self.handle, _dev_ptr(x2), _dev_ptr(y2), nrhs, self.n, float(alpha),
+                                 float(beta), _stream(stream)))
+        return y
+
+
+# ------------------------------------------------------------- H-LU handle
+class HLU:
+    """hlu_build + workspace + hlu_factor / hlu_solve / hlu_apply_lu."""
+
+    def __init__(self, row_ptr, col, val, mid2, eta=2.0, leaf=64):
+        self._rp = np.ascontiguousarray(row_ptr, np.int32)
+        self._ci = np.ascontiguousarray(col, np.int32)
+        self._va = np.ascontiguousarray(val, np.float64)
+        mid = np.ascontiguousarray(mid2, np.int32)
+        csr = L.HluCsr(len(self._rp) - 1, len(self._ci), _ptr(self._rp, ctypes.c_int32),
+                       _ptr(self._ci, ctypes.c_int32), _ptr(self._va, ctypes.c_double))
+        h = ctypes.c_void_p()
+        L.check(L.lib().hlu_build(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), float(eta), int(leaf),
+                                  ctypes.byref(h)))
+        self.handle = h
+        self.n = len(self._rp) - 1
+        self.leaf = leaf
+        self.eta = eta
+        self.work = None
+        self.prec = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            L.lib().hlu_destroy(self.handle)
+            self.handle = None
+
+    @staticmethod
+    def _opts(eps, max_rank, prec):
+        return L.FactorOpts(float(eps), int(max_rank), PREC[prec])
+
+    def hlu_workspace_bytes(self, eps, max_rank=0, prec="fp64"):
+        o = self._opts(eps, max_rank, prec)
+        b = ctypes.c_size_t()
+        L.check(L.lib().hlu_workspace_bytes(self.handle, ctypes.byref(o), ctypes.byref(b)))
+        return b.value
+
+    def hlu_bind_workspace(self, nbytes):
+        torch = _torch()
+        if self.work is None or self.work.numel() < nbytes:
+            self.work = None
+            self.work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        L.check(L.lib().hlu_bind_workspace(self.handle, _dev_ptr(self.work), self.work.numel()))
+
+    def hlu_factor(self, eps, max_rank=0, prec="fp64", stream=None, allow_overflow=False):
+        nbytes = self.hlu_workspace_bytes(eps, max_rank, prec)
+        self.hlu_bind_workspace(nbytes)
+        o = self._opts(eps, max_rank, prec)
+        st = L.lib().hlu_factor(self.handle, ctypes.byref(o), _stream(stream))
+        if st == -7 and allow_overflow:
+            st = L.HLU_OK
+        L.check(st)
+        self.prec = prec
+        return self
+
+    def hlu_solve(self, b, x=None, stream=None):
+        torch = _torch()
+        b2, nrhs = _as_block(b, self.n)
+        if x is None:
+            x = torch.empty_like(b)
+        x2, _ = _as_block(x, self.n)
+        L.check(L.lib().hlu_solve(self.handle, _dev_ptr(b2), _dev_ptr(x2), nrhs, self.n, _stream(stream)))
+        return x
+
+    def hlu_apply_lu(self, v, stream=None):
+        torch = _torch()
+        v2, nrhs = _as_block(v, self.n)
+        y = torch.empty_like(v)
+        y2, _ = _as_block(y, self.n)
+        L.check(L.lib().hlu_apply_lu(self.handle, _dev_ptr(v2), _dev_ptr(y2), nrhs, self.n, _stream(stream)))
+        return y
+
+    def hlu_get_stats(self):
+        s = L.Stats()
+        L.check(L.lib().hlu_get_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def hlu_get_ranks(self):
+        nb = self.structure_sizes()[2]
+        r = np.empty(nb, np.int32)
+        L.check(L.lib().hlu_get_ranks(self.handle, _ptr(r, ctypes.c_int32)))
+        return r
+
+    def structure_sizes(self):
+        N, C, B = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().hlu_structure_sizes(self.handle, ctypes.byref(N), ctypes.byref(C), ctypes.byref(B)))
+        return N.value, C.value, B.value
+
+    def hlu_export_structure(self):
+        N, C, B = self.structure_sizes()
+        out = {k: np.empty(N if k == "perm" else (C if k in ("begin", "end", "level", "son0", "son1") else B),
+                           np.int32)
+               for k in ("perm", "begin", "end", "level", "son0", "son1", "brow", "bcol", "bkind")}
+        L.check(L.lib().hlu_export_structure(self.handle, *[_ptr(out[k], ctypes.c_int32) for k in
+                                                            ("perm", "begin", "end", "level", "son0", "son1",
+                                                             "brow", "bcol", "bkind")]))
+        return out
+
+
+# -------------------------------------------------------------------- GMRES
+def gmres_workspace_bytes(n, nrhs, restart):
+    return L.lib().gmres_workspace_bytes(n, nrhs, restart)
+
+
+def gmres_solve(A, b, precond=None, restart=50, tol=1e-8, max_iters=1000, stream=None, work=None,
+                raise_on_fail=True):
+    """Returns (x, infos) with infos a list of dicts (iters, converged,
+    relres, abs_res) per right-hand side."""
+    torch = _torch()
+    b2, nrhs = _as_block(b, A.n)
+    x = torch.zeros_like(b2)
+    nbytes = gmres_workspace_bytes(A.n, nrhs, restart)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    o = L.GmresOpts(int(restart), int(max_iters), float(tol))
+    info = (L.GmresInfo * nrhs)()
+    st = L.lib().gmres_solve(A.handle, _dev_ptr(b2), _dev_ptr(x), nrhs, A.n,
+                             precond.handle if precond is not None else None, ctypes.byref(o), info,
+                             _dev_ptr(work), work.numel(), _stream(stream))
+    infos = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, abs_res=i.abs_res) for i in info]
+    if st != L.HLU_OK and (raise_on_fail or st != -5):
+        L.check(st)
+    return x.reshape(b.shape), infos

@@ -1,0 +1,110 @@
+"""Library checks that need no GPU: the shared library loads and exports
+every symbol of include/hlu.h; host-side assembly and the integer cluster /
+block structure are bit-exact against the oracle; argument errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.assemble import Discretisation
+from oracle.cluster import Structure
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2211_11303_amd", "libhlu.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhlu.so not built")
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "hlu.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hlu_[a-z_]+|gmres_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    syms = _header_symbols()
+    assert "hlu_factor" in syms and "gmres_solve" in syms and len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (2, 3.0), (4, 2.0), (8, 8.0)])
+def test_assembly_matches_oracle(n, kappa):
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, kappa)
+    d = Discretisation(n, kappa)
+    assert np.array_equal(rp, d.A.indptr) and np.array_equal(ci, d.A.indices)
+    assert np.abs(va - d.A.data).max() <= 1e-14 * np.abs(d.A.data).max()
+    assert np.array_equal(mid, d.mesh.midpoints2())
+    assert hlu.hlu_kuhn_sizes(n) == (7 * n ** 3 - 9 * n ** 2 + 3 * n, len(ci))
+
+
+@pytest.mark.parametrize("n,leaf", [(4, 32), (4, 8), (5, 20), (8, 64), (8, 17)])
+def test_structure_bit_exact(n, leaf):
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, 2.0)
+    h = hlu.HLU(rp, ci, va, mid, 2.0, leaf)
+    st = h.hlu_export_structure()
+    s = Structure(mid, leaf, 2.0)
+    assert np.array_equal(st["perm"], s.perm)
+    assert np.array_equal(st["begin"], [c.begin for c in s.clusters])
+    assert np.array_equal(st["end"], [c.end for c in s.clusters])
+    assert np.array_equal(st["level"], [c.level for c in s.clusters])
+    assert np.array_equal(st["son0"], [c.sons[0].id if c.sons else -1 for c in s.clusters])
+    assert np.array_equal(st["son1"], [c.sons[1].id if c.sons else -1 for c in s.clusters])
+    assert np.array_equal(st["brow"], [b.row.id for b in s.block_leaves])
+    assert np.array_equal(st["bcol"], [b.col.id for b in s.block_leaves])
+    assert np.array_equal(st["bkind"], [b.kind for b in s.block_leaves])
+    stats = h.hlu_get_stats()
+    sm = s.summary()
+    assert stats["num_admissible"] == sm["admissible"] and stats["num_dense"] == sm["dense"]
+    assert stats["dense_entries"] == sm["dense_entries"] and stats["depth"] == sm["depth"]
+
+
+@pytest.mark.slow
+def test_structure_bit_exact_16():
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(16, 4.0)
+    h = hlu.HLU(rp, ci, va, mid, 2.0, 64)
+    st = h.hlu_export_structure()
+    s = Structure(mid, 64, 2.0)
+    assert np.array_equal(st["perm"], s.perm)
+    assert np.array_equal(st["bkind"], [b.kind for b in s.block_leaves])
+    assert np.array_equal(st["brow"], [b.row.id for b in s.block_leaves])
+
+
+def test_argument_errors():
+    from paper_2211_11303_amd import _lib as L
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(2, 1.0)
+    bad = ci.copy()
+    bad[0] = len(rp) + 5                      # column out of range
+    with pytest.raises(L.HluError) as e:
+        hlu.HLU(rp, bad, va, mid, 2.0, 8)
+    assert e.value.status == -1
+    unsorted = ci.copy()
+    unsorted[[0, 1]] = unsorted[[1, 0]]
+    with pytest.raises(L.HluError):
+        hlu.HLU(rp, unsorted, va, mid, 2.0, 8)
+    with pytest.raises(L.HluError):
+        hlu.HLU(rp, ci, va, mid, 2.0, 0)     # leaf size 0
+    h = hlu.HLU(rp, ci, va, mid, 2.0, 8)
+    with pytest.raises(L.HluError):
+        h.hlu_workspace_bytes(-1.0)          # negative eps
+    with pytest.raises(L.HluError) as e:
+        L.check(L.lib().hlu_solve(h.handle, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, h.n, None))
+    assert e.value.status == -6              # not factored
+
+
+def test_plan_sizes_reported():
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(4, 2.0)
+    h = hlu.HLU(rp, ci, va, mid, 2.0, 32)
+    b64 = h.hlu_workspace_bytes(1e-6, prec="fp64")
+    b32 = h.hlu_workspace_bytes(1e-6, prec="fp32")
+    assert b32 < b64
+    st = h.hlu_get_stats()
+    assert st["factor_waves"] > 0 and st["factor_tasks"] > 0 and st["solve_waves"] > 0
