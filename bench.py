@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark: H-LU factor seconds and H-LU preconditioned GMRES solves/sec to
+a relative residual of 1e-8, FP32 H-LU vs FP64 H-LU, on one MI355X.
+
+Workload (default): the Kuhn-split unit cube with 32^3 cubes (N = 220,256
+interior-edge unknowns), A = K - kappa^2 M with kappa = 8, eta = 2, leaf 64,
+truncation eps = 1e-3, right-hand sides b = A x* with x* uniform in [-1, 1]
+(8 columns per seed, seeds 0..2), FP64 GMRES(50) to 1e-8.  Inputs are
+synthetic and seeded; everything is resident in HBM before timing.
+
+A step is one GMRES(50) solve of an 8-column right-hand-side batch with the
+cached FP32 H-LU preconditioner (SpMV, H-solves, orthogonalisation, true
+residual).  value = right-hand sides solved per second.  The FP32 and FP64
+factorisations are timed separately (HIP events) and reported beside it.
+
+Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=32)
+    p.add_argument("--kappa", type=float, default=8.0)
+    p.add_argument("--eps", type=float, default=1e-3)
+    p.add_argument("--leaf", type=int, default=64)
+    p.add_argument("--nrhs", type=int, default=8)
+    p.add_argument("--restart", type=int, default=50)
+    p.add_argument("--tol", type=float, default=1e-8)
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 H-LU comparison")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-level", type=int, default=5,
+                   help="cluster-tree level of the principal block the oracle sample factors")
+    return p.parse_args()
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def event_time(fn, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    out = fn()
+    e1.record(stream)
+    e1.synchronize()
+    return out, e0.elapsed_time(e1) / 1e3
+
+
+def cpu_baseline(n, kappa, leaf, eps, restart, tol, level):
+    """The oracle (FP64, plain Python/NumPy, one BLAS thread) on a bounded
+    sample of the same workload: the principal diagonal block of A on one
+    cluster of the cluster tree at `level`, factored and solved for one
+    right-hand side."""
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    import numpy as np
+    from oracle.assemble import Discretisation
+    from oracle.cluster import Structure
+    from oracle.hmatrix import HLU
+    from oracle.krylov import gmres
+    from paper_2211_11303_amd.inputs import exact_solution_cols
+
+    d = Discretisation(n, kappa)
+    mid = d.mesh.midpoints2()
+    full = Structure(mid, leaf, 2.0)
+    c = next(c for c in full.clusters if c.level == level)
+    idx = np.sort(full.perm[c.begin:c.end])
+    A = d.A[idx][:, idx].tocsr()
+    s = Structure(mid[idx], leaf, 2.0)
+    t0 = time.perf_counter()
+    h = HLU(s, A, eps).factor()
+    t_factor = time.perf_counter() - t0
+    x = exact_solution_cols(len(idx), 1, seed=0)[0]
+    b = A @ x
+    t1 = time.perf_counter()
+    _, info = gmres(A, b, h.solve, restart=restart, tol=tol, max_iters=500)
+    t_solve = time.perf_counter() - t1
+    return {
+        "value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"principal block of the {n}^3 matrix on one level-{level} cluster "
+                   f"({len(idx)} of {d.N} unknowns, kappa {kappa:g}, leaf {leaf}, eps {eps:g}): "
+                   f"oracle H-LU factor {t_factor:.1f} s, then GMRES({restart}) to {tol:g} on one "
+                   f"right-hand side ({info['iters']} iterations), 1 BLAS thread"),
+        "factor_s": t_factor, "solve_s": t_solve, "unknowns": int(len(idx)),
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
+              f"supported by this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2211_11303_amd import hlu, inputs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    log(f"assembling n={args.n}")
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(args.n, args.kappa)
+    A = hlu.SpMat(rp, ci, va)
+    N = A.n
+    H = hlu.HLU(rp, ci, va, mid, eta=2.0, leaf=args.leaf)
+    log(f"N={N}: planning the factorisation")
+    ws32 = H.hlu_workspace_bytes(args.eps, prec="fp32")
+    setup_s = time.perf_counter() - t
+    log(f"setup {setup_s:.1f}s, workspace {ws32 / 1e9:.1f} GB")
+    stats0 = H.hlu_get_stats()
+
+    # right-hand sides for seeds 0..2, resident on the device
+    X = [torch.tensor(inputs.exact_solution_cols(N, args.nrhs, seed=s), device="cuda") for s in range(3)]
+    B = [A.hlu_spmv(x) for x in X]
+    torch.cuda.synchronize()
+
+    def factor(prec):
+        log(f"{prec}: first factorisation (uploads plans, binds workspace)")
+        H.hlu_factor(args.eps, prec=prec, allow_overflow=True)
+        log(f"{prec}: timed factorisation")
+        _, tf = event_time(lambda: H.hlu_factor(args.eps, prec=prec, allow_overflow=True), stream)
+        log(f"{prec}: factor {tf:.2f}s")
+        return tf, H.hlu_get_stats()
+
+    def solve_batch(i):
+        return hlu.gmres_solve(A, B[i % 3], H, restart=args.restart, tol=args.tol, max_iters=1000,
+                               raise_on_fail=False)
+
+    result = {}
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+        tf, st = factor(prec)
+        for w in range(args.warmup):
+            solve_batch(w)
+        # one preconditioner application, timed with HIP events on this stream
+        _, t_apply = event_time(lambda: H.hlu_solve(B[0]), stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, relres, errs = [], [], []
+        for k in range(args.steps):
+            x, infos = solve_batch(k)
+            log(f"{prec}: step {k} iters {[i['iters'] for i in infos]}")
+            iters += [i["iters"] for i in infos]
+            relres += [i["relres"] for i in infos]
+            errs.append(((x - X[k % 3]).norm(dim=1) / X[k % 3].norm(dim=1)).max().item())
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        result[prec] = dict(factor_s=tf, T=T, solves_per_s=args.steps * args.nrhs / T, iters=iters,
+                            relres_max=max(relres), err_xstar_max=max(errs), apply_s=t_apply,
+                            max_rank=st["max_rank"], mean_rank=st["mean_rank"],
+                            lowrank_entries=st["lowrank_entries"], capped=st["capped_blocks"])
+
+    r32 = result["fp32"]
+    # algorithmic bytes of one H-solve (L then U sweep) for nrhs columns:
+    # every stored factor entry read once + the vector block read and written
+    # once per sweep
+    s_bytes = 4
+    D = stats0["dense_entries"]
+    R = r32["lowrank_entries"]
+    alg_bytes = s_bytes * (D + R) + 2 * 2 * s_bytes * N * args.nrhs
+    achieved = alg_bytes / r32["apply_s"] / 1e9
+    line = {
+        "metric": "H-LU factor s + precond. GMRES solves/sec to 1e-8; FP32-HLU vs FP64-HLU",
+        "value": r32["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r32["T"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-hlu+f64-gmres",
+        "data": "synthetic",
+        "config": {"workload": f"kuhn-cube-{args.n}^3 Nedelec (N={N}), kappa={args.kappa:g}, eta=2, "
+                               f"leaf={args.leaf}, eps={args.eps:g}, GMRES({args.restart}) to {args.tol:g}, "
+                               f"{args.nrhs} rhs per step",
+                   "n": args.n, "N": N, "nnz": A.nnz, "kappa": args.kappa, "eps": args.eps,
+                   "leaf": args.leaf, "nrhs": args.nrhs, "restart": args.restart, "tol": args.tol},
+        "factor_s_fp32": r32["factor_s"],
+        "iters_fp32": sorted(set(r32["iters"])),
+        "relres_max_fp32": r32["relres_max"],
+        "err_vs_xstar_max_fp32": r32["err_xstar_max"],
+        "setup_s": setup_s,
+        "workspace_gb_fp32": ws32 / 1e9,
+        "structure": {k: stats0[k] for k in ("num_clusters", "num_leaf_clusters", "num_admissible",
+                                              "num_dense", "dense_entries", "factor_waves",
+                                              "factor_tasks", "solve_waves")},
+        "ranks_fp32": {"max": r32["max_rank"], "mean": r32["mean_rank"], "capped": r32["capped"]},
+        "roofline": {"bound": "hbm", "kernel": "H-solve (L then U sweep), one application, fp32 factors",
+                     "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "traffic": None, "alg_bytes": alg_bytes, "apply_s": r32["apply_s"]},
+    }
+    if "fp64" in result:
+        r64 = result["fp64"]
+        line.update({"factor_s_fp64": r64["factor_s"], "solves_per_s_fp64": r64["solves_per_s"],
+                     "iters_fp64": sorted(set(r64["iters"])), "relres_max_fp64": r64["relres_max"],
+                     "err_vs_xstar_max_fp64": r64["err_xstar_max"],
+                     "ranks_fp64": {"max": r64["max_rank"], "mean": r64["mean_rank"]},
+                     "fp32_over_fp64_solves": r32["solves_per_s"] / r64["solves_per_s"]})
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        line["cpu_baseline"] = cpu_baseline(args.n, args.kappa, args.leaf, args.eps, args.restart, args.tol,
+                                            args.cpu_level)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

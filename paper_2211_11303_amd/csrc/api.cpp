@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -29,7 +30,7 @@ void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vect
 // kernels (kernels_hlu.hip / kernels_vec.hip)
 template <class T>
 hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status, double eps,
-                       double floor_rel, int32_t max_leaf, int32_t tile_base, hipStream_t s);
+                       double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64, hipStream_t s);
 hipError_t spmv_launch(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                        double* y, int32_t nrhs, int64_t ld, double alpha, double beta, hipStream_t s);
 template <class T>
@@ -159,6 +160,7 @@ struct hlu_s {
   bool factored = false;
   int32_t prec = HLU_FP64;
   double eps = 0.0;
+  bool factor_compute64 = false;
   hlu_stats stats{};
   ~hlu_s() {
     if (d_perm) (void)hipFree(d_perm);
@@ -271,14 +273,14 @@ void ensure_device(hlu_s* h) {
 }
 
 template <class T>
-void run_plan(hlu_s* h, const Plan& pl, const DevArrays& d, hipStream_t s) {
+void run_plan(hlu_s* h, const Plan& pl, const DevArrays& d, bool compute64, hipStream_t s) {
   const WorkLayout L = work_layout(*h->plans, h->prec);
   T* arena = static_cast<T*>(h->work);
   int32_t* dims = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.dims_off);
   int32_t* status = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.status_off);
   int32_t tile_base = 0;
   for (const Wave& w : pl.waves) {
-    HIP_OK(launch_wave<T>(arena, d.P, w, dims, status, h->eps, kFloorRel, h->max_leaf, tile_base, s));
+    HIP_OK(launch_wave<T>(arena, d.P, w, dims, status, h->eps, kFloorRel, h->max_leaf, tile_base, compute64, s));
     tile_base += w.gemm_tiles;
   }
 }
@@ -296,7 +298,7 @@ void factor_impl(hlu_s* h, hipStream_t s) {
   HIP_OK(scatter_values_launch<T>((int64_t)h->col.size(), h->d_target, h->d_val, arena, s));
   HIP_OK(zero_int_launch(dims, st.num_slots, s));
   HIP_OK(zero_int_launch(status, 64, s));
-  run_plan<T>(h, ps.factor, *h->dfactor, s);
+  run_plan<T>(h, ps.factor, *h->dfactor, h->factor_compute64, s);
 }
 
 template <class T>
@@ -312,7 +314,8 @@ void solve_impl(hlu_s* h, const Plan& pl, const DevArrays& d, const double* b, d
     const int32_t nc = std::min(st.max_rhs, nrhs - c0);
     HIP_OK(gather_launch<T>(N, nc, h->d_perm, b + (int64_t)c0 * ld, ld, arena + st.vec_off, N, s));
     HIP_OK(set_int_launch(dims + st.nrhs_slot, nc, s));
-    run_plan<T>(h, pl, d, s);
+    // the solves read FP32 factors but accumulate in FP64
+    run_plan<T>(h, pl, d, true, s);
     (void)apply;
     HIP_OK(scatter_perm_launch<T>(N, nc, h->d_perm, arena + st.vec_off, N, x + (int64_t)c0 * ld, ld, s));
   }
@@ -506,6 +509,10 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     h->factored = false;
     h->prec = o->prec;
     h->eps = o->eps;
+    {
+      const char* e = getenv("HLU_DEBUG_FACTOR_COMPUTE64");
+      h->factor_compute64 = (o->prec == HLU_FP64) || (e && e[0] == '1');
+    }
     if (o->prec == HLU_FP32) factor_impl<float>(h, s);
     else factor_impl<double>(h, s);
     HIP_OK(hipStreamSynchronize(s));

@@ -25,10 +25,10 @@ __device__ __forceinline__ T& at(T* base, const MatRef& m, int i, int j) {
 // Unpivoted right-looking LU of one dense diagonal leaf per workgroup,
 // staged in LDS.  A zero pivot is counted in status[0] (the factor goes on,
 // so that every wave finishes); |pivot| extremes are not tracked here.
-template <class T>
+template <class T, class C>
 __global__ void __launch_bounds__(256) getrf_kernel(T* arena, const GetrfOp* ops, int32_t* status) {
   extern __shared__ unsigned char smem_raw[];
-  T* D = reinterpret_cast<T*>(smem_raw);
+  C* D = reinterpret_cast<C*>(smem_raw);
   const GetrfOp op = ops[blockIdx.x];
   const int m = op.m;
   T* g = arena + op.off;
@@ -38,11 +38,11 @@ __global__ void __launch_bounds__(256) getrf_kernel(T* arena, const GetrfOp* ops
   }
   __syncthreads();
   for (int p = 0; p < m; ++p) {
-    const T piv = D[p + p * m];
-    if (piv == T(0)) {
+    const C piv = D[p + p * m];
+    if (piv == C(0)) {
       if (threadIdx.x == 0) atomicAdd(&status[0], 1);
     }
-    const T inv = piv == T(0) ? T(0) : T(1) / piv;
+    const C inv = piv == C(0) ? C(0) : C(1) / piv;
     for (int i = p + 1 + threadIdx.x; i < m; i += blockDim.x) D[i + p * m] *= inv;
     __syncthreads();
     const int rem = m - p - 1;
@@ -54,78 +54,96 @@ __global__ void __launch_bounds__(256) getrf_kernel(T* arena, const GetrfOp* ops
   }
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int i = e % m, j = e / m;
-    g[i + (int64_t)j * op.ld] = D[i + j * m];
+    g[i + (int64_t)j * op.ld] = T(D[i + j * m]);
   }
 }
 
 // ----------------------------------------------------------------- TRI
-// Triangular solve / multiply with a dense diagonal leaf (m <= kMaxLeaf),
-// one workgroup per task; columns of V are processed in chunks of 64 held
-// in LDS, one thread per column.
-constexpr int kTriCols = 64;
+// Triangular solve / multiply with a dense diagonal leaf (m <= max leaf),
+// one workgroup per task.  The leaf and a chunk of up to 64 columns of V
+// are staged in LDS; substitutions eliminate one row per step with all
+// threads updating the remaining rows (m barriers per chunk).
+constexpr int kTriMaxCols = 64;
+constexpr size_t kLdsBytes = 160 * 1024;
 
-template <class T>
-__global__ void __launch_bounds__(256) tri_kernel(T* arena, const TriOp* ops, const int32_t* dims) {
+template <class T, class C>
+__global__ void __launch_bounds__(256) tri_kernel(T* arena, const TriOp* ops, const int32_t* dims,
+                                                  int tri_cols) {
   extern __shared__ unsigned char smem_raw[];
-  T* Vs = reinterpret_cast<T*>(smem_raw);  // m x kTriCols, row-major by column index
   const TriOp op = ops[blockIdx.x];
   const int m = op.m;
+  const int kTriCols = tri_cols;                     // columns per chunk (<= 64)
+  C* Ts = reinterpret_cast<C*>(smem_raw);          // m x m, column-major (ld m)
+  C* Vs = Ts + m * m;                                // m x kTriCols, row i at Vs[i * kTriCols]
   const int p = dimv(op.V.cols, dims);
-  const T* Tm = arena + op.tri;
-  const int ld = op.ld;
+  const T* Tg = arena + op.tri;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) Ts[e] = C(Tg[(e % m) + (int64_t)(e / m) * op.ld]);
   const bool mul = op.mode == kMulUpper || op.mode == kMulUnitLower;
   for (int c0 = 0; c0 < p; c0 += kTriCols) {
     const int pc = min(kTriCols, p - c0);
     for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
       const int i = e % m, j = e / m;
-      Vs[i * kTriCols + j] = at(arena, op.V, i, c0 + j);
+      Vs[i * kTriCols + j] = C(at(arena, op.V, i, c0 + j));
     }
     __syncthreads();
-    const int j = threadIdx.x;
-    if (j < pc) {
-      switch (op.mode) {
-        case kSolveUnitLower:
-          for (int i = 1; i < m; ++i) {
-            T s = Vs[i * kTriCols + j];
-            for (int q = 0; q < i; ++q) s -= Tm[i + (int64_t)q * ld] * Vs[q * kTriCols + j];
-            Vs[i * kTriCols + j] = s;
+    switch (op.mode) {
+      case kSolveUnitLower:     // forward: rows below step q get V[r] -= L[r][q] V[q]
+        for (int q = 0; q < m - 1; ++q) {
+          const int rows = m - q - 1;
+          for (int e = threadIdx.x; e < rows * pc; e += blockDim.x) {
+            const int r = q + 1 + e % rows, j = e / rows;
+            Vs[r * kTriCols + j] -= Ts[r + q * m] * Vs[q * kTriCols + j];
           }
-          break;
-        case kSolveUpperT:
-          for (int i = 0; i < m; ++i) {
-            T s = Vs[i * kTriCols + j];
-            for (int q = 0; q < i; ++q) s -= Tm[q + (int64_t)i * ld] * Vs[q * kTriCols + j];
-            Vs[i * kTriCols + j] = s / Tm[i + (int64_t)i * ld];
+          __syncthreads();
+        }
+        break;
+      case kSolveUpperT:        // U^T lower, non-unit: scale row q, then update below
+        for (int q = 0; q < m; ++q) {
+          const C d = C(1) / Ts[q + q * m];
+          for (int j = threadIdx.x; j < pc; j += blockDim.x) Vs[q * kTriCols + j] *= d;
+          __syncthreads();
+          const int rows = m - q - 1;
+          for (int e = threadIdx.x; e < rows * pc; e += blockDim.x) {
+            const int r = q + 1 + e % rows, j = e / rows;
+            Vs[r * kTriCols + j] -= Ts[q + r * m] * Vs[q * kTriCols + j];
           }
-          break;
-        case kSolveUpper:
-          for (int i = m - 1; i >= 0; --i) {
-            T s = Vs[i * kTriCols + j];
-            for (int q = i + 1; q < m; ++q) s -= Tm[i + (int64_t)q * ld] * Vs[q * kTriCols + j];
-            Vs[i * kTriCols + j] = s / Tm[i + (int64_t)i * ld];
+          __syncthreads();
+        }
+        break;
+      case kSolveUpper:         // backward: scale row q, then update above
+        for (int q = m - 1; q >= 0; --q) {
+          const C d = C(1) / Ts[q + q * m];
+          for (int j = threadIdx.x; j < pc; j += blockDim.x) Vs[q * kTriCols + j] *= d;
+          __syncthreads();
+          for (int e = threadIdx.x; e < q * pc; e += blockDim.x) {
+            const int r = e % q, j = e / q;
+            Vs[r * kTriCols + j] -= Ts[r + q * m] * Vs[q * kTriCols + j];
           }
-          break;
-        case kMulUpper:
-          for (int i = 0; i < m; ++i) {
-            T s = 0;
-            for (int q = i; q < m; ++q) s += Tm[i + (int64_t)q * ld] * Vs[q * kTriCols + j];
-            at(arena, op.W, i, c0 + j) = s;
-          }
-          break;
-        case kMulUnitLower:
-          for (int i = 0; i < m; ++i) {
-            T s = Vs[i * kTriCols + j];
-            for (int q = 0; q < i; ++q) s += Tm[i + (int64_t)q * ld] * Vs[q * kTriCols + j];
-            at(arena, op.W, i, c0 + j) = s;
-          }
-          break;
-      }
+          __syncthreads();
+        }
+        break;
+      case kMulUpper:
+        for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
+          const int i = e % m, j = e / m;
+          C s = 0;
+          for (int q = i; q < m; ++q) s += Ts[i + q * m] * Vs[q * kTriCols + j];
+          at(arena, op.W, i, c0 + j) = T(s);
+        }
+        break;
+      case kMulUnitLower:
+        for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
+          const int i = e % m, j = e / m;
+          C s = Vs[i * kTriCols + j];
+          for (int q = 0; q < i; ++q) s += Ts[i + q * m] * Vs[q * kTriCols + j];
+          at(arena, op.W, i, c0 + j) = T(s);
+        }
+        break;
     }
     __syncthreads();
     if (!mul) {
       for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
         const int i = e % m, jj = e / m;
-        at(arena, op.V, i, c0 + jj) = Vs[i * kTriCols + jj];
+        at(arena, op.V, i, c0 + jj) = T(Vs[i * kTriCols + jj]);
       }
     }
     __syncthreads();
@@ -138,12 +156,12 @@ __global__ void __launch_bounds__(256) tri_kernel(T* arena, const TriOp* ops, co
 // the 256 threads accumulates a 4 x 4 sub-tile.
 constexpr int kGT = 64, kGK = 16;
 
-template <class T>
+template <class T, class C>
 __global__ void __launch_bounds__(256) gemm_kernel(T* arena, const GemmOp* ops, const GemmTerm* terms,
                                                    const int32_t* tile_op, const int32_t* tile_ij,
                                                    int32_t tile0, const int32_t* dims) {
-  __shared__ T As[kGK][kGT + 1];
-  __shared__ T Bs[kGK][kGT + 1];
+  __shared__ C As[kGK][kGT + 1];
+  __shared__ C Bs[kGK][kGT + 1];
   const int tile = tile0 + blockIdx.x;
   const GemmOp op = ops[tile_op[tile]];
   const int ti = tile_ij[tile] >> 16, tj = tile_ij[tile] & 0xffff;
@@ -151,20 +169,20 @@ __global__ void __launch_bounds__(256) gemm_kernel(T* arena, const GemmOp* ops, 
   const int i0 = ti * kGT, j0 = tj * kGT;
   if (i0 >= M || j0 >= N) return;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  T acc[4][4];
+  C acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+    for (int b = 0; b < 4; ++b) acc[a][b] = C(0);
   for (int t = 0; t < op.nt; ++t) {
     const GemmTerm tm = terms[op.t0 + t];
     const int K = dimv(tm.A.cols, dims);
-    const T alpha = T(tm.alpha);
-    T part[4][4];
+    const C alpha = C(tm.alpha);
+    C part[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) part[a][b] = T(0);
+      for (int b = 0; b < 4; ++b) part[a][b] = C(0);
     for (int k0 = 0; k0 < K; k0 += kGK) {
       for (int e = threadIdx.x; e < kGK * kGT; e += 256) {
         // A tile: rows i0.., cols k0..; index so that consecutive threads
@@ -172,16 +190,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(T* arena, const GemmOp* ops, 
         int r, c;
         if (tm.A.rs == 1) { r = e % kGT; c = e / kGT; } else { c = e % kGK; r = e / kGK; }
         const int gi = i0 + r, gk = k0 + c;
-        As[c][r] = (gi < M && gk < K) ? at(arena, tm.A, gi, gk) : T(0);
+        As[c][r] = (gi < M && gk < K) ? C(at(arena, tm.A, gi, gk)) : C(0);
         int r2, c2;
         if (tm.B.cs == 1) { c2 = e % kGT; r2 = e / kGT; } else { r2 = e % kGK; c2 = e / kGK; }
         const int bk = k0 + r2, bj = j0 + c2;
-        Bs[r2][c2] = (bk < K && bj < N) ? at(arena, tm.B, bk, bj) : T(0);
+        Bs[r2][c2] = (bk < K && bj < N) ? C(at(arena, tm.B, bk, bj)) : C(0);
       }
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < kGK; ++kk) {
-        T av[4], bv[4];
+        C av[4], bv[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
 #pragma unroll
@@ -198,7 +216,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(T* arena, const GemmOp* ops, 
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] += alpha * part[a][b];
   }
-  const T beta = T(op.beta);
+  const C beta = C(op.beta);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -206,7 +224,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(T* arena, const GemmOp* ops, 
       const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
       if (gi < M && gj < N) {
         T& c = at(arena, op.C, gi, gj);
-        c = (op.beta == 0.0 ? T(0) : beta * c) + acc[a][b];
+        c = T((op.beta == 0.0 ? C(0) : beta * C(c)) + acc[a][b]);
       }
     }
 }
@@ -333,7 +351,7 @@ __device__ void jacobi_eig(double* A, int K, double* U1, double* U2, double* cs_
     const double offs = red[0] + red[1] + red[2] + red[3];
     const double tots = red[4] + red[5] + red[6] + red[7];
     __syncthreads();
-    if (tots == 0.0 || offs <= 1e-30 * tots) break;
+    if (tots == 0.0 || offs <= 1e-26 * tots) break;
     for (int r = 0; r < Kp - 1; ++r) {
       // rotation parameters for the pairs of this round
       for (int k = threadIdx.x; k < npair; k += blockDim.x) {
@@ -353,7 +371,8 @@ __device__ void jacobi_eig(double* A, int K, double* U1, double* U2, double* cs_
         double c = 1.0, s = 0.0;
         if (q < K) {
           const double apq = A[p * kLd + q];
-          if (apq != 0.0) {
+          const double app = A[p * kLd + p], aqq = A[q * kLd + q];
+          if (fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)) && apq != 0.0) {
             const double th = (A[q * kLd + q] - A[p * kLd + p]) / (2.0 * apq);
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
@@ -559,24 +578,36 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
 
 // ------------------------------------------------------------ launchers
 
-template <class T>
-hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
-                       double eps, double floor_rel, int32_t max_leaf, int32_t tile_base,
-                       hipStream_t s) {
+template <class T, class C>
+hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
+                         double eps, double floor_rel, int32_t max_leaf, int32_t tile_base,
+                         hipStream_t s) {
+  static bool attrs_set = false;
+  if (!attrs_set) {
+    // allow dynamic LDS up to the 160 KB of a gfx950 CU
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::getrf_kernel<T, C>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dev::kLdsBytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::tri_kernel<T, C>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dev::kLdsBytes);
+    attrs_set = true;
+  }
   if (w.count[kFill] > 0) {
     dim3 g(64, w.count[kFill]);
     dev::fill_kernel<T><<<g, 256, 0, s>>>(arena, P.fill + w.begin[kFill], dims);
   }
   if (w.count[kGetrf] > 0) {
-    const size_t sh = (size_t)max_leaf * max_leaf * sizeof(T);
-    dev::getrf_kernel<T><<<w.count[kGetrf], 256, sh, s>>>(arena, P.getrf + w.begin[kGetrf], status);
+    const size_t sh = (size_t)max_leaf * max_leaf * sizeof(C);
+    dev::getrf_kernel<T, C><<<w.count[kGetrf], 256, sh, s>>>(arena, P.getrf + w.begin[kGetrf], status);
   }
   if (w.count[kTri] > 0) {
-    const size_t sh = (size_t)max_leaf * dev::kTriCols * sizeof(T);
-    dev::tri_kernel<T><<<w.count[kTri], 256, sh, s>>>(arena, P.tri + w.begin[kTri], dims);
+    const size_t tri_bytes = (size_t)max_leaf * max_leaf * sizeof(C);
+    int cols = (int)((dev::kLdsBytes - tri_bytes) / ((size_t)max_leaf * sizeof(C)));
+    cols = cols > dev::kTriMaxCols ? dev::kTriMaxCols : cols;
+    const size_t sh = tri_bytes + (size_t)max_leaf * cols * sizeof(C);
+    dev::tri_kernel<T, C><<<w.count[kTri], 256, sh, s>>>(arena, P.tri + w.begin[kTri], dims, cols);
   }
   if (w.gemm_tiles > 0) {
-    dev::gemm_kernel<T><<<w.gemm_tiles, 256, 0, s>>>(arena, P.gemm, P.terms, P.tile_op, P.tile_ij,
+    dev::gemm_kernel<T, C><<<w.gemm_tiles, 256, 0, s>>>(arena, P.gemm, P.terms, P.tile_op, P.tile_ij,
                                                       tile_base, dims);
   }
   if (w.count[kTrunc] > 0) {
@@ -586,9 +617,20 @@ hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims,
   return hipGetLastError();
 }
 
+// T: storage type of the factors; compute64: do the arithmetic of the dense
+// tasks in FP64 (always the case for FP64 storage).
+template <class T>
+hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
+                       double eps, double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64,
+                       hipStream_t s) {
+  if (compute64)
+    return launch_wave_c<T, double>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s);
+  return launch_wave_c<T, T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s);
+}
+
 template hipError_t launch_wave<float>(float*, const DevPlan&, const Wave&, int32_t*, int32_t*, double,
-                                       double, int32_t, int32_t, hipStream_t);
+                                       double, int32_t, int32_t, bool, hipStream_t);
 template hipError_t launch_wave<double>(double*, const DevPlan&, const Wave&, int32_t*, int32_t*, double,
-                                        double, int32_t, int32_t, hipStream_t);
+                                        double, int32_t, int32_t, bool, hipStream_t);
 
 }  // namespace hlu

@@ -85,10 +85,13 @@ int32_t dyn(int32_t slot) { return -(slot + 1); }
 // H-block handle: a node of the block tree or a temporary low-rank block.
 struct HB {
   BlockKind kind;
-  int32_t node;      // block-tree node id (-1 for temporaries)
+  int32_t node;      // block-tree node id (-1 for a quadrant of a low-rank block)
   int32_t r0, r1, c0, c1;
   View D, X, Y;      // storage of leaves
   int32_t slot = -1, cap = 0;
+  // low-rank updates land in the low-rank leaf `root` (a block-tree node),
+  // at row/column offset (roff, coff) inside it
+  int32_t root = -1, roff = 0, coff = 0;
 };
 
 struct Access {
@@ -186,6 +189,7 @@ class Planner {
       h.cap = st_.cap[l];
       h.X = View{st_.off[l], 1, m, m, dyn(h.slot), m, h.cap, rc.begin, -1, leaf_buf_[l], false};
       h.Y = View{st_.yoff[l], 1, n, n, dyn(h.slot), n, h.cap, cc.begin, -1, leaf_ybuf_[l], false};
+      h.root = node;
     }
     return h;
   }
@@ -299,8 +303,8 @@ class Planner {
       const int32_t m = C.r1 - C.r0, n = C.c1 - C.c0;
       View Sv{inits[i].off, 1, m, m, n, m, n, C.r0, C.c0, init_buf_[i], false};
       (void)b;
-      if (n <= m) trunc_op(C, {{Sv, identity(n), 0, 0, 1.0}});
-      else trunc_op(C, {{identity(m), transpose(Sv), 0, 0, 1.0}});
+      if (n <= m) defer(C, Sv, identity(n), 1.0);
+      else defer(C, identity(m), transpose(Sv), 1.0);
     }
   }
 
@@ -321,6 +325,7 @@ class Planner {
 
   void trsm_lower(const HB& Ld, const HB& B) {
     if (B.kind == kLowRank) {
+      flush(B);
       hsolve_lower(Ld, B.X);
     } else if (B.kind == kDense) {
       hsolve_lower(Ld, B.D);
@@ -337,6 +342,7 @@ class Planner {
 
   void trsm_upper(const HB& Ud, const HB& B) {
     if (B.kind == kLowRank) {
+      flush(B);
       hsolve_upper_T(Ud, B.Y);
     } else if (B.kind == kDense) {
       hsolve_upper_T(Ud, transpose(B.D));
@@ -416,6 +422,8 @@ class Planner {
 
   // C -= A B in H-arithmetic.
   void gemm(const HB& C, const HB& A, const HB& B) {
+    if (A.kind == kLowRank) flush(A);
+    if (B.kind == kLowRank) flush(B);
     if (A.kind == kLowRank) {
       View W = temp_spatial(C.c0, C.c1 - C.c0, A.X.cols, A.cap);
       hmv(B, true, A.Y, W, 1.0, 0.0);
@@ -460,9 +468,11 @@ class Planner {
           HB Ai0 = son(A, i, 0), B0j = son(B, 0, j);
           HB Q = temp_lowrank(Ai0.r0, Ai0.r1, B0j.c0, B0j.c1);
           for (int k = 0; k < 2; ++k) gemm(Q, son(A, i, k), son(B, k, j));
-          parts.push_back({Q.X, Q.Y, Q.r0 - C.r0, Q.c0 - C.c0, 1.0});
+          flush(Q);
+          parts.push_back({Q.X, Q.Y, C.roff + Q.r0 - C.r0, C.coff + Q.c0 - C.c0, 1.0});
         }
-      trunc_op(C, parts);
+      flush(C);
+      trunc_op(root_of(C), parts);
     } else {
       fail(HLU_ERR_INVALID_ARG, "planner: dense target with two subdivided factors");
     }
@@ -473,7 +483,7 @@ class Planner {
     if (C.kind == kDense) {
       gemm_op(C.D, 1.0, {{X, transpose(Y), alpha}});
     } else if (C.kind == kLowRank) {
-      trunc_op(C, {{X, Y, 0, 0, alpha}});
+      defer(C, X, Y, alpha);
     } else {
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
@@ -487,6 +497,8 @@ class Planner {
   void hmv(const HB& B, bool trans, const View& V, const View& W, double alpha, double beta) {
     std::vector<HB> lv;
     collect_leaves(B, &lv);
+    for (const HB& l : lv)
+      if (l.kind == kLowRank) flush(l);
     const int32_t out0 = trans ? B.c0 : B.r0, out1 = trans ? B.c1 : B.r1;
     const int32_t in0 = trans ? B.r0 : B.c0;
     const int32_t lf0 = leaf_of_pos_[out0], lf1 = leaf_of_pos_[out1 - 1] + 1;
@@ -719,13 +731,65 @@ class Planner {
     const int32_t m = r1 - r0, n = c1 - c0;
     h.cap = std::max(1, std::min(std::min(m, n), kcap_));
     h.slot = st_.num_slots++;
-    View X = temp_spatial(r0, m, dyn(h.slot), h.cap);
-    View Y = temp_spatial(c0, n, dyn(h.slot), h.cap);
-    h.X = X;
-    h.Y = Y;
+    h.X = temp_spatial(r0, m, dyn(h.slot), h.cap);
+    h.Y = temp_spatial(c0, n, dyn(h.slot), h.cap);
+    h.root = -2 - h.slot;              // temporaries are their own root
+    temp_hb_[h.root] = h;
     return h;
   }
 
+  HB root_of(const HB& C) const {
+    if (C.root >= 0) return block(C.root);
+    return temp_hb_.at(C.root);
+  }
+
+  HB quadrant(const HB& C, int32_t r0, int32_t r1, int32_t c0, int32_t c1) const {
+    HB q;
+    q.kind = kLowRank;
+    q.node = -1;
+    q.r0 = r0;
+    q.r1 = r1;
+    q.c0 = c0;
+    q.c1 = c1;
+    q.root = C.root;
+    q.roff = C.roff + (r0 - C.r0);
+    q.coff = C.coff + (c0 - C.c0);
+    return q;
+  }
+
+ public:
+  // Record the low-rank term alpha X Y^T of the low-rank leaf (or quadrant
+  // of a leaf) C; the recorded terms are truncated into C together when C
+  // is next read or when kMaxPending terms have accumulated.
+  static constexpr size_t kMaxPending = 1;
+  void defer(const HB& C, const View& X, const View& Y, double alpha) {
+    auto& v = pending_[C.root];
+    v.push_back({X, Y, C.roff, C.coff, alpha});
+    if (v.size() >= kMaxPending) flush(C);
+  }
+
+  void flush(const HB& C) {
+    if (C.root == -1) return;
+    auto it = pending_.find(C.root);
+    if (it == pending_.end()) return;
+    std::vector<PartSpec> parts;
+    parts.swap(it->second);
+    pending_.erase(it);
+    trunc_op(root_of(C), parts);
+  }
+
+  void flush_all() {
+    std::vector<int32_t> roots;
+    for (auto& kv : pending_) roots.push_back(kv.first);
+    std::sort(roots.begin(), roots.end());
+    for (int32_t r : roots) {
+      HB h;
+      h.root = r;
+      flush(h);
+    }
+  }
+
+ private:
   void grow_segments() {
     if ((int64_t)last_w_.size() < nseg_) {
       last_w_.resize(nseg_, -1);
@@ -870,6 +934,8 @@ class Planner {
   std::vector<int32_t> leaf_of_pos_;
   std::vector<int32_t> leaf_buf_, leaf_ybuf_, init_buf_;
   std::vector<Temp> temps_;
+  std::map<int32_t, std::vector<PartSpec>> pending_;
+  std::map<int32_t, HB> temp_hb_;
   std::vector<int32_t> temp_of_buf_;
   int64_t temp_peak_ = 0;
   int64_t max_peak_ = 0;
@@ -901,6 +967,7 @@ void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
   pl.begin_plan(&ps.factor, temp_base);
   pl.init_lowrank(ps.init_blocks);
   pl.hlu(pl.block(0));
+  pl.flush_all();
   pl.end_plan();
   st.temp_elems = pl.temp_used();
 
