@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "plan.h"
+#include "solve_sched.h"
 #include "structure.h"
 
 namespace hlu {
@@ -58,6 +59,22 @@ hipError_t combine_launch(int32_t N, int32_t nrhs, int32_t nz, const double* Z, 
 hipError_t residual_launch(int32_t N, int32_t nrhs, const double* b, int64_t ldb, double* r, hipStream_t s);
 hipError_t copy_cols_launch(int32_t N, int32_t nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,
                             hipStream_t s);
+struct SolveDev {
+  const STask* tasks;
+  const SLeaf* leaves;
+  const SDense* dense;
+  const SLow* low;
+  const STprod* tprod;
+  double* y;
+  double* tbuf;
+  int32_t* leaf_flag;
+  int32_t* tp_flag;
+  int32_t* ctr;
+  int32_t ntasks, n_fwd, L, max_m, max_rhs;
+};
+template <class T>
+hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const SolveDev& d, int32_t N,
+                                   int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s);
 
 namespace {
 
@@ -152,6 +169,11 @@ struct hlu_s {
   std::unique_ptr<DevArrays> dfactor, dsolve, dapply;
   int32_t* d_perm = nullptr;
   int64_t* d_target = nullptr;   // arena element of every stored entry of A
+  // persistent solve
+  std::unique_ptr<SolveSched> ssched;
+  std::vector<void*> sowned;
+  SolveDev sdev{};
+  int32_t solve_epoch = 0;
   double* d_val = nullptr;
   // workspace
   void* work = nullptr;
@@ -163,6 +185,8 @@ struct hlu_s {
   bool factor_compute64 = false;
   hlu_stats stats{};
   ~hlu_s() {
+    for (void* p : sowned)
+      if (p) (void)hipFree(p);
     if (d_perm) (void)hipFree(d_perm);
     if (d_target) (void)hipFree(d_target);
     if (d_val) (void)hipFree(d_val);
@@ -210,6 +234,10 @@ void ensure_plans(hlu_s* h, int32_t kcap) {
   h->dfactor.reset();
   h->dsolve.reset();
   h->dapply.reset();
+  for (void* p : h->sowned)
+    if (p) (void)hipFree(p);
+  h->sowned.clear();
+  h->ssched.reset();
   h->factored = false;
   // scatter targets depend on the storage layout
   if (h->d_target) {
@@ -234,6 +262,33 @@ void ensure_device(hlu_s* h) {
     auto d = std::make_unique<DevArrays>();
     d->load(ps.apply);
     h->dapply = std::move(d);
+  }
+  if (!h->ssched) {
+    auto sc = std::make_unique<SolveSched>();
+    build_solve_sched(h->S, ps.store, sc.get());
+    auto keep = [&](void* p) { h->sowned.push_back(p); return p; };
+    SolveDev& d = h->sdev;
+    d.tasks = static_cast<const STask*>(keep(upload(sc->tasks)));
+    d.leaves = static_cast<const SLeaf*>(keep(upload(sc->leaves)));
+    d.dense = static_cast<const SDense*>(keep(upload(sc->dense)));
+    d.low = static_cast<const SLow*>(keep(upload(sc->low)));
+    d.tprod = static_cast<const STprod*>(keep(upload(sc->tprod)));
+    d.max_rhs = kMaxRhs;
+    d.y = static_cast<double*>(keep(dmalloc<double>((size_t)h->S.N * kMaxRhs)));
+    d.tbuf = static_cast<double*>(keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc->tbuf_per_rhs) * kMaxRhs)));
+    const size_t nflags = 2 * (size_t)sc->L + sc->tprod.size() + 1;
+    int32_t* flags = static_cast<int32_t*>(keep(dmalloc<int32_t>(nflags)));
+    HIP_OK(hipMemset(flags, 0, nflags * sizeof(int32_t)));
+    d.leaf_flag = flags;
+    d.tp_flag = flags + 2 * sc->L;
+    d.ctr = static_cast<int32_t*>(keep(dmalloc<int32_t>(4)));
+    HIP_OK(hipMemset(d.ctr, 0, 4 * sizeof(int32_t)));
+    d.ntasks = (int32_t)sc->tasks.size();
+    d.n_fwd = sc->n_fwd_tasks;
+    d.L = sc->L;
+    d.max_m = sc->max_m;
+    h->solve_epoch = 0;
+    h->ssched = std::move(sc);
   }
   if (!h->d_perm) h->d_perm = upload(h->S.perm);
   if (!h->d_val) h->d_val = upload(h->val);
@@ -318,6 +373,28 @@ void solve_impl(hlu_s* h, const Plan& pl, const DevArrays& d, const double* b, d
     run_plan<T>(h, pl, d, true, s);
     (void)apply;
     HIP_OK(scatter_perm_launch<T>(N, nc, h->d_perm, arena + st.vec_off, N, x + (int64_t)c0 * ld, ld, s));
+  }
+}
+
+template <class T>
+hipError_t gather_y(hlu_s* h, const double* b, int64_t ld, int32_t nc, hipStream_t s) {
+  return gather_launch<double>(h->S.N, nc, h->d_perm, b, ld, h->sdev.y, h->S.N, s);
+}
+
+// x = P^T U^{-1} L^{-1} P b with the persistent solve kernel (FP64 vectors).
+template <class T>
+void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, int64_t ld, hipStream_t s) {
+  const WorkLayout L = work_layout(*h->plans, h->prec);
+  const T* arena = static_cast<const T*>(h->work);
+  const int32_t* dims = reinterpret_cast<const int32_t*>(static_cast<char*>(h->work) + L.dims_off);
+  const int32_t N = h->S.N;
+  const int grid = std::max(1, std::min<int>(h->sdev.ntasks, 256));   // one 112 KB-LDS workgroup per CU
+  for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
+    const int32_t nc = std::min(kMaxRhs, nrhs - c0);
+    HIP_OK(gather_y<T>(h, b + (int64_t)c0 * ld, ld, nc, s));
+    h->solve_epoch = h->solve_epoch % 1000000000 + 1;
+    HIP_OK(solve_persistent_launch<T>(arena, dims, h->sdev, N, nc, h->solve_epoch, grid, s));
+    HIP_OK(scatter_perm_launch<double>(N, nc, h->d_perm, h->sdev.y, N, x + (int64_t)c0 * ld, ld, s));
   }
 }
 
@@ -535,10 +612,17 @@ hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs,
     HLU_REQUIRE(h && d_b && d_x && nrhs >= 1 && ld >= h->S.N, HLU_ERR_INVALID_ARG, "hlu_solve: bad arguments");
     HLU_REQUIRE(h->factored, HLU_ERR_STATE, "hlu_solve: handle is not factored");
     hipStream_t s = (hipStream_t)stream;
-    if (h->prec == HLU_FP32)
-      solve_impl<float>(h, h->plans->fwd_bwd, *h->dsolve, d_b, d_x, nrhs, ld, false, s);
-    else
-      solve_impl<double>(h, h->plans->fwd_bwd, *h->dsolve, d_b, d_x, nrhs, ld, false, s);
+    const char* e = getenv("HLU_DEBUG_WAVE_SOLVE");
+    if (e && e[0] == '1') {   // the planned wave form of the same solve, for cross-checks
+      if (h->prec == HLU_FP32)
+        solve_impl<float>(h, h->plans->fwd_bwd, *h->dsolve, d_b, d_x, nrhs, ld, false, s);
+      else
+        solve_impl<double>(h, h->plans->fwd_bwd, *h->dsolve, d_b, d_x, nrhs, ld, false, s);
+    } else if (h->prec == HLU_FP32) {
+      solve_persistent_impl<float>(h, d_b, d_x, nrhs, ld, s);
+    } else {
+      solve_persistent_impl<double>(h, d_b, d_x, nrhs, ld, s);
+    }
   });
 }
 

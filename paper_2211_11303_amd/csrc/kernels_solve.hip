@@ -1,0 +1,398 @@
+// Persistent H-triangular solve (Algorithm 1, step III) for gfx950.
+//
+// One launch runs both sweeps.  Workgroups claim tasks in the schedule's
+// order through an atomic counter; a task waits (bounded spin) on the
+// completion flags of the tasks it reads, which always come earlier in the
+// order, so every claimed task can finish.  Results passed between tasks
+// (solution rows, T products) are stored and loaded with agent-scope
+// coherent accesses and flags are set after the stores complete, so no
+// L2 writeback or invalidation (one L2 per XCD) sits on the critical path.
+// Factors are read in their storage type T; arithmetic and vectors are FP64.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "solve_sched.h"
+
+namespace hlu {
+namespace dev {
+
+constexpr int kSolveThreads = 256;
+constexpr int kMaxRhsTile = 8;          // columns per register tile of the triangular solve
+constexpr int kSpinLimit = 1 << 25;     // bounded waits; on overflow the error flag is set
+
+struct SolveArgs {
+  const STask* tasks;
+  const SLeaf* leaves;
+  const SDense* dense;
+  const SLow* low;
+  const STprod* tprod;
+  const int32_t* dims;
+  double* y;            // N x nrhs, cluster order, leading dimension N
+  double* tbuf;         // T products
+  int32_t* leaf_flag;   // 2L flags
+  int32_t* tp_flag;     // one per T-product
+  int32_t* ctr;         // [0] claim counter, [1] finished forward tasks, [2] error
+  int32_t ntasks, n_fwd, N, nrhs, max_rhs, L, epoch;
+};
+
+// Data exchanged between tasks (y, T products) is written and read with
+// agent-scope relaxed atomics: such accesses go to the device coherence
+// point, so no cache writeback/invalidation is needed between tasks.
+__device__ __forceinline__ double cload(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cstore(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t load_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin (relaxed loads, no cache maintenance) until *f == want, bounded;
+// returns false on timeout or if another task already reported one.
+__device__ bool spin_eq(const int32_t* f, int32_t want, int32_t* err) {
+  int spins = 0;
+  while (load_relaxed(f) != want) {
+    if (load_relaxed(err) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
+// After flags were observed by some threads: order the workgroup's later
+// (coherent) loads after the flag loads.
+__device__ void acquire_all() {
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// All threads: wait for flags[lf0..lf1) == epoch, then acquire.
+__device__ void wait_leaves(const SolveArgs& a, int base, int lf0, int lf1) {
+  for (int f = lf0 + (int)threadIdx.x; f < lf1; f += blockDim.x)
+    spin_eq(a.leaf_flag + base + f, a.epoch, a.ctr + 2);
+  acquire_all();
+}
+
+__device__ void wait_one(const SolveArgs& a, const int32_t* f, int32_t want) {
+  if (threadIdx.x == 0) spin_eq(f, want, a.ctr + 2);
+  acquire_all();
+}
+
+// Publish this task's results: every wave completes its coherent stores
+// (workgroup release = wait for outstanding stores), then the flag.
+__device__ void publish(int32_t* f, int32_t epoch) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// acc (m x nrhs, LDS, row-major with stride ldacc) := tri^{-1} acc with the
+// unit lower (forward) or upper (backward) triangle of the diagonal leaf,
+// done by wavefront 0 in registers: lane l owns rows l and l + 64.
+template <class P>
+__device__ void leaf_triangular(const P* D, int m, bool forward, double* acc, int ldacc, int nrhs) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  for (int c0 = 0; c0 < nrhs; c0 += kMaxRhsTile) {
+    const int nc = min(kMaxRhsTile, nrhs - c0);
+    double v0[kMaxRhsTile], v1[kMaxRhsTile];
+#pragma unroll
+    for (int c = 0; c < kMaxRhsTile; ++c) {
+      v0[c] = (lane < m && c < nc) ? acc[lane * ldacc + c0 + c] : 0.0;
+      v1[c] = (lane + 64 < m && c < nc) ? acc[(lane + 64) * ldacc + c0 + c] : 0.0;
+    }
+    if (forward) {
+      for (int q = 0; q < m; ++q) {
+        const int ql = q & 63;
+        const bool hiq = q >= 64;
+        const double l0 = (lane > q && lane < m) ? double(D[lane + (int64_t)q * m]) : 0.0;
+        const double l1 = (lane + 64 > q && lane + 64 < m) ? double(D[lane + 64 + (int64_t)q * m]) : 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxRhsTile; ++c) {
+          const double yq = bcast(hiq ? v1[c] : v0[c], ql);
+          v0[c] -= l0 * yq;
+          v1[c] -= l1 * yq;
+        }
+      }
+    } else {
+      for (int q = m - 1; q >= 0; --q) {
+        const int ql = q & 63;
+        const bool hiq = q >= 64;
+        const double dq = double(D[q + (int64_t)q * m]);
+        const double u0 = lane < q ? double(D[lane + (int64_t)q * m]) : 0.0;
+        const double u1 = (lane + 64 < q) ? double(D[lane + 64 + (int64_t)q * m]) : 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxRhsTile; ++c) {
+          const double zq = bcast(hiq ? v1[c] : v0[c], ql) / dq;
+          if (lane == ql && !hiq) v0[c] = zq;
+          if (lane == ql && hiq) v1[c] = zq;
+          v0[c] -= u0 * zq;
+          v1[c] -= u1 * zq;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhsTile; ++c) {
+      if (c < nc && lane < m) acc[lane * ldacc + c0 + c] = v0[c];
+      if (c < nc && lane + 64 < m) acc[(lane + 64) * ldacc + c0 + c] = v1[c];
+    }
+  }
+}
+
+// Staging buffers of a workgroup (LDS): A chunk (max_m x kKC doubles) and
+// B chunk (kKC x max_rhs doubles).
+constexpr int kKC = 64;
+
+// r[(i, c)] -= sum_k A[i, k] B[k, c] with A (m x K, type T, A[i + k*lda]) and
+// B (K x nrhs, FP64, B[k*bs + c*bcs]); both streamed through LDS in chunks of
+// kKC so that all loads of a chunk are in flight together.
+template <class T>
+__device__ void mm_sub(const T* A, int64_t lda, const double* B, int64_t bs, int64_t bcs, int m, int K,
+                       int nrhs, double* r, double* As, double* Bs) {
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+    const int kc = min(kKC, K - k0);
+    for (int e = threadIdx.x; e < m * kc; e += blockDim.x) {
+      const int i = e % m, k = e / m;
+      As[k * 128 + i] = double(A[i + (int64_t)(k0 + k) * lda]);
+    }
+    for (int e = threadIdx.x; e < kc * nrhs; e += blockDim.x) {
+      const int k = e % kc, c = e / kc;
+      Bs[c * kKC + k] = cload(B + (int64_t)(k0 + k) * bs + (int64_t)c * bcs);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int o = threadIdx.x + q * kSolveThreads;
+      if (o < m * nrhs) {
+        const int i = o % m, c = o / m;
+        double sum = 0.0;
+        for (int k = 0; k < kc; ++k) sum += As[k * 128 + i] * Bs[c * kKC + k];
+        r[q] -= sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+__device__ void dense_contrib(const SolveArgs& a, const T* arena, const SDense& D, int m, int nrhs, double* r,
+                              double* As, double* Bs) {
+  mm_sub<T>(arena + D.off, D.ld, a.y + D.col0, 1, a.N, m, D.ncols, nrhs, r, As, Bs);
+}
+
+template <class T>
+__device__ void low_contrib(const SolveArgs& a, const T* arena, const SLow& Lw, int m, int nrhs, double* r,
+                            double* As, double* Bs) {
+  const STprod tp = a.tprod[Lw.tp];
+  const int k = a.dims[tp.slot];
+  const double* Tb = a.tbuf + tp.toff * a.max_rhs;
+  mm_sub<T>(arena + Lw.xoff, Lw.ldx, Tb, 1, tp.cap, m, k, nrhs, r, As, Bs);
+}
+
+constexpr int kMaxContrib = 256;   // contributions per leaf task checked for early readiness
+
+template <class T>
+__device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward, double* acc,
+                         int* ready, double* As, double* Bs) {
+  const SLeaf lf = a.leaves[s];
+  const int m = lf.m, nrhs = a.nrhs;
+  const int ldacc = a.max_rhs;
+  const int flag_base = forward ? 0 : a.L;
+  if (!forward) {
+    // the backward sweep overwrites y in place: wait for every forward task
+    wait_one(a, a.ctr + 1, a.n_fwd);
+  }
+  // outputs (i, c) owned by fixed threads; partial sums in registers
+  constexpr int kPer = 16;   // m * nrhs <= 128 * 32 = 16 * 256
+  double r[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * kSolveThreads;
+    r[q] = (o < m * nrhs) ? cload(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N) : 0.0;
+  }
+  // pass 1: contributions whose inputs are already complete
+  const int nc = lf.nd + lf.nl;
+  for (int t = threadIdx.x; t < nc && t < kMaxContrib; t += blockDim.x) {
+    bool ok = true;
+    if (t < lf.nd) {
+      const SDense D = a.dense[lf.d0 + t];
+      for (int f = D.lf0; f < D.lf1 && ok; ++f) ok = load_relaxed(a.leaf_flag + flag_base + f) == a.epoch;
+    } else {
+      ok = load_relaxed(a.tp_flag + a.low[lf.l0 + t - lf.nd].tp) == a.epoch;
+    }
+    ready[t] = ok ? 1 : 0;
+  }
+  acquire_all();
+  for (int t = 0; t < nc; ++t) {
+    if (t < kMaxContrib && ready[t]) {
+      if (t < lf.nd) dense_contrib<T>(a, arena, a.dense[lf.d0 + t], m, nrhs, r, As, Bs);
+      else low_contrib<T>(a, arena, a.low[lf.l0 + t - lf.nd], m, nrhs, r, As, Bs);
+    }
+  }
+  // pass 2: wait for the rest
+  for (int t = 0; t < nc; ++t) {
+    if (t < kMaxContrib && ready[t]) continue;
+    if (t < lf.nd) {
+      const SDense D = a.dense[lf.d0 + t];
+      wait_leaves(a, flag_base, D.lf0, D.lf1);
+      dense_contrib<T>(a, arena, D, m, nrhs, r, As, Bs);
+    } else {
+      const SLow Lw = a.low[lf.l0 + t - lf.nd];
+      wait_one(a, a.tp_flag + Lw.tp, a.epoch);
+      low_contrib<T>(a, arena, Lw, m, nrhs, r, As, Bs);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * kSolveThreads;
+    if (o < m * nrhs) acc[(o % m) * ldacc + o / m] = r[q];
+  }
+  // stage the diagonal leaf in the A buffer when it fits (m <= 90)
+  if (m * m <= 128 * kKC) {
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) As[e] = double(arena[lf.diag + e]);
+    __syncthreads();
+    leaf_triangular<double>(As, m, forward, acc, ldacc, nrhs);
+  } else {
+    leaf_triangular<T>(arena + lf.diag, m, forward, acc, ldacc, nrhs);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < m * nrhs; o += blockDim.x)
+    cstore(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N, acc[(o % m) * ldacc + o / m]);
+  publish(a.leaf_flag + s, a.epoch);
+}
+
+// T = Y^T y[cols] (k x nrhs): one output per thread for short blocks, a
+// row-split reduction through LDS for long ones.
+template <class T>
+__device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forward, double* As, double* Bs) {
+  const STprod tp = a.tprod[tpi];
+  wait_leaves(a, forward ? 0 : a.L, tp.lf0, tp.lf1);
+  const int k = a.dims[tp.slot];
+  const int nrhs = a.nrhs;
+  double* Tb = a.tbuf + tp.toff * a.max_rhs;
+  const T* Y = arena + tp.yoff;
+  const int nout = k * nrhs;     // <= 64 * 32 = 8 * 256
+  double s[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s[q] = 0.0;
+  for (int r0 = 0; r0 < tp.ncols; r0 += kKC) {
+    const int rc = min(kKC, tp.ncols - r0);
+    for (int e = threadIdx.x; e < rc * k; e += blockDim.x) {
+      const int r = e % rc, kk = e / rc;
+      As[kk * kKC + r] = double(Y[r0 + r + (int64_t)kk * tp.ldy]);
+    }
+    for (int e = threadIdx.x; e < rc * nrhs; e += blockDim.x) {
+      const int r = e % rc, c = e / rc;
+      Bs[c * kKC + r] = cload(a.y + tp.col0 + r0 + r + (int64_t)c * a.N);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int o = threadIdx.x + q * kSolveThreads;
+      if (o < nout) {
+        const int kk = o % k, c = o / k;
+        double sum = 0.0;
+        for (int r = 0; r < rc; ++r) sum += As[kk * kKC + r] * Bs[c * kKC + r];
+        s[q] += sum;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int o = threadIdx.x + q * kSolveThreads;
+    if (o < nout) cstore(Tb + (o % k) + (o / k) * tp.cap, s[q]);
+  }
+  publish(a.tp_flag + tpi, a.epoch);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T* arena, SolveArgs a) {
+  // LDS: acc (128 x 32 doubles), A staging (128 x kKC doubles), B staging
+  // (32 x kKC doubles): 112 KB
+  extern __shared__ double smem[];
+  __shared__ int s_task;
+  __shared__ int ready[kMaxContrib];
+  double* acc = smem;
+  double* As = acc + 128 * 32;
+  double* Bs = As + 128 * kKC;
+  while (true) {
+    if (threadIdx.x == 0) s_task = atomicAdd(a.ctr, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= a.ntasks) break;
+    const STask task = a.tasks[t];
+    switch (task.kind) {
+      case kFwdLeaf: run_leaf<T>(a, arena, task.idx, true, acc, ready, As, Bs); break;
+      case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
+      case kBwdLeaf: run_leaf<T>(a, arena, task.idx, false, acc, ready, As, Bs); break;
+      case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
+    }
+    if (task.kind == kFwdLeaf || task.kind == kFwdTprod) {
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(a.ctr + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void solve_reset_kernel(int32_t* ctr) {
+  if (threadIdx.x < 2) ctr[threadIdx.x] = 0;
+}
+
+}  // namespace dev
+
+struct SolveDev {
+  const STask* tasks;
+  const SLeaf* leaves;
+  const SDense* dense;
+  const SLow* low;
+  const STprod* tprod;
+  double* y;
+  double* tbuf;
+  int32_t* leaf_flag;
+  int32_t* tp_flag;
+  int32_t* ctr;
+  int32_t ntasks, n_fwd, L, max_m, max_rhs;
+};
+
+template <class T>
+hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const SolveDev& d, int32_t N,
+                                   int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s) {
+  dev::solve_reset_kernel<<<1, 64, 0, s>>>(d.ctr);
+  dev::SolveArgs a{d.tasks, d.leaves, d.dense, d.low, d.tprod, dims, d.y, d.tbuf, d.leaf_flag, d.tp_flag,
+                   d.ctr, d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch};
+  // acc 128 x 32, A staging 128 x kKC (also the diagonal leaf), B staging 32 x kKC
+  const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::solve_persistent_kernel<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    attr = true;
+  }
+  dev::solve_persistent_kernel<T><<<grid, dev::kSolveThreads, sh, s>>>(arena, a);
+  return hipGetLastError();
+}
+
+template hipError_t solve_persistent_launch<float>(const float*, const int32_t*, const SolveDev&, int32_t, int32_t,
+                                                   int32_t, int32_t, hipStream_t);
+template hipError_t solve_persistent_launch<double>(const double*, const int32_t*, const SolveDev&, int32_t,
+                                                    int32_t, int32_t, int32_t, hipStream_t);
+
+}  // namespace hlu
