@@ -586,10 +586,7 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     h->factored = false;
     h->prec = o->prec;
     h->eps = o->eps;
-    {
-      const char* e = getenv("HLU_DEBUG_FACTOR_COMPUTE64");
-      h->factor_compute64 = (o->prec == HLU_FP64) || (e && e[0] == '1');
-    }
+    h->factor_compute64 = (o->prec == HLU_FP64);
     if (o->prec == HLU_FP32) factor_impl<float>(h, s);
     else factor_impl<double>(h, s);
     HIP_OK(hipStreamSynchronize(s));

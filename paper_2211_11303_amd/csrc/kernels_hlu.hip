@@ -241,16 +241,17 @@ __global__ void fill_kernel(T* arena, const FillOp* ops, const int32_t* dims) {
 
 // --------------------------------------------------------------- TRUNC
 // Truncated low-rank addition C <- C + sum_p alpha_p X_p Y_p^T, one
-// workgroup per task.  With Xa = [X_C, parts], Ya = [Y_C, parts] (K columns):
-//   G = Xa^T Xa = V diag(lambda) V^T                 (Jacobi, LDS)
-//   S = diag(s) V^T (Ya^T Ya) V diag(s), s = sqrt(lambda)
-//     = W diag(sigma^2) W^T                          (Jacobi, LDS)
-// sigma are the singular values of Xa Ya^T.  Keep the r leading ones with
-// sigma_i > max(eps, floor) sigma_1, r <= capacity, and write
-//   X_C = Xa V diag(1/s) W_r,  Y_C = Ya V diag(s) W_r,
-// so X_C Y_C^T is the best rank-r approximation of Xa Ya^T.  More than
-// kKMax columns are absorbed in chunks, truncating after each chunk.
-constexpr int kKMax = 78;   // three (kKMax x kKMax+1) FP64 buffers fit the 160 KB LDS
+// workgroup per task.  With Xa = [X_C, parts], Ya = [Y_C, parts] (K
+// columns), the singular values of Xa Ya^T are found as follows (all FP64):
+//   Gx = Xa^T Xa = R^T R        pivoted Cholesky, numerical rank r1
+//                               (Xa P_1..r1 = Q R11 with Q orthonormal)
+//   S  = R (Ya^T Ya) R^T = W diag(sigma^2) W^T     cyclic Jacobi, LDS
+// Keeping the r leading triplets with sigma_i > max(eps, floor) sigma_1
+// (r <= capacity) gives the best rank-r approximation Q W_r W_r^T R Ya^T:
+//   X_C = Xa T_x,  T_x = P_1..r1 R11^{-1} W_r   (orthonormal columns)
+//   Y_C = Ya T_y,  T_y = R^T W_r                (norms sigma_i)
+// More than kKMax columns are absorbed in chunks, truncating after each.
+constexpr int kKMax = 64;
 constexpr int kLd = kKMax + 1;
 
 struct ColSrc {
@@ -262,8 +263,7 @@ struct ColSrc {
 };
 
 template <class T>
-__device__ void load_tile(const T* arena, const ColSrc* src, int K, int i0, int RT, int mrows,
-                          double* tile) {
+__device__ void load_tile(const T* arena, const ColSrc* src, int K, int i0, int RT, int mrows, double* tile) {
   // tile[i * kLd + a] = column a, row i0 + i
   for (int e = threadIdx.x; e < RT * K; e += blockDim.x) {
     const int a = e / RT, i = e % RT;
@@ -278,67 +278,130 @@ __device__ void load_tile(const T* arena, const ColSrc* src, int K, int i0, int 
   }
 }
 
-// Gram matrix of the K source columns over mrows rows into G (K x K, ld kLd),
-// staging row tiles in stage (at least kKMax * kLd doubles).
+// G = A^T A for the K source columns over mrows rows (G: K x K, ld kLd).
+// Each thread owns a 4 x 4 block of G (16 x 16 blocks cover K <= 64); row
+// tiles of kKMax rows are staged in `stage`.
 template <class T>
 __device__ void gram(const T* arena, const ColSrc* src, int K, int mrows, double* G, double* stage) {
-  const int RT = kKMax;
-  const int npairs = K * (K + 1) / 2;
-  // each thread owns pairs e = tid, tid + 256, ...  (at most 13 for K <= 80)
-  double acc[14];
+  const int bi = threadIdx.x / 16, bj = threadIdx.x % 16;
+  double acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 14; ++q) acc[q] = 0.0;
-  for (int i0 = 0; i0 < mrows; i0 += RT) {
-    load_tile(arena, src, K, i0, RT, mrows, stage);
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  const bool active = 4 * bi < K && 4 * bj < K;
+  for (int i0 = 0; i0 < mrows; i0 += kKMax) {
+    load_tile(arena, src, K, i0, kKMax, mrows, stage);
     __syncthreads();
-    const int rt = min(RT, mrows - i0);
+    const int rt = min(kKMax, mrows - i0);
+    if (active) {
+      for (int i = 0; i < rt; ++i) {
+        double x[4], y[4];
 #pragma unroll
-    for (int q = 0; q < 14; ++q) {
-      const int e = threadIdx.x + q * 256;
-      if (e < npairs) {
-        // map e -> (a, b), a <= b
-        int a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((a + 1) * (a + 2) / 2 <= e) ++a;
-        while (a * (a + 1) / 2 > e) --a;
-        const int b = e - a * (a + 1) / 2;   // b <= a
-        double s = 0.0;
-        for (int i = 0; i < rt; ++i) s += stage[i * kLd + a] * stage[i * kLd + b];
-        acc[q] += s;
+        for (int a = 0; a < 4; ++a) {
+          x[a] = (4 * bi + a < K) ? stage[i * kLd + 4 * bi + a] : 0.0;
+          y[a] = (4 * bj + a < K) ? stage[i * kLd + 4 * bj + a] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 14; ++q) {
-    const int e = threadIdx.x + q * 256;
-    if (e < npairs) {
-      int a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while ((a + 1) * (a + 2) / 2 <= e) ++a;
-      while (a * (a + 1) / 2 > e) --a;
-      const int b = e - a * (a + 1) / 2;
-      G[a * kLd + b] = acc[q];
-      G[b * kLd + a] = acc[q];
-    }
-  }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (4 * bi + a < K && 4 * bj + b < K) G[(4 * bi + a) * kLd + 4 * bj + b] = acc[a][b];
   __syncthreads();
 }
 
-// Cyclic parallel Jacobi on the symmetric K x K matrix A (ld kLd, LDS).
-// Rotations are also applied to the columns of U1 (and U2 if not null).
-// Round-robin pairing: K is padded to an even Kp with inert indices.
-__device__ void jacobi_eig(double* A, int K, double* U1, double* U2, double* cs_buf, double* red) {
-  const int Kp = K + (K & 1);
-  const int npair = Kp / 2;
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence test: off-diagonal vs total Frobenius norm
-    double off = 0.0, tot = 0.0;
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int i = e / K, j = e % K;
-      const double v = A[i * kLd + j];
-      tot += v * v;
-      if (i != j) off += v * v;
+// Pivoted Cholesky of the symmetric positive semidefinite G (K x K, ld
+// kLd), whose content is overwritten by Schur complements.  Row k < r1 of R
+// (ld kLd) receives R[k][:] in the original column order (zero in columns
+// chosen earlier), piv[k] the k-th pivot; stops when the largest remaining
+// diagonal is <= tol2 times the largest initial one.  Returns r1.
+__device__ int pivoted_cholesky(double* G, double* R, int K, double tol2, int* piv, double* d, int* chosen,
+                                int* s_int, double* s_dbl) {
+  for (int j = threadIdx.x; j < K; j += blockDim.x) {
+    d[j] = G[j * kLd + j];
+    chosen[j] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double dm = 0.0;
+    for (int j = 0; j < K; ++j) dm = fmax(dm, d[j]);
+    s_dbl[0] = dm;
+  }
+  __syncthreads();
+  const double dmax0 = s_dbl[0];
+  int r1 = 0;
+  for (int k = 0; k < K; ++k) {
+    if (threadIdx.x < 64) {   // argmax of the unchosen diagonal, lowest index on ties
+      double best = -1.0;
+      int bidx = K;
+      for (int j = threadIdx.x; j < K; j += 64)
+        if (!chosen[j] && d[j] > best) {
+          best = d[j];
+          bidx = j;
+        }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bidx, o, 64);
+        if (ob > best || (ob == best && oi < bidx)) {
+          best = ob;
+          bidx = oi;
+        }
+      }
+      if (threadIdx.x == 0) {
+        s_int[0] = (bidx < K && best > 0.0 && best > tol2 * dmax0) ? bidx : -1;
+        s_dbl[1] = best;
+      }
     }
-    // block reduction
+    __syncthreads();
+    const int p = s_int[0];
+    if (p < 0) break;
+    const double rkk = sqrt(s_dbl[1]);
+    for (int j = threadIdx.x; j < K; j += blockDim.x)
+      R[k * kLd + j] = (j == p) ? rkk : (chosen[j] ? 0.0 : G[p * kLd + j] / rkk);
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int a = e / K, b = e % K;
+      if (!chosen[a] && !chosen[b] && a != p && b != p) G[a * kLd + b] -= R[k * kLd + a] * R[k * kLd + b];
+    }
+    for (int j = threadIdx.x; j < K; j += blockDim.x)
+      if (!chosen[j] && j != p) d[j] -= R[k * kLd + j] * R[k * kLd + j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      chosen[p] = 1;
+      piv[k] = p;
+    }
+    __syncthreads();
+    r1 = k + 1;
+  }
+  return r1;
+}
+
+// Cyclic Jacobi on the symmetric n x n matrix A (ld kLd).  Each round pairs
+// the indices round-robin; the rotations of the n/2 disjoint pairs are
+// computed first, then A' = J^T A J is written to B (double buffering) and
+// W <- W J.  Returns the buffer that holds the final A.
+__device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, int* pk, int* pfirst,
+                          double* red) {
+  const int np = n + (n & 1);
+  const int npair = np / 2;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) W[(e / n) * kLd + e % n] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+  if (n <= 1) return A;
+  for (int sweep = 0; sweep < 20; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const double v = A[(e / n) * kLd + e % n];
+      tot += v * v;
+      if (e / n != e % n) off += v * v;
+    }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_down(off, o, 64);
       tot += __shfl_down(tot, o, 64);
@@ -352,16 +415,15 @@ __device__ void jacobi_eig(double* A, int K, double* U1, double* U2, double* cs_
     const double tots = red[4] + red[5] + red[6] + red[7];
     __syncthreads();
     if (tots == 0.0 || offs <= 1e-26 * tots) break;
-    for (int r = 0; r < Kp - 1; ++r) {
-      // rotation parameters for the pairs of this round
+    for (int r = 0; r < np - 1; ++r) {
       for (int k = threadIdx.x; k < npair; k += blockDim.x) {
         int p, q;
         if (k == 0) {
-          p = Kp - 1;
+          p = np - 1;
           q = r;
         } else {
-          p = (r + k) % (Kp - 1);
-          q = (r - k + Kp - 1) % (Kp - 1);
+          p = (r + k) % (np - 1);
+          q = (r - k + np - 1) % (np - 1);
         }
         if (p > q) {
           const int t = p;
@@ -369,71 +431,88 @@ __device__ void jacobi_eig(double* A, int K, double* U1, double* U2, double* cs_
           q = t;
         }
         double c = 1.0, s = 0.0;
-        if (q < K) {
+        if (q < n) {
           const double apq = A[p * kLd + q];
           const double app = A[p * kLd + p], aqq = A[q * kLd + q];
-          if (fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)) && apq != 0.0) {
-            const double th = (A[q * kLd + q] - A[p * kLd + p]) / (2.0 * apq);
+          if (apq != 0.0 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+            const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
           }
+          pk[p] = k;
+          pk[q] = k;
+          pfirst[p] = 1;
+          pfirst[q] = 0;
+          cs[4 * k + 2] = p;
+          cs[4 * k + 3] = q;
+        } else {
+          pk[p] = -1;   // unpaired index (odd n): untouched this round
         }
-        cs_buf[4 * k + 0] = c;
-        cs_buf[4 * k + 1] = s;
-        cs_buf[4 * k + 2] = p;
-        cs_buf[4 * k + 3] = q;
+        cs[4 * k] = c;
+        cs[4 * k + 1] = s;
       }
       __syncthreads();
-      // columns of A
-      for (int e = threadIdx.x; e < npair * K; e += blockDim.x) {
-        const int k = e / K, row = e % K;
-        const int p = (int)cs_buf[4 * k + 2], q = (int)cs_buf[4 * k + 3];
-        if (q >= K) continue;
-        const double c = cs_buf[4 * k], s = cs_buf[4 * k + 1];
-        const double ap = A[row * kLd + p], aq = A[row * kLd + q];
-        A[row * kLd + p] = c * ap - s * aq;
-        A[row * kLd + q] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // rows of A, and columns of U1/U2
-      for (int e = threadIdx.x; e < npair * K; e += blockDim.x) {
-        const int k = e / K, col = e % K;
-        const int p = (int)cs_buf[4 * k + 2], q = (int)cs_buf[4 * k + 3];
-        if (q >= K) continue;
-        const double c = cs_buf[4 * k], s = cs_buf[4 * k + 1];
-        const double ap = A[p * kLd + col], aq = A[q * kLd + col];
-        A[p * kLd + col] = c * ap - s * aq;
-        A[q * kLd + col] = s * ap + c * aq;
-        const double u1p = U1[col * kLd + p], u1q = U1[col * kLd + q];
-        U1[col * kLd + p] = c * u1p - s * u1q;
-        U1[col * kLd + q] = s * u1p + c * u1q;
-        if (U2) {
-          const double u2p = U2[col * kLd + p], u2q = U2[col * kLd + q];
-          U2[col * kLd + p] = c * u2p - s * u2q;
-          U2[col * kLd + q] = s * u2p + c * u2q;
+      // B[i][j] = sum_{a in pair(i)} sum_{b in pair(j)} t_i[a] t_j[b] A[a][b],
+      // with t = (c, -s) on (p, q) for the first index of a pair, (s, c) for the second
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        const int ki = pk[i], kj = pk[j];
+        int ia = i, ib = i, ja = j, jb = j;
+        double ti0 = 1.0, ti1 = 0.0, tj0 = 1.0, tj1 = 0.0;
+        if (ki >= 0) {
+          ia = (int)cs[4 * ki + 2];
+          ib = (int)cs[4 * ki + 3];
+          const double c = cs[4 * ki], s = cs[4 * ki + 1];
+          if (pfirst[i]) { ti0 = c; ti1 = -s; } else { ti0 = s; ti1 = c; }
         }
+        if (kj >= 0) {
+          ja = (int)cs[4 * kj + 2];
+          jb = (int)cs[4 * kj + 3];
+          const double c = cs[4 * kj], s = cs[4 * kj + 1];
+          if (pfirst[j]) { tj0 = c; tj1 = -s; } else { tj0 = s; tj1 = c; }
+        }
+        double v = ti0 * (tj0 * A[ia * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ia * kLd + jb] : 0.0));
+        if (ti1 != 0.0) v += ti1 * (tj0 * A[ib * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ib * kLd + jb] : 0.0));
+        B[i * kLd + j] = v;
+      }
+      for (int e = threadIdx.x; e < n * npair; e += blockDim.x) {
+        const int row = e / npair, k = e % npair;
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+        if (cs[4 * k] == 1.0 && cs[4 * k + 1] == 0.0) continue;
+        const double c = cs[4 * k], s = cs[4 * k + 1];
+        const double wp = W[row * kLd + p], wq = W[row * kLd + q];
+        W[row * kLd + p] = c * wp - s * wq;
+        W[row * kLd + q] = s * wp + c * wq;
       }
       __syncthreads();
+      double* t = A;
+      A = B;
+      B = t;
     }
   }
+  return A;
 }
 
 template <class T>
 __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops, const TruncPart* parts,
                                                     int32_t* dims, double eps, double floor_rel,
                                                     int32_t* status) {
-  __shared__ double bufA[kKMax * kLd];
-  __shared__ double bufB[kKMax * kLd];
-  __shared__ double bufC[kKMax * kLd];
+  __shared__ double bufG[kKMax * kLd];
+  __shared__ double bufR[kKMax * kLd];
+  __shared__ double bufS[kKMax * kLd];
+  __shared__ double bufW[kKMax * kLd];
   __shared__ ColSrc xs[kKMax], ys[kKMax];
-  __shared__ double lam[kKMax], sq[kKMax], mu[kKMax];
-  __shared__ double cs_buf[4 * (kKMax / 2 + 1)];
+  __shared__ double dvec[kKMax], mu[kKMax], dscale[kKMax], dinv[kKMax];
+  __shared__ double cs[4 * (kKMax / 2 + 1)];
+  __shared__ double s_dbl[4];
   __shared__ double red[8];
-  __shared__ int sel[kKMax];
-  __shared__ int s_K, s_r, s_part, s_pcol, s_done;
+  __shared__ int piv[kKMax], chosen[kKMax], sel[kKMax], pk[kKMax], pfirst[kKMax];
+  __shared__ int s_int[4];
+  __shared__ int s_K, s_r, s_r1, s_part, s_pcol, s_done;
 
   const TruncOp op = ops[blockIdx.x];
+  const double tol2 = floor_rel * floor_rel;
   if (threadIdx.x == 0) {
     s_r = dims[op.slot];
     s_part = 0;
@@ -441,7 +520,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   }
   __syncthreads();
   while (true) {
-    // assemble the column list: current C columns, then up to kKMax - r part columns
+    // column list: current C columns, then up to kKMax - r part columns
     if (threadIdx.x == 0) {
       int K = 0;
       const int r = s_r;
@@ -464,7 +543,6 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         ++K;
         ++c;
       }
-      // skip exhausted parts
       while (p < op.np && c >= dimv(parts[op.p0 + p].X.cols, dims)) {
         ++p;
         c = 0;
@@ -481,92 +559,122 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       __syncthreads();
       break;
     }
-    // (1) G = Xa^T Xa -> A ; V -> B
-    gram(arena, xs, K, op.m, bufA, bufC);
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int i = e / K, j = e % K;
-      bufB[i * kLd + j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    jacobi_eig(bufA, K, bufB, nullptr, cs_buf, red);
-    if (threadIdx.x == 0) {
-      double lmax = 0.0;
-      for (int a = 0; a < K; ++a) lmax = fmax(lmax, bufA[a * kLd + a]);
-      for (int a = 0; a < K; ++a) {
-        const double l = bufA[a * kLd + a];
-        lam[a] = l;
-        sq[a] = (l > 1e-15 * K * lmax && l > 0.0) ? sqrt(l) : 0.0;
-      }
-    }
-    __syncthreads();
-    // (2) Gy -> A, C = Gy V, A = V^T C, scaled by sq
-    gram(arena, ys, K, op.n, bufA, bufC);
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int i = e / K, j = e % K;
-      double s = 0.0;
-      for (int c = 0; c < K; ++c) s += bufA[i * kLd + c] * bufB[c * kLd + j];
-      bufC[i * kLd + j] = s;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int i = e / K, j = e % K;
-      double s = 0.0;
-      for (int c = 0; c < K; ++c) s += bufB[c * kLd + i] * bufC[c * kLd + j];
-      bufA[i * kLd + j] = sq[i] * s * sq[j];
-    }
-    __syncthreads();
-    // (3) U1 = V diag(1/s) -> C, U2 = V diag(s) -> B (in place)
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int i = e / K, j = e % K;
-      const double v = bufB[i * kLd + j];
-      bufC[i * kLd + j] = sq[j] > 0.0 ? v / sq[j] : 0.0;
-      bufB[i * kLd + j] = v * sq[j];
-    }
-    __syncthreads();
-    jacobi_eig(bufA, K, bufC, bufB, cs_buf, red);
-    // (4) order the eigenvalues of S, choose the rank
-    for (int a = threadIdx.x; a < K; a += blockDim.x) mu[a] = fmax(bufA[a * kLd + a], 0.0);
-    __syncthreads();
+    // (1) Gy -> S buffer, Gx -> G buffer; balance every column pair so that
+    // |x_a| = |y_a| (x_a y_a^T unchanged), then pivoted Cholesky of Gx -> R
+    gram(arena, ys, K, op.n, bufS, bufG);
+    gram(arena, xs, K, op.m, bufG, bufR);
     for (int a = threadIdx.x; a < K; a += blockDim.x) {
-      int rank = 0;
-      for (int b = 0; b < K; ++b)
-        if (mu[b] > mu[a] || (mu[b] == mu[a] && b < a)) ++rank;
-      sel[rank] = a;
+      const double gx = bufG[a * kLd + a], gy = bufS[a * kLd + a];
+      const bool nz = gx > 0.0 && gy > 0.0;
+      dscale[a] = nz ? sqrt(sqrt(gy / gx)) : 0.0;
+      dinv[a] = nz ? 1.0 / dscale[a] : 0.0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      const double s1 = sqrt(mu[sel[0]]);
-      const double thr = fmax(eps, floor_rel) * s1;
-      int cnt = 0;
-      for (int a = 0; a < K; ++a)
-        if (sqrt(mu[sel[a]]) > thr) ++cnt;
-      if (s1 == 0.0) cnt = 0;
-      int r = cnt < op.cap ? cnt : op.cap;
-      if (cnt > op.cap) atomicAdd(&status[1], 1);
-      s_r = r;
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int a = e / K, b = e % K;
+      bufG[a * kLd + b] *= dscale[a] * dscale[b];
+      bufS[a * kLd + b] *= dinv[a] * dinv[b];
     }
     __syncthreads();
-    const int rnew = s_r;
-    // (5) X_C = Xa U1[:, sel], Y_C = Ya U2[:, sel], row tiles staged in A
-    for (int pass = 0; pass < 2; ++pass) {
-      const ColSrc* src = pass == 0 ? xs : ys;
-      const int mrows = pass == 0 ? op.m : op.n;
-      const double* U = pass == 0 ? bufC : bufB;
-      const int64_t out = pass == 0 ? op.xoff : op.yoff;
-      const int ldo = pass == 0 ? op.ldx : op.ldy;
-      for (int i0 = 0; i0 < mrows; i0 += kKMax) {
-        load_tile(arena, src, K, i0, kKMax, mrows, bufA);
-        __syncthreads();
-        const int rt = min(kKMax, mrows - i0);
-        for (int e = threadIdx.x; e < rt * rnew; e += blockDim.x) {
-          const int i = e % rt, j = e / rt;
-          const int col = sel[j];
-          double s = 0.0;
-          for (int a = 0; a < K; ++a) s += bufA[i * kLd + a] * U[a * kLd + col];
-          arena[out + (i0 + i) + (int64_t)j * ldo] = T(s);
-        }
-        __syncthreads();
+    const int r1c = pivoted_cholesky(bufG, bufR, K, tol2, piv, dvec, chosen, s_int, s_dbl);
+    if (threadIdx.x == 0) s_r1 = r1c;
+    __syncthreads();
+    const int r1 = s_r1;
+    int rnew = 0;
+    if (r1 > 0) {
+      // (2) T1 = Gy R^T -> G buffer; S = R T1 -> S buffer
+      for (int e = threadIdx.x; e < K * r1; e += blockDim.x) {
+        const int a = e / r1, k = e % r1;
+        double acc = 0.0;
+        for (int b = 0; b < K; ++b) acc += bufS[a * kLd + b] * bufR[k * kLd + b];
+        bufG[a * kLd + k] = acc;
       }
+      __syncthreads();
+      for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) {
+        const int k = e / r1, l = e % r1;
+        double acc = 0.0;
+        for (int a = 0; a < K; ++a) acc += bufR[k * kLd + a] * bufG[a * kLd + l];
+        bufS[k * kLd + l] = acc;
+      }
+      __syncthreads();
+      // symmetrise against rounding
+      for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) {
+        const int k = e / r1, l = e % r1;
+        if (k < l) {
+          const double v = 0.5 * (bufS[k * kLd + l] + bufS[l * kLd + k]);
+          bufS[k * kLd + l] = v;
+          bufS[l * kLd + k] = v;
+        }
+      }
+      __syncthreads();
+      // (3) eigen-decomposition of S
+      double* Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red);
+      double* Free = (Sres == bufS) ? bufG : bufS;
+      for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = fmax(Sres[k * kLd + k], 0.0);
+      __syncthreads();
+      for (int k = threadIdx.x; k < r1; k += blockDim.x) {
+        int rank = 0;
+        for (int l = 0; l < r1; ++l)
+          if (mu[l] > mu[k] || (mu[l] == mu[k] && l < k)) ++rank;
+        sel[rank] = k;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const double s1 = sqrt(mu[sel[0]]);
+        const double thr = fmax(eps, floor_rel) * s1;
+        int cnt = 0;
+        for (int k = 0; k < r1; ++k)
+          if (sqrt(mu[sel[k]]) > thr) ++cnt;
+        if (s1 == 0.0) cnt = 0;
+        const int r = cnt < op.cap ? cnt : op.cap;
+        if (cnt > op.cap) atomicAdd(&status[1], 1);
+        s_r = r;
+      }
+      __syncthreads();
+      rnew = s_r;
+      // (4) Z = R11^{-1} W_r (r1 x rnew) -> Free ; Ty = R^T W_r (K x rnew) -> Sres
+      for (int c = threadIdx.x; c < rnew; c += blockDim.x) {
+        const int ev = sel[c];
+        for (int k = r1 - 1; k >= 0; --k) {
+          double v = bufW[k * kLd + ev];
+          for (int l = k + 1; l < r1; ++l) v -= bufR[k * kLd + piv[l]] * Free[l * kLd + c];
+          Free[k * kLd + c] = v / bufR[k * kLd + piv[k]];
+        }
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < K * rnew; e += blockDim.x) {
+        const int a = e / rnew, c = e % rnew;
+        const int ev = sel[c];
+        double v = 0.0;
+        for (int k = 0; k < r1; ++k) v += bufR[k * kLd + a] * bufW[k * kLd + ev];
+        Sres[a * kLd + c] = v;
+      }
+      __syncthreads();
+      // (5) X_C = Xa[:, piv] Z ; Y_C = Ya Ty (row tiles staged in the R buffer)
+      for (int pass = 0; pass < 2; ++pass) {
+        const ColSrc* src = pass == 0 ? xs : ys;
+        const int mrows = pass == 0 ? op.m : op.n;
+        const int64_t out = pass == 0 ? op.xoff : op.yoff;
+        const int ldo = pass == 0 ? op.ldx : op.ldy;
+        for (int i0 = 0; i0 < mrows; i0 += kKMax) {
+          load_tile(arena, src, K, i0, kKMax, mrows, bufR);
+          __syncthreads();
+          const int rt = min(kKMax, mrows - i0);
+          for (int e = threadIdx.x; e < rt * rnew; e += blockDim.x) {
+            const int i = e % rt, c = e / rt;
+            double v = 0.0;
+            if (pass == 0) {
+              for (int k = 0; k < r1; ++k) v += bufR[i * kLd + piv[k]] * dscale[piv[k]] * Free[k * kLd + c];
+            } else {
+              for (int a = 0; a < K; ++a) v += bufR[i * kLd + a] * dinv[a] * Sres[a * kLd + c];
+            }
+            arena[out + (i0 + i) + (int64_t)c * ldo] = T(v);
+          }
+          __syncthreads();
+        }
+      }
+    } else if (threadIdx.x == 0) {
+      s_r = 0;
     }
     __syncthreads();
     if (s_done) break;
