@@ -70,6 +70,12 @@ struct SolveDev {
   int32_t* leaf_flag;
   int32_t* tp_flag;
   int32_t* ctr;
+  const int32_t* push0;
+  const int32_t* push_recs;
+  double* pbuf;
+  int32_t* pflag;
+  int64_t pstride;
+  int64_t* trace;
   int32_t ntasks, n_fwd, L, max_m, max_rhs;
 };
 template <class T>
@@ -276,15 +282,25 @@ void ensure_device(hlu_s* h) {
     d.max_rhs = kMaxRhs;
     d.y = static_cast<double*>(keep(dmalloc<double>((size_t)h->S.N * kMaxRhs)));
     d.tbuf = static_cast<double*>(keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc->tbuf_per_rhs) * kMaxRhs)));
-    const size_t nflags = 2 * (size_t)sc->L + sc->tprod.size() + 1;
+    const size_t nflags = 2 * (size_t)sc->L + sc->tprod.size() + sc->dense.size() + 1;
     int32_t* flags = static_cast<int32_t*>(keep(dmalloc<int32_t>(nflags)));
     HIP_OK(hipMemset(flags, 0, nflags * sizeof(int32_t)));
     d.leaf_flag = flags;
     d.tp_flag = flags + 2 * sc->L;
+    d.pflag = flags + 2 * sc->L + sc->tprod.size();
+    d.push0 = static_cast<const int32_t*>(keep(upload(sc->push0)));
+    d.push_recs = static_cast<const int32_t*>(keep(upload(sc->push_recs)));
+    d.pstride = (int64_t)sc->max_m * kMaxRhs;
+    d.pbuf = static_cast<double*>(keep(dmalloc<double>(std::max<size_t>(1, sc->dense.size()) * (size_t)d.pstride)));
     d.ctr = static_cast<int32_t*>(keep(dmalloc<int32_t>(4)));
     HIP_OK(hipMemset(d.ctr, 0, 4 * sizeof(int32_t)));
     d.ntasks = (int32_t)sc->tasks.size();
     d.n_fwd = sc->n_fwd_tasks;
+    d.trace = nullptr;
+    if (const char* tr = getenv("HLU_DEBUG_SOLVE_TRACE")) {   // debug: per-task clocks
+      (void)tr;
+      d.trace = static_cast<int64_t*>(keep(dmalloc<int64_t>(4 * (size_t)d.ntasks)));
+    }
     d.L = sc->L;
     d.max_m = sc->max_m;
     h->solve_epoch = 0;
@@ -395,6 +411,19 @@ void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, i
     h->solve_epoch = h->solve_epoch % 1000000000 + 1;
     HIP_OK(solve_persistent_launch<T>(arena, dims, h->sdev, N, nc, h->solve_epoch, grid, s));
     HIP_OK(scatter_perm_launch<double>(N, nc, h->d_perm, h->sdev.y, N, x + (int64_t)c0 * ld, ld, s));
+    if (h->sdev.trace) {   // debug: dump task clocks and kinds
+      HIP_OK(hipStreamSynchronize(s));
+      const SolveSched& sc = *h->ssched;
+      std::vector<int64_t> tr(4 * (size_t)h->sdev.ntasks);
+      HIP_OK(hipMemcpy(tr.data(), h->sdev.trace, tr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+      if (FILE* f = fopen(getenv("HLU_DEBUG_SOLVE_TRACE"), "wb")) {
+        for (int32_t t = 0; t < h->sdev.ntasks; ++t) {
+          int64_t rec[6] = {sc.tasks[t].kind, sc.tasks[t].idx, tr[4 * t], tr[4 * t + 1], tr[4 * t + 2], tr[4 * t + 3]};
+          fwrite(rec, sizeof(rec), 1, f);
+        }
+        fclose(f);
+      }
+    }
   }
 }
 

@@ -33,7 +33,14 @@ struct SolveArgs {
   int32_t* leaf_flag;   // 2L flags
   int32_t* tp_flag;     // one per T-product
   int32_t* ctr;         // [0] claim counter, [1] finished forward tasks, [2] error
+  const int32_t* push0; // push task -> first record in push_recs
+  const int32_t* push_recs;
+  double* pbuf;         // partial-sum records, pstride doubles each (m x nrhs, ld m)
+  int32_t* pflag;       // one per record
+  int64_t pstride;
+  int64_t* trace;       // optional (debug): per task claim / start-of-compute / end clocks
   int32_t ntasks, n_fwd, N, nrhs, max_rhs, L, epoch;
+  int32_t cur_task;     // set per task (trace only)
 };
 
 // Data exchanged between tasks (y, T products) is written and read with
@@ -106,7 +113,8 @@ __device__ __forceinline__ double bcast(double v, int lane) {
 // unit lower (forward) or upper (backward) triangle of the diagonal leaf,
 // done by wavefront 0 in registers: lane l owns rows l and l + 64.
 template <class P>
-__device__ void leaf_triangular(const P* D, int m, bool forward, double* acc, int ldacc, int nrhs) {
+__device__ void leaf_triangular(const P* D, int m, bool forward, double* acc, int ldacc, int nrhs,
+                                const double* rdiag) {
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   for (int c0 = 0; c0 < nrhs; c0 += kMaxRhsTile) {
@@ -134,12 +142,12 @@ __device__ void leaf_triangular(const P* D, int m, bool forward, double* acc, in
       for (int q = m - 1; q >= 0; --q) {
         const int ql = q & 63;
         const bool hiq = q >= 64;
-        const double dq = double(D[q + (int64_t)q * m]);
+        const double rq = rdiag ? rdiag[q] : 1.0 / double(D[q + (int64_t)q * m]);
         const double u0 = lane < q ? double(D[lane + (int64_t)q * m]) : 0.0;
         const double u1 = (lane + 64 < q) ? double(D[lane + 64 + (int64_t)q * m]) : 0.0;
 #pragma unroll
         for (int c = 0; c < kMaxRhsTile; ++c) {
-          const double zq = bcast(hiq ? v1[c] : v0[c], ql) / dq;
+          const double zq = bcast(hiq ? v1[c] : v0[c], ql) * rq;
           if (lane == ql && !hiq) v0[c] = zq;
           if (lane == ql && hiq) v1[c] = zq;
           v0[c] -= u0 * zq;
@@ -162,7 +170,7 @@ constexpr int kKC = 64;
 // r[(i, c)] -= sum_k A[i, k] B[k, c] with A (m x K, type T, A[i + k*lda]) and
 // B (K x nrhs, FP64, B[k*bs + c*bcs]); both streamed through LDS in chunks of
 // kKC so that all loads of a chunk are in flight together.
-template <class T>
+template <class T, bool kBInLds = false>
 __device__ void mm_sub(const T* A, int64_t lda, const double* B, int64_t bs, int64_t bcs, int m, int K,
                        int nrhs, double* r, double* As, double* Bs) {
   for (int k0 = 0; k0 < K; k0 += kKC) {
@@ -173,7 +181,8 @@ __device__ void mm_sub(const T* A, int64_t lda, const double* B, int64_t bs, int
     }
     for (int e = threadIdx.x; e < kc * nrhs; e += blockDim.x) {
       const int k = e % kc, c = e / kc;
-      Bs[c * kKC + k] = cload(B + (int64_t)(k0 + k) * bs + (int64_t)c * bcs);
+      const double* bp = B + (int64_t)(k0 + k) * bs + (int64_t)c * bcs;
+      Bs[c * kKC + k] = kBInLds ? *bp : cload(bp);
     }
     __syncthreads();
 #pragma unroll
@@ -209,7 +218,7 @@ constexpr int kMaxContrib = 256;   // contributions per leaf task checked for ea
 
 template <class T>
 __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward, double* acc,
-                         int* ready, double* As, double* Bs) {
+                         int* ready, double* As, double* Bs, double* Dg, double* rdiag) {
   const SLeaf lf = a.leaves[s];
   const int m = lf.m, nrhs = a.nrhs;
   const int ldacc = a.max_rhs;
@@ -226,55 +235,134 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
     const int o = threadIdx.x + q * kSolveThreads;
     r[q] = (o < m * nrhs) ? cload(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N) : 0.0;
   }
-  // pass 1: contributions whose inputs are already complete
-  const int nc = lf.nd + lf.nl;
-  for (int t = threadIdx.x; t < nc && t < kMaxContrib; t += blockDim.x) {
-    bool ok = true;
-    if (t < lf.nd) {
-      const SDense D = a.dense[lf.d0 + t];
-      for (int f = D.lf0; f < D.lf1 && ok; ++f) ok = load_relaxed(a.leaf_flag + flag_base + f) == a.epoch;
-    } else {
-      ok = load_relaxed(a.tp_flag + a.low[lf.l0 + t - lf.nd].tp) == a.epoch;
-    }
-    ready[t] = ok ? 1 : 0;
-  }
+  // low-rank contributions: those whose T product is complete first, then
+  // wait for the rest
+  const int nl = lf.nl;
+  for (int t = threadIdx.x; t < nl && t < kMaxContrib; t += blockDim.x)
+    ready[t] = load_relaxed(a.tp_flag + a.low[lf.l0 + t].tp) == a.epoch ? 1 : 0;
   acquire_all();
-  for (int t = 0; t < nc; ++t) {
-    if (t < kMaxContrib && ready[t]) {
-      if (t < lf.nd) dense_contrib<T>(a, arena, a.dense[lf.d0 + t], m, nrhs, r, As, Bs);
-      else low_contrib<T>(a, arena, a.low[lf.l0 + t - lf.nd], m, nrhs, r, As, Bs);
+  for (int t = 0; t < nl; ++t)
+    if (t < kMaxContrib && ready[t]) low_contrib<T>(a, arena, a.low[lf.l0 + t], m, nrhs, r, As, Bs);
+  for (int t = 0; t < nl; ++t) {
+    if (t < kMaxContrib && ready[t]) continue;
+    const SLow Lw = a.low[lf.l0 + t];
+    wait_one(a, a.tp_flag + Lw.tp, a.epoch);
+    low_contrib<T>(a, arena, Lw, m, nrhs, r, As, Bs);
+  }
+  // stage factor data of the critical section before waiting on the
+  // preceding leaf: the diagonal leaf (with reciprocal pivots) and the
+  // neighbouring row's block multiplied after the solve
+  const bool diag_lds = m * m <= 64 * 64;
+  if (diag_lds) {
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) Dg[e] = double(arena[lf.diag + e]);
+  }
+  SDense Dn{};
+  const bool next_lds = lf.next_rec >= 0 && a.dense[lf.next_rec].m <= 128 && a.dense[lf.next_rec].ncols <= kKC;
+  if (lf.next_rec >= 0) Dn = a.dense[lf.next_rec];
+  if (next_lds) {
+    for (int e = threadIdx.x; e < Dn.m * Dn.ncols; e += blockDim.x) {
+      const int i = e % Dn.m, k = e / Dn.m;
+      As[k * 128 + i] = double(arena[Dn.off + i + (int64_t)k * Dn.ld]);
     }
   }
-  // pass 2: wait for the rest
-  for (int t = 0; t < nc; ++t) {
-    if (t < kMaxContrib && ready[t]) continue;
-    if (t < lf.nd) {
-      const SDense D = a.dense[lf.d0 + t];
-      wait_leaves(a, flag_base, D.lf0, D.lf1);
-      dense_contrib<T>(a, arena, D, m, nrhs, r, As, Bs);
-    } else {
-      const SLow Lw = a.low[lf.l0 + t - lf.nd];
-      wait_one(a, a.tp_flag + Lw.tp, a.epoch);
-      low_contrib<T>(a, arena, Lw, m, nrhs, r, As, Bs);
+  __syncthreads();
+  if (diag_lds)
+    for (int q = threadIdx.x; q < m; q += blockDim.x) rdiag[q] = 1.0 / Dg[q + q * m];
+  // dense contributions: wait for every partial-sum record of this row,
+  // then add them in record order
+  for (int t = threadIdx.x; t < lf.nd; t += blockDim.x) spin_eq(a.pflag + lf.d0 + t, a.epoch, a.ctr + 2);
+  acquire_all();
+  for (int t0 = 0; t0 < lf.nd; t0 += 4) {
+    // four records' loads in flight together
+    double v[4][kPer];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* P = a.pbuf + (int64_t)(lf.d0 + t0 + u) * a.pstride;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int o = threadIdx.x + q * kSolveThreads;
+        v[u][q] = (t0 + u < lf.nd && o < m * nrhs) ? cload(P + o) : 0.0;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) r[q] -= v[u][q];
   }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int o = threadIdx.x + q * kSolveThreads;
     if (o < m * nrhs) acc[(o % m) * ldacc + o / m] = r[q];
   }
-  // stage the diagonal leaf in the A buffer when it fits (m <= 90)
-  if (m * m <= 128 * kKC) {
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) As[e] = double(arena[lf.diag + e]);
-    __syncthreads();
-    leaf_triangular<double>(As, m, forward, acc, ldacc, nrhs);
-  } else {
-    leaf_triangular<T>(arena + lf.diag, m, forward, acc, ldacc, nrhs);
-  }
+  if (a.trace && threadIdx.x == 0) a.trace[4 * a.cur_task + 1] = (int64_t)wall_clock64();
+  // every wave wrote rows of acc; wavefront 0 reads all of them
+  __syncthreads();
+  if (diag_lds) leaf_triangular<double>(Dg, m, forward, acc, ldacc, nrhs, rdiag);
+  else leaf_triangular<T>(arena + lf.diag, m, forward, acc, ldacc, nrhs, nullptr);
   __syncthreads();
   for (int o = threadIdx.x; o < m * nrhs; o += blockDim.x)
     cstore(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N, acc[(o % m) * ldacc + o / m]);
+  if (lf.next_rec >= 0) {
+    // the neighbouring row's dense block times this solution row (both in LDS)
+    const SDense& D = Dn;
+    double pr[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) pr[q] = 0.0;
+    if (next_lds) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int o = threadIdx.x + q * kSolveThreads;
+        if (o < D.m * nrhs) {
+          const int i = o % D.m, c = o / D.m;
+          double sum = 0.0;
+          for (int k = 0; k < D.ncols; ++k) sum += As[k * 128 + i] * acc[k * ldacc + c];
+          pr[q] = sum;
+        }
+      }
+    } else {
+      mm_sub<T, true>(arena + D.off, D.ld, acc, ldacc, 1, D.m, D.ncols, nrhs, pr, As, Bs);
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) pr[q] = -pr[q];
+    }
+    double* P = a.pbuf + (int64_t)lf.next_rec * a.pstride;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int o = threadIdx.x + q * kSolveThreads;
+      if (o < D.m * nrhs) cstore(P + o, pr[q]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(a.pflag + lf.next_rec, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.leaf_flag + s, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   publish(a.leaf_flag + s, a.epoch);
+}
+
+// Partial-sum records of dense blocks whose column cluster this task's leaf
+// completes: P = D y[sigma] (m x nrhs).
+template <class T>
+__device__ void run_push(const SolveArgs& a, const T* arena, int id, bool forward, double* As, double* Bs) {
+  const int flag_base = forward ? 0 : a.L;
+  for (int q0 = a.push0[id]; q0 < a.push0[id + 1]; ++q0) {
+    const int rec = a.push_recs[q0];
+    const SDense D = a.dense[rec];
+    wait_leaves(a, flag_base, D.lf0, D.lf1);
+    double pr[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pr[q] = 0.0;
+    mm_sub<T>(arena + D.off, D.ld, a.y + D.col0, 1, a.N, D.m, D.ncols, a.nrhs, pr, As, Bs);
+    double* P = a.pbuf + (int64_t)rec * a.pstride;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int o = threadIdx.x + q * kSolveThreads;
+      if (o < D.m * a.nrhs) cstore(P + o, -pr[q]);
+    }
+    publish(a.pflag + rec, a.epoch);
+  }
 }
 
 // T = Y^T y[cols] (k x nrhs): one output per thread for short blocks, a
@@ -323,15 +411,19 @@ __device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forw
 }
 
 template <class T>
-__global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T* arena, SolveArgs a) {
+__global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T* arena, SolveArgs a0) {
+  SolveArgs a = a0;
   // LDS: acc (128 x 32 doubles), A staging (128 x kKC doubles), B staging
-  // (32 x kKC doubles): 112 KB
+  // (32 x kKC doubles), diagonal leaf (64 x 64 doubles), reciprocal pivots:
+  // 145 KB
   extern __shared__ double smem[];
   __shared__ int s_task;
   __shared__ int ready[kMaxContrib];
   double* acc = smem;
   double* As = acc + 128 * 32;
   double* Bs = As + 128 * kKC;
+  double* Dg = Bs + 32 * kKC;
+  double* rdiag = Dg + 64 * 64;
   while (true) {
     if (threadIdx.x == 0) s_task = atomicAdd(a.ctr, 1);
     __syncthreads();
@@ -339,13 +431,21 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
     __syncthreads();
     if (t >= a.ntasks) break;
     const STask task = a.tasks[t];
-    switch (task.kind) {
-      case kFwdLeaf: run_leaf<T>(a, arena, task.idx, true, acc, ready, As, Bs); break;
-      case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
-      case kBwdLeaf: run_leaf<T>(a, arena, task.idx, false, acc, ready, As, Bs); break;
-      case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
+    a.cur_task = t;
+    if (a.trace && threadIdx.x == 0) {
+      a.trace[4 * t] = (int64_t)wall_clock64();
+      a.trace[4 * t + 3] = blockIdx.x;
     }
-    if (task.kind == kFwdLeaf || task.kind == kFwdTprod) {
+    switch (task.kind) {
+      case kFwdLeaf: run_leaf<T>(a, arena, task.idx, true, acc, ready, As, Bs, Dg, rdiag); break;
+      case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
+      case kBwdLeaf: run_leaf<T>(a, arena, task.idx, false, acc, ready, As, Bs, Dg, rdiag); break;
+      case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
+      case kFwdPush: run_push<T>(a, arena, task.idx, true, As, Bs); break;
+      case kBwdPush: run_push<T>(a, arena, task.idx, false, As, Bs); break;
+    }
+    if (a.trace && threadIdx.x == 0) a.trace[4 * t + 2] = (int64_t)wall_clock64();
+    if (task.kind == kFwdLeaf || task.kind == kFwdTprod || task.kind == kFwdPush) {
       if (threadIdx.x == 0) __hip_atomic_fetch_add(a.ctr + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -369,6 +469,12 @@ struct SolveDev {
   int32_t* leaf_flag;
   int32_t* tp_flag;
   int32_t* ctr;
+  const int32_t* push0;
+  const int32_t* push_recs;
+  double* pbuf;
+  int32_t* pflag;
+  int64_t pstride;
+  int64_t* trace;
   int32_t ntasks, n_fwd, L, max_m, max_rhs;
 };
 
@@ -377,9 +483,10 @@ hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const So
                                    int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s) {
   dev::solve_reset_kernel<<<1, 64, 0, s>>>(d.ctr);
   dev::SolveArgs a{d.tasks, d.leaves, d.dense, d.low, d.tprod, dims, d.y, d.tbuf, d.leaf_flag, d.tp_flag,
-                   d.ctr, d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch};
+                   d.ctr, d.push0, d.push_recs, d.pbuf, d.pflag, d.pstride, d.trace,
+                   d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch, 0};
   // acc 128 x 32, A staging 128 x kKC (also the diagonal leaf), B staging 32 x kKC
-  const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC) * sizeof(double);
+  const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC + 64 * 64 + 128) * sizeof(double);
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::solve_persistent_kernel<T>),

@@ -38,6 +38,8 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
         SDense d{};
         d.off = st.off[b] + (lc.begin - rc.begin);
         d.ld = rc.size();
+        d.m = lc.size();
+        d.row0 = lc.begin;
         d.col0 = cc.begin;
         d.ncols = cc.size();
         d.lf0 = cc.leaf_first;
@@ -89,15 +91,45 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
     sc.low.insert(sc.low.end(), ll[s].begin(), ll[s].end());
     sc.max_m = std::max(sc.max_m, lf.m);
   }
+  // producers of the dense records: the leaf task of the preceding leaf for
+  // the block coupling neighbours, otherwise the push task of the leaf that
+  // completes sigma
+  std::vector<std::vector<int32_t>> push(2 * L);
+  for (int32_t s = 0; s < 2 * L; ++s) sc.leaves[s].next_rec = -1;
+  for (int32_t s = 0; s < 2 * L; ++s) {
+    const bool fwd = s < L;
+    const int32_t j = s % L;
+    const SLeaf& lf = sc.leaves[s];
+    for (int32_t r = lf.d0; r < lf.d0 + lf.nd; ++r) {
+      const SDense& d = sc.dense[r];
+      const int32_t prod = fwd ? d.lf1 - 1 : d.lf0;     // leaf that completes sigma
+      const bool neighbour = (d.lf1 - d.lf0 == 1) && (fwd ? prod == j - 1 : prod == j + 1);
+      const int32_t ps = (fwd ? 0 : L) + prod;
+      if (neighbour && sc.leaves[ps].next_rec < 0) sc.leaves[ps].next_rec = r;
+      else push[ps].push_back(r);
+    }
+  }
+  auto add_push = [&](int32_t s) {
+    if (push[s].empty()) return -1;
+    const int32_t id = (int32_t)sc.push0.size();
+    sc.push0.push_back((int32_t)sc.push_recs.size());
+    sc.push_recs.insert(sc.push_recs.end(), push[s].begin(), push[s].end());
+    return id;
+  };
   for (int32_t f = 0; f < L; ++f) {
     sc.tasks.push_back({kFwdLeaf, f});
+    const int32_t id = add_push(f);
+    if (id >= 0) sc.tasks.push_back({kFwdPush, id});
     for (int32_t tp : tp_after[f]) sc.tasks.push_back({kFwdTprod, tp});
   }
   sc.n_fwd_tasks = (int32_t)sc.tasks.size();
   for (int32_t f = L - 1; f >= 0; --f) {
     sc.tasks.push_back({kBwdLeaf, L + f});
+    const int32_t id = add_push(L + f);
+    if (id >= 0) sc.tasks.push_back({kBwdPush, id});
     for (int32_t tp : tp_after[L + f]) sc.tasks.push_back({kBwdTprod, tp});
   }
+  sc.push0.push_back((int32_t)sc.push_recs.size());
 }
 
 }  // namespace hlu

@@ -1,13 +1,16 @@
 // Task schedule of the persistent H-triangular solve (Algorithm 1, step III:
 // z = U^{-1}(L^{-1} r)).
 //
-// The forward sweep visits the leaf clusters in order; the task of leaf j
-// pulls every contribution of the blocks of L in its block row (dense:
-// L_b y[sigma]; low-rank: X_b (Y_b^T y[sigma]) with the small product
-// Y_b^T y[sigma] computed once per block by a T-product task), then solves
-// with the unit lower triangle of the diagonal leaf.  The backward sweep is
-// the mirror image with U.  This is the left-looking form of the recursive
-// H-forward/backward substitution: the same arithmetic, summed per row.
+// The forward sweep visits the leaf clusters in order; leaf j's solution
+// row is y_j = L_jj^{-1} (b_j - sum over the blocks of L in its block row).
+// Low-rank blocks contribute X_b (Y_b^T y[sigma]), the small product being
+// formed once per block by a T-product task.  Every dense block L_b y[sigma]
+// is formed into its own partial-sum record: by the task of leaf j-1 for the
+// block coupling j to j-1 (on the critical path), otherwise by the push task
+// of the leaf that completes sigma.  The task of leaf j then adds its
+// records in a fixed order.  The backward sweep mirrors this with U.  This
+// is the left-looking form of the recursive H-forward/backward
+// substitution: the same arithmetic, summed per row.
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -20,12 +23,16 @@ namespace hlu {
 struct SLeaf {
   int32_t row0, m;     // rows in cluster order
   int64_t diag;        // diagonal leaf (column-major, leading dimension m)
-  int32_t d0, nd;      // dense contributions
+  int32_t d0, nd;      // dense contributions (partial-sum records) of this row
   int32_t l0, nl;      // low-rank contributions
+  int32_t next_rec;    // dense record this leaf task computes after solving (-1: none)
+  int32_t pad;
 };
 struct SDense {        // block rows of leaf j: off + i + k*ld, k < ncols
   int64_t off;
   int32_t ld, col0, ncols, lf0, lf1;   // columns [col0, col0+ncols) = leaves [lf0, lf1)
+  int32_t m;           // rows (= size of leaf j)
+  int32_t row0;        // first row of leaf j
   int32_t pad;
 };
 struct SLow {          // X rows of leaf j: xoff + i + kk*ldx
@@ -37,7 +44,7 @@ struct STprod {        // T = Y^T y[cols]: Y at yoff + r + kk*ldy
   int64_t toff;        // T (cap x nrhs, leading dimension cap) in the T buffer
   int32_t ldy, col0, ncols, slot, lf0, lf1, cap, pad;
 };
-enum STaskKind : int32_t { kFwdLeaf = 0, kFwdTprod = 1, kBwdLeaf = 2, kBwdTprod = 3 };
+enum STaskKind : int32_t { kFwdLeaf = 0, kFwdTprod = 1, kBwdLeaf = 2, kBwdTprod = 3, kFwdPush = 4, kBwdPush = 5 };
 struct STask {
   int32_t kind, idx;
 };
@@ -49,6 +56,8 @@ struct SolveSched {
   std::vector<SLow> low;
   std::vector<STprod> tprod;
   std::vector<STask> tasks;       // claim order
+  std::vector<int32_t> push0;     // per push task: first record in push_recs (size #push + 1)
+  std::vector<int32_t> push_recs; // dense records computed by push tasks
   int32_t n_fwd_tasks = 0;
   int64_t tbuf_per_rhs = 0;       // doubles of the T buffer per right-hand side
   int32_t max_m = 0;

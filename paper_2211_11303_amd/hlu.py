@@ -80,10 +80,12 @@ class SpMat:
         L.check(L.lib().hlu_spmat_create(self.n, self.nnz, _dev_ptr(self.rp), _dev_ptr(self.ci),
                                          _dev_ptr(self.val), ctypes.byref(h)))
         self.handle = h
+        # bound now: module globals may already be gone when the interpreter exits
+        self._destroy = L.lib().hlu_spmat_destroy
 
     def __del__(self):
         if getattr(self, "handle", None):
-            L.lib().hlu_spmat_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = None
 
     def hlu_spmv(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
@@ -112,6 +114,7 @@ class HLU:
         L.check(L.lib().hlu_build(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), float(eta), int(leaf),
                                   ctypes.byref(h)))
         self.handle = h
+        self._destroy = L.lib().hlu_destroy
         self.n = len(self._rp) - 1
         self.leaf = leaf
         self.eta = eta
@@ -120,7 +123,7 @@ class HLU:
 
     def __del__(self):
         if getattr(self, "handle", None):
-            L.lib().hlu_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = None
 
     @staticmethod

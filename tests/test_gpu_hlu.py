@@ -125,7 +125,8 @@ def test_n8_factor_and_gmres(gpu, prec, eps):
             assert abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
 
 
-@pytest.mark.parametrize("n,leaf,prec", [(8, 64, "fp64"), (5, 20, "fp64"), (4, 8, "fp32"), (8, 32, "fp32")])
+@pytest.mark.parametrize("n,leaf,prec", [(8, 64, "fp64"), (5, 20, "fp64"), (4, 8, "fp32"), (8, 32, "fp32"),
+                                          (16, 64, "fp64"), (8, 128, "fp64")])
 def test_persistent_solve_matches_wave_solve(gpu, n, leaf, prec, monkeypatch):
     """The persistent left-looking H-solve equals the planned recursive
     H-solve (same arithmetic, different summation order).  With FP32
@@ -137,11 +138,12 @@ def test_persistent_solve_matches_wave_solve(gpu, n, leaf, prec, monkeypatch):
     H = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(1e-4, prec=prec)
     for nrhs in (1, 5, 33):
         b = torch.tensor(inputs.exact_solution_cols(A.n, nrhs, seed=7), device="cuda")
-        z_p = H.hlu_solve(b)
         monkeypatch.setenv("HLU_DEBUG_WAVE_SOLVE", "1")
         z_w = H.hlu_solve(b)
         monkeypatch.delenv("HLU_DEBUG_WAVE_SOLVE")
-        torch.cuda.synchronize()
-        assert torch.isfinite(z_p).all()
         tol = 1e-10 if prec == "fp64" else 1e-4
-        assert (z_p - z_w).norm() <= tol * z_w.norm(), (nrhs, (z_p - z_w).norm().item(), z_w.norm().item())
+        for rep in range(3):   # the persistent form is scheduled dynamically: repeat
+            z_p = H.hlu_solve(b)
+            torch.cuda.synchronize()
+            assert torch.isfinite(z_p).all()
+            assert (z_p - z_w).norm() <= tol * z_w.norm(), (nrhs, rep, (z_p - z_w).norm().item(), z_w.norm().item())
