@@ -59,29 +59,6 @@ hipError_t combine_launch(int32_t N, int32_t nrhs, int32_t nz, const double* Z, 
 hipError_t residual_launch(int32_t N, int32_t nrhs, const double* b, int64_t ldb, double* r, hipStream_t s);
 hipError_t copy_cols_launch(int32_t N, int32_t nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,
                             hipStream_t s);
-struct SolveDev {
-  const STask* tasks;
-  const SLeaf* leaves;
-  const SDense* dense;
-  const SLow* low;
-  const STprod* tprod;
-  double* y;
-  double* tbuf;
-  int32_t* leaf_flag;
-  int32_t* tp_flag;
-  int32_t* ctr;
-  const int32_t* push0;
-  const int32_t* push_recs;
-  double* pbuf;
-  int32_t* pflag;
-  int64_t pstride;
-  int64_t* trace;
-  int32_t ntasks, n_fwd, L, max_m, max_rhs;
-};
-template <class T>
-hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const SolveDev& d, int32_t N,
-                                   int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s);
-
 namespace {
 
 constexpr int kDefaultCap = 64;
@@ -280,6 +257,8 @@ void ensure_device(hlu_s* h) {
     d.low = static_cast<const SLow*>(keep(upload(sc->low)));
     d.tprod = static_cast<const STprod*>(keep(upload(sc->tprod)));
     d.max_rhs = kMaxRhs;
+    // sized for FP64; FP32 factors use the first half
+    d.inv = keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc->inv_elems)));
     d.y = static_cast<double*>(keep(dmalloc<double>((size_t)h->S.N * kMaxRhs)));
     d.tbuf = static_cast<double*>(keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc->tbuf_per_rhs) * kMaxRhs)));
     const size_t nflags = 2 * (size_t)sc->L + sc->tprod.size() + sc->dense.size() + 1;
@@ -299,7 +278,7 @@ void ensure_device(hlu_s* h) {
     d.trace = nullptr;
     if (const char* tr = getenv("HLU_DEBUG_SOLVE_TRACE")) {   // debug: per-task clocks
       (void)tr;
-      d.trace = static_cast<int64_t*>(keep(dmalloc<int64_t>(4 * (size_t)d.ntasks)));
+      d.trace = static_cast<int64_t*>(keep(dmalloc<int64_t>(8 * (size_t)d.ntasks)));
     }
     d.L = sc->L;
     d.max_m = sc->max_m;
@@ -370,6 +349,8 @@ void factor_impl(hlu_s* h, hipStream_t s) {
   HIP_OK(zero_int_launch(dims, st.num_slots, s));
   HIP_OK(zero_int_launch(status, 64, s));
   run_plan<T>(h, ps.factor, *h->dfactor, h->factor_compute64, s);
+  // the persistent solve applies the diagonal leaves through their inverses
+  HIP_OK(diag_inverse_launch<T>(static_cast<const T*>(h->work), h->sdev, s));
 }
 
 template <class T>
@@ -414,12 +395,12 @@ void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, i
     if (h->sdev.trace) {   // debug: dump task clocks and kinds
       HIP_OK(hipStreamSynchronize(s));
       const SolveSched& sc = *h->ssched;
-      std::vector<int64_t> tr(4 * (size_t)h->sdev.ntasks);
+      std::vector<int64_t> tr(8 * (size_t)h->sdev.ntasks);
       HIP_OK(hipMemcpy(tr.data(), h->sdev.trace, tr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
       if (FILE* f = fopen(getenv("HLU_DEBUG_SOLVE_TRACE"), "wb")) {
         for (int32_t t = 0; t < h->sdev.ntasks; ++t) {
-          int64_t rec[6] = {sc.tasks[t].kind, sc.tasks[t].idx, tr[4 * t], tr[4 * t + 1], tr[4 * t + 2], tr[4 * t + 3]};
-          fwrite(rec, sizeof(rec), 1, f);
+          fwrite(&sc.tasks[t], sizeof(STask), 1, f);   // kind, idx (int32 each)
+          fwrite(tr.data() + 8 * t, 8 * sizeof(int64_t), 1, f);
         }
         fclose(f);
       }

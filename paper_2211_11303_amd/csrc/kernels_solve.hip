@@ -10,6 +10,7 @@
 // Factors are read in their storage type T; arithmetic and vectors are FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "solve_sched.h"
@@ -20,6 +21,9 @@ namespace dev {
 constexpr int kSolveThreads = 256;
 constexpr int kMaxRhsTile = 8;          // columns per register tile of the triangular solve
 constexpr int kSpinLimit = 1 << 25;     // bounded waits; on overflow the error flag is set
+// debug trace per task: claim, solve start, end, workgroup, low-rank done,
+// triangle done, product done, flags stored
+constexpr int kTraceFields = 8;
 
 struct SolveArgs {
   const STask* tasks;
@@ -38,10 +42,14 @@ struct SolveArgs {
   double* pbuf;         // partial-sum records, pstride doubles each (m x nrhs, ld m)
   int32_t* pflag;       // one per record
   int64_t pstride;
-  int64_t* trace;       // optional (debug): per task claim / start-of-compute / end clocks
+  int64_t* trace;       // optional (debug): kTraceFields clocks per task
   int32_t ntasks, n_fwd, N, nrhs, max_rhs, L, epoch;
   int32_t cur_task;     // set per task (trace only)
 };
+
+__device__ __forceinline__ void stamp(const SolveArgs& a, int field) {
+  if (a.trace && threadIdx.x == 0) a.trace[kTraceFields * a.cur_task + field] = (int64_t)wall_clock64();
+}
 
 // Data exchanged between tasks (y, T products) is written and read with
 // agent-scope relaxed atomics: such accesses go to the device coherence
@@ -110,57 +118,39 @@ __device__ __forceinline__ double bcast(double v, int lane) {
 }
 
 // acc (m x nrhs, LDS, row-major with stride ldacc) := tri^{-1} acc with the
-// unit lower (forward) or upper (backward) triangle of the diagonal leaf,
-// done by wavefront 0 in registers: lane l owns rows l and l + 64.
+// precomputed inverse I of the diagonal leaf's triangle (m x m, column-major):
+// forward, the strictly lower part of L^{-1} with its unit diagonal;
+// backward, U^{-1} (on and above the diagonal).  A dense product over all
+// threads instead of m dependent substitution steps.
 template <class P>
-__device__ void leaf_triangular(const P* D, int m, bool forward, double* acc, int ldacc, int nrhs,
-                                const double* rdiag) {
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
-  for (int c0 = 0; c0 < nrhs; c0 += kMaxRhsTile) {
-    const int nc = min(kMaxRhsTile, nrhs - c0);
-    double v0[kMaxRhsTile], v1[kMaxRhsTile];
+__device__ void apply_inverse(const P* I, int m, bool forward, double* acc, int ldacc, int nrhs) {
+  constexpr int kPer = 16;
+  double out[kPer];
 #pragma unroll
-    for (int c = 0; c < kMaxRhsTile; ++c) {
-      v0[c] = (lane < m && c < nc) ? acc[lane * ldacc + c0 + c] : 0.0;
-      v1[c] = (lane + 64 < m && c < nc) ? acc[(lane + 64) * ldacc + c0 + c] : 0.0;
-    }
-    if (forward) {
-      for (int q = 0; q < m; ++q) {
-        const int ql = q & 63;
-        const bool hiq = q >= 64;
-        const double l0 = (lane > q && lane < m) ? double(D[lane + (int64_t)q * m]) : 0.0;
-        const double l1 = (lane + 64 > q && lane + 64 < m) ? double(D[lane + 64 + (int64_t)q * m]) : 0.0;
-#pragma unroll
-        for (int c = 0; c < kMaxRhsTile; ++c) {
-          const double yq = bcast(hiq ? v1[c] : v0[c], ql);
-          v0[c] -= l0 * yq;
-          v1[c] -= l1 * yq;
-        }
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * 256;
+    out[q] = 0.0;
+    if (o < m * nrhs) {
+      const int i = o % m, c = o / m;
+      double sum = 0.0;
+      if (forward) {
+        sum = acc[i * ldacc + c];
+#pragma unroll 8
+        for (int k = 0; k < i; ++k) sum += double(I[i + k * m]) * acc[k * ldacc + c];
+      } else {
+#pragma unroll 8
+        for (int k = i; k < m; ++k) sum += double(I[i + k * m]) * acc[k * ldacc + c];
       }
-    } else {
-      for (int q = m - 1; q >= 0; --q) {
-        const int ql = q & 63;
-        const bool hiq = q >= 64;
-        const double rq = rdiag ? rdiag[q] : 1.0 / double(D[q + (int64_t)q * m]);
-        const double u0 = lane < q ? double(D[lane + (int64_t)q * m]) : 0.0;
-        const double u1 = (lane + 64 < q) ? double(D[lane + 64 + (int64_t)q * m]) : 0.0;
-#pragma unroll
-        for (int c = 0; c < kMaxRhsTile; ++c) {
-          const double zq = bcast(hiq ? v1[c] : v0[c], ql) * rq;
-          if (lane == ql && !hiq) v0[c] = zq;
-          if (lane == ql && hiq) v1[c] = zq;
-          v0[c] -= u0 * zq;
-          v1[c] -= u1 * zq;
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < kMaxRhsTile; ++c) {
-      if (c < nc && lane < m) acc[lane * ldacc + c0 + c] = v0[c];
-      if (c < nc && lane + 64 < m) acc[(lane + 64) * ldacc + c0 + c] = v1[c];
+      out[q] = sum;
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * 256;
+    if (o < m * nrhs) acc[(o % m) * ldacc + o / m] = out[q];
+  }
+  __syncthreads();
 }
 
 // Staging buffers of a workgroup (LDS): A chunk (max_m x kKC doubles) and
@@ -191,6 +181,7 @@ __device__ void mm_sub(const T* A, int64_t lda, const double* B, int64_t bs, int
       if (o < m * nrhs) {
         const int i = o % m, c = o / m;
         double sum = 0.0;
+#pragma unroll 8
         for (int k = 0; k < kc; ++k) sum += As[k * 128 + i] * Bs[c * kKC + k];
         r[q] -= sum;
       }
@@ -217,8 +208,8 @@ __device__ void low_contrib(const SolveArgs& a, const T* arena, const SLow& Lw, 
 constexpr int kMaxContrib = 256;   // contributions per leaf task checked for early readiness
 
 template <class T>
-__device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward, double* acc,
-                         int* ready, double* As, double* Bs, double* Dg, double* rdiag) {
+__device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s, bool forward, double* acc,
+                         int* ready, double* As, double* Bs, double* Dg) {
   const SLeaf lf = a.leaves[s];
   const int m = lf.m, nrhs = a.nrhs;
   const int ldacc = a.max_rhs;
@@ -249,12 +240,13 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
     wait_one(a, a.tp_flag + Lw.tp, a.epoch);
     low_contrib<T>(a, arena, Lw, m, nrhs, r, As, Bs);
   }
+  stamp(a, 4);
   // stage factor data of the critical section before waiting on the
-  // preceding leaf: the diagonal leaf (with reciprocal pivots) and the
+  // preceding leaf: the triangle inverses of the diagonal leaf and the
   // neighbouring row's block multiplied after the solve
   const bool diag_lds = m * m <= 64 * 64;
   if (diag_lds) {
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) Dg[e] = double(arena[lf.diag + e]);
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) Dg[e] = double(inv[lf.inv + e]);
   }
   SDense Dn{};
   const bool next_lds = lf.next_rec >= 0 && a.dense[lf.next_rec].m <= 128 && a.dense[lf.next_rec].ncols <= kKC;
@@ -266,8 +258,6 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
     }
   }
   __syncthreads();
-  if (diag_lds)
-    for (int q = threadIdx.x; q < m; q += blockDim.x) rdiag[q] = 1.0 / Dg[q + q * m];
   // dense contributions: wait for every partial-sum record of this row,
   // then add them in record order
   for (int t = threadIdx.x; t < lf.nd; t += blockDim.x) spin_eq(a.pflag + lf.d0 + t, a.epoch, a.ctr + 2);
@@ -294,12 +284,11 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
     const int o = threadIdx.x + q * kSolveThreads;
     if (o < m * nrhs) acc[(o % m) * ldacc + o / m] = r[q];
   }
-  if (a.trace && threadIdx.x == 0) a.trace[4 * a.cur_task + 1] = (int64_t)wall_clock64();
-  // every wave wrote rows of acc; wavefront 0 reads all of them
+  stamp(a, 1);
   __syncthreads();
-  if (diag_lds) leaf_triangular<double>(Dg, m, forward, acc, ldacc, nrhs, rdiag);
-  else leaf_triangular<T>(arena + lf.diag, m, forward, acc, ldacc, nrhs, nullptr);
-  __syncthreads();
+  if (diag_lds) apply_inverse<double>(Dg, m, forward, acc, ldacc, nrhs);
+  else apply_inverse<T>(inv + lf.inv, m, forward, acc, ldacc, nrhs);
+  stamp(a, 5);
   for (int o = threadIdx.x; o < m * nrhs; o += blockDim.x)
     cstore(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N, acc[(o % m) * ldacc + o / m]);
   if (lf.next_rec >= 0) {
@@ -315,6 +304,7 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
         if (o < D.m * nrhs) {
           const int i = o % D.m, c = o / D.m;
           double sum = 0.0;
+#pragma unroll 8
           for (int k = 0; k < D.ncols; ++k) sum += As[k * 128 + i] * acc[k * ldacc + c];
           pr[q] = sum;
         }
@@ -330,6 +320,7 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
       const int o = threadIdx.x + q * kSolveThreads;
       if (o < D.m * nrhs) cstore(P + o, pr[q]);
     }
+    stamp(a, 6);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -337,6 +328,7 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, int s, bool forward
       __hip_atomic_store(a.pflag + lf.next_rec, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(a.leaf_flag + s, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    stamp(a, 7);
     return;
   }
   publish(a.leaf_flag + s, a.epoch);
@@ -396,6 +388,7 @@ __device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forw
       if (o < nout) {
         const int kk = o % k, c = o / k;
         double sum = 0.0;
+#pragma unroll 8
         for (int r = 0; r < rc; ++r) sum += As[kk * kKC + r] * Bs[c * kKC + r];
         s[q] += sum;
       }
@@ -411,11 +404,12 @@ __device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forw
 }
 
 template <class T>
-__global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T* arena, SolveArgs a0) {
+__global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T* arena, const T* inv,
+                                                                        SolveArgs a0) {
   SolveArgs a = a0;
   // LDS: acc (128 x 32 doubles), A staging (128 x kKC doubles), B staging
-  // (32 x kKC doubles), diagonal leaf (64 x 64 doubles), reciprocal pivots:
-  // 145 KB
+  // (32 x kKC doubles), triangle inverses of a leaf up to 64 rows (64 x 64
+  // doubles): 144 KB
   extern __shared__ double smem[];
   __shared__ int s_task;
   __shared__ int ready[kMaxContrib];
@@ -423,7 +417,6 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
   double* As = acc + 128 * 32;
   double* Bs = As + 128 * kKC;
   double* Dg = Bs + 32 * kKC;
-  double* rdiag = Dg + 64 * 64;
   while (true) {
     if (threadIdx.x == 0) s_task = atomicAdd(a.ctr, 1);
     __syncthreads();
@@ -433,20 +426,72 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
     const STask task = a.tasks[t];
     a.cur_task = t;
     if (a.trace && threadIdx.x == 0) {
-      a.trace[4 * t] = (int64_t)wall_clock64();
-      a.trace[4 * t + 3] = blockIdx.x;
+      a.trace[kTraceFields * t] = (int64_t)wall_clock64();
+      a.trace[kTraceFields * t + 3] = blockIdx.x;
     }
     switch (task.kind) {
-      case kFwdLeaf: run_leaf<T>(a, arena, task.idx, true, acc, ready, As, Bs, Dg, rdiag); break;
+      case kFwdLeaf: run_leaf<T>(a, arena, inv, task.idx, true, acc, ready, As, Bs, Dg); break;
       case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
-      case kBwdLeaf: run_leaf<T>(a, arena, task.idx, false, acc, ready, As, Bs, Dg, rdiag); break;
+      case kBwdLeaf: run_leaf<T>(a, arena, inv, task.idx, false, acc, ready, As, Bs, Dg); break;
       case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
       case kFwdPush: run_push<T>(a, arena, task.idx, true, As, Bs); break;
       case kBwdPush: run_push<T>(a, arena, task.idx, false, As, Bs); break;
     }
-    if (a.trace && threadIdx.x == 0) a.trace[4 * t + 2] = (int64_t)wall_clock64();
+    stamp(a, 2);
     if (task.kind == kFwdLeaf || task.kind == kFwdTprod || task.kind == kFwdPush) {
       if (threadIdx.x == 0) __hip_atomic_fetch_add(a.ctr + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+// Inverses of the two triangles of each diagonal leaf, one workgroup per
+// (leaf, triangle): blockIdx.y = 0 forms L^{-1} (unit lower) and writes its
+// strictly lower part, blockIdx.y = 1 forms U^{-1} and writes the upper part
+// with the diagonal, so both share one m x m block.  Columns of the identity
+// are solved in chunks of `cols` in LDS by column-oriented substitution.
+template <class T>
+__global__ void __launch_bounds__(256) diag_inverse_kernel(const T* arena, const SLeaf* leaves, T* inv, int cols) {
+  extern __shared__ double sm[];
+  const SLeaf lf = leaves[blockIdx.x];
+  const int m = lf.m;
+  const bool upper = blockIdx.y == 1;
+  double* Ts = sm;            // m x m, column-major
+  double* Vs = sm + m * m;    // m x cols, row i at Vs[i * cols]
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) Ts[e] = double(arena[lf.diag + e]);
+  for (int c0 = 0; c0 < m; c0 += cols) {
+    const int pc = min(cols, m - c0);
+    for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
+      const int i = e / pc, j = e % pc;
+      Vs[i * cols + j] = (i == c0 + j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (!upper) {
+      // rows above column c0 + j of the result stay zero: start at q = c0
+      for (int q = c0; q < m - 1; ++q) {
+        const int rows = m - q - 1;
+        for (int e = threadIdx.x; e < rows * pc; e += blockDim.x) {
+          const int r = q + 1 + e % rows, j = e / rows;
+          Vs[r * cols + j] -= Ts[r + q * m] * Vs[q * cols + j];
+        }
+        __syncthreads();
+      }
+    } else {
+      // rows below column c0 + j stay zero: start at the chunk's last column
+      for (int q = c0 + pc - 1; q >= 0; --q) {
+        const double d = 1.0 / Ts[q + q * m];
+        for (int j = threadIdx.x; j < pc; j += blockDim.x) Vs[q * cols + j] *= d;
+        __syncthreads();
+        for (int e = threadIdx.x; e < q * pc; e += blockDim.x) {
+          const int r = e % q, j = e / q;
+          Vs[r * cols + j] -= Ts[r + q * m] * Vs[q * cols + j];
+        }
+        __syncthreads();
+      }
+    }
+    for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
+      const int i = e % m, j = e / m, col = c0 + j;
+      if (upper ? i <= col : i > col) inv[lf.inv + i + (int64_t)col * m] = T(Vs[i * cols + j]);
     }
     __syncthreads();
   }
@@ -458,26 +503,6 @@ __global__ void solve_reset_kernel(int32_t* ctr) {
 
 }  // namespace dev
 
-struct SolveDev {
-  const STask* tasks;
-  const SLeaf* leaves;
-  const SDense* dense;
-  const SLow* low;
-  const STprod* tprod;
-  double* y;
-  double* tbuf;
-  int32_t* leaf_flag;
-  int32_t* tp_flag;
-  int32_t* ctr;
-  const int32_t* push0;
-  const int32_t* push_recs;
-  double* pbuf;
-  int32_t* pflag;
-  int64_t pstride;
-  int64_t* trace;
-  int32_t ntasks, n_fwd, L, max_m, max_rhs;
-};
-
 template <class T>
 hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const SolveDev& d, int32_t N,
                                    int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s) {
@@ -485,17 +510,38 @@ hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const So
   dev::SolveArgs a{d.tasks, d.leaves, d.dense, d.low, d.tprod, dims, d.y, d.tbuf, d.leaf_flag, d.tp_flag,
                    d.ctr, d.push0, d.push_recs, d.pbuf, d.pflag, d.pstride, d.trace,
                    d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch, 0};
-  // acc 128 x 32, A staging 128 x kKC (also the diagonal leaf), B staging 32 x kKC
-  const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC + 64 * 64 + 128) * sizeof(double);
+  // acc 128 x 32, A staging 128 x kKC, B staging 32 x kKC, inverses 64 x 64
+  const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC + 64 * 64) * sizeof(double);
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::solve_persistent_kernel<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     attr = true;
   }
-  dev::solve_persistent_kernel<T><<<grid, dev::kSolveThreads, sh, s>>>(arena, a);
+  dev::solve_persistent_kernel<T><<<grid, dev::kSolveThreads, sh, s>>>(arena, static_cast<const T*>(d.inv), a);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s) {
+  constexpr size_t kLds = 160 * 1024;
+  const size_t m = (size_t)d.max_m;
+  const size_t tri = m * m * sizeof(double);
+  int cols = (int)std::min<size_t>(m, (kLds - tri) / (m * sizeof(double)));
+  const size_t sh = tri + m * (size_t)cols * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::diag_inverse_kernel<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
+    attr = true;
+  }
+  dim3 g(d.L, 2);
+  dev::diag_inverse_kernel<T><<<g, 256, sh, s>>>(arena, d.leaves, static_cast<T*>(d.inv), cols);
+  return hipGetLastError();
+}
+
+template hipError_t diag_inverse_launch<float>(const float*, const SolveDev&, hipStream_t);
+template hipError_t diag_inverse_launch<double>(const double*, const SolveDev&, hipStream_t);
 
 template hipError_t solve_persistent_launch<float>(const float*, const int32_t*, const SolveDev&, int32_t, int32_t,
                                                    int32_t, int32_t, hipStream_t);

@@ -19,6 +19,7 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
   std::vector<int32_t> leaf_of_cluster(S.clusters.size(), -1);
   for (int32_t l = 0; l < L; ++l) leaf_of_cluster[S.leaf_clusters[l]] = l;
   std::vector<std::vector<int32_t>> tp_after(2 * L);   // T-products to run after leaf task
+  std::vector<int32_t> tp_need;                        // sweep position of the first consumer
   int64_t toff = 0;
   for (size_t b = 0; b < S.leaves.size(); ++b) {
     const BlockNode& B = S.blocks[S.leaves[b]];
@@ -60,9 +61,11 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
       toff += t.cap;
       const int32_t tp = (int32_t)sc.tprod.size();
       sc.tprod.push_back(t);
-      // forward: ready after the last leaf of sigma; backward: after the first
+      // forward: ready after the last leaf of sigma; backward: after the first.
+      // The key is the first row leaf that needs it in sweep order.
       if (lower) tp_after[cc.leaf_last - 1].push_back(tp);
       else tp_after[L + cc.leaf_first].push_back(tp);
+      tp_need.push_back(lower ? rc.leaf_first : L - rc.leaf_last);
       for (int32_t f = rc.leaf_first; f < rc.leaf_last; ++f) {
         const ClusterNode& lc = S.clusters[S.leaf_clusters[f]];
         SLow w{};
@@ -75,6 +78,12 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
   }
   sc.tbuf_per_rhs = toff;
   sc.leaves.resize(2 * L);
+  std::vector<int64_t> inv(L);
+  for (int32_t f = 0; f < L; ++f) {
+    inv[f] = sc.inv_elems;
+    const int64_t m = S.clusters[S.leaf_clusters[f]].size();
+    sc.inv_elems += m * m;
+  }
   for (int32_t s = 0; s < 2 * L; ++s) {
     const int32_t f = s % L;
     const ClusterNode& lc = S.clusters[S.leaf_clusters[f]];
@@ -82,6 +91,7 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
     lf.row0 = lc.begin;
     lf.m = lc.size();
     lf.diag = diag[f];
+    lf.inv = inv[f];
     HLU_REQUIRE(lf.diag >= 0, HLU_ERR_INVALID_ARG, "solve schedule: missing diagonal leaf");
     lf.d0 = (int32_t)sc.dense.size();
     lf.nd = (int32_t)dl[s].size();
@@ -109,25 +119,35 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
       else push[ps].push_back(r);
     }
   }
-  auto add_push = [&](int32_t s) {
-    if (push[s].empty()) return -1;
-    const int32_t id = (int32_t)sc.push0.size();
-    sc.push0.push_back((int32_t)sc.push_recs.size());
-    sc.push_recs.insert(sc.push_recs.end(), push[s].begin(), push[s].end());
-    return id;
+  // Work released by one leaf is queued in the order its consumers come in
+  // the sweep (forward: ascending rows, backward: descending), and the
+  // records are split into tasks of kPushChunk so that several workgroups
+  // form them together.
+  auto emit = [&](int32_t s, int32_t push_kind, int32_t tp_kind) {
+    const bool fwd = s < L;
+    std::vector<int32_t>& pr = push[s];
+    std::stable_sort(pr.begin(), pr.end(), [&](int32_t x, int32_t y) {
+      return fwd ? sc.dense[x].row0 < sc.dense[y].row0 : sc.dense[x].row0 > sc.dense[y].row0;
+    });
+    std::vector<int32_t>& tl = tp_after[s];
+    std::stable_sort(tl.begin(), tl.end(), [&](int32_t x, int32_t y) { return tp_need[x] < tp_need[y]; });
+    for (size_t c = 0; c < pr.size(); c += kPushChunk) {
+      const int32_t id = (int32_t)sc.push0.size();
+      sc.push0.push_back((int32_t)sc.push_recs.size());
+      const size_t e = std::min(pr.size(), c + kPushChunk);
+      sc.push_recs.insert(sc.push_recs.end(), pr.begin() + c, pr.begin() + e);
+      sc.tasks.push_back({push_kind, id});
+    }
+    for (int32_t tp : tl) sc.tasks.push_back({tp_kind, tp});
   };
   for (int32_t f = 0; f < L; ++f) {
     sc.tasks.push_back({kFwdLeaf, f});
-    const int32_t id = add_push(f);
-    if (id >= 0) sc.tasks.push_back({kFwdPush, id});
-    for (int32_t tp : tp_after[f]) sc.tasks.push_back({kFwdTprod, tp});
+    emit(f, kFwdPush, kFwdTprod);
   }
   sc.n_fwd_tasks = (int32_t)sc.tasks.size();
   for (int32_t f = L - 1; f >= 0; --f) {
     sc.tasks.push_back({kBwdLeaf, L + f});
-    const int32_t id = add_push(L + f);
-    if (id >= 0) sc.tasks.push_back({kBwdPush, id});
-    for (int32_t tp : tp_after[L + f]) sc.tasks.push_back({kBwdTprod, tp});
+    emit(L + f, kBwdPush, kBwdTprod);
   }
   sc.push0.push_back((int32_t)sc.push_recs.size());
 }

@@ -12,6 +12,8 @@
 // is the left-looking form of the recursive H-forward/backward
 // substitution: the same arithmetic, summed per row.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <vector>
 
@@ -23,6 +25,7 @@ namespace hlu {
 struct SLeaf {
   int32_t row0, m;     // rows in cluster order
   int64_t diag;        // diagonal leaf (column-major, leading dimension m)
+  int64_t inv;         // its triangle inverses in the inverse buffer (m x m, leading dimension m)
   int32_t d0, nd;      // dense contributions (partial-sum records) of this row
   int32_t l0, nl;      // low-rank contributions
   int32_t next_rec;    // dense record this leaf task computes after solving (-1: none)
@@ -44,6 +47,7 @@ struct STprod {        // T = Y^T y[cols]: Y at yoff + r + kk*ldy
   int64_t toff;        // T (cap x nrhs, leading dimension cap) in the T buffer
   int32_t ldy, col0, ncols, slot, lf0, lf1, cap, pad;
 };
+constexpr int32_t kPushChunk = 2;   // partial-sum records per push task
 enum STaskKind : int32_t { kFwdLeaf = 0, kFwdTprod = 1, kBwdLeaf = 2, kBwdTprod = 3, kFwdPush = 4, kBwdPush = 5 };
 struct STask {
   int32_t kind, idx;
@@ -60,6 +64,7 @@ struct SolveSched {
   std::vector<int32_t> push_recs; // dense records computed by push tasks
   int32_t n_fwd_tasks = 0;
   int64_t tbuf_per_rhs = 0;       // doubles of the T buffer per right-hand side
+  int64_t inv_elems = 0;          // elements of the inverse buffer (sum of m^2 over leaves)
   int32_t max_m = 0;
   // algorithmic element reads of one application (both sweeps), for the
   // roofline: dense entries read + low-rank capacity entries touched is
@@ -67,5 +72,37 @@ struct SolveSched {
 };
 
 void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* out);
+
+// Device copy of a schedule and the buffers of the persistent solve.
+struct SolveDev {
+  const STask* tasks;
+  const SLeaf* leaves;
+  const SDense* dense;
+  const SLow* low;
+  const STprod* tprod;
+  void* inv;            // triangle inverses of the diagonal leaves (factor storage type)
+  double* y;
+  double* tbuf;
+  int32_t* leaf_flag;
+  int32_t* tp_flag;
+  int32_t* ctr;
+  const int32_t* push0;
+  const int32_t* push_recs;
+  double* pbuf;
+  int32_t* pflag;
+  int64_t pstride;
+  int64_t* trace;
+  int32_t ntasks, n_fwd, L, max_m, max_rhs;
+};
+
+// Both triangle inverses of every diagonal leaf (arena storage type T,
+// arithmetic in FP64), written to d.inv; run after each factorization.
+template <class T>
+hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s);
+
+// z = U^{-1} L^{-1} y for the nrhs columns of d.y (cluster order), in place.
+template <class T>
+hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const SolveDev& d, int32_t N,
+                                   int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s);
 
 }  // namespace hlu
