@@ -106,8 +106,10 @@ typedef struct {
   int32_t capped_blocks;         /* blocks whose eps-rank exceeded capacity   */
   double mean_rank;              /* mean rank over admissible blocks          */
   double lowrank_entries;        /* sum over admissible blocks of (m+n) rank  */
-  double min_abs_pivot, max_abs_pivot; /* over all diagonal leaves            */
-  double factor_flops;           /* nominal flops of the executed tasks       */
+  double min_abs_pivot, max_abs_pivot; /* |U_ii| over all diagonal leaves     */
+  int64_t solve_launches;        /* persistent solve launches timed since hlu_set_timing */
+  int64_t solve_columns;         /* right-hand-side columns those launches processed */
+  double solve_kernel_ms;        /* their summed durations (HIP events on the launch stream) */
 } hlu_stats;
 
 /* ---------------------------------------------------------------- problem
@@ -203,6 +205,12 @@ hlu_status hlu_export_structure(hlu_handle h, int32_t* perm, int32_t* begin, int
  * dense blocks) after hlu_factor. Synchronous. */
 hlu_status hlu_get_ranks(hlu_handle h, int32_t* ranks);
 hlu_status hlu_get_stats(hlu_handle h, hlu_stats* out);
+
+/* enable != 0: from now on bracket every persistent solve launch of hlu_solve
+ * (and of gmres_solve's preconditioner) with HIP events on its stream;
+ * hlu_get_stats then waits for the recorded events and reports their count
+ * and summed duration.  Every call resets both; enable == 0 stops timing. */
+hlu_status hlu_set_timing(hlu_handle h, int32_t enable);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hlu_last_error(void);

@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
         ("lowrank_rows_plus_cols", c_int64), ("workspace_bytes", c_int64), ("factor_waves", c_int64),
         ("factor_tasks", c_int64), ("solve_waves", c_int64), ("max_rank", c_int32),
         ("capped_blocks", c_int32), ("mean_rank", c_double), ("lowrank_entries", c_double),
-        ("min_abs_pivot", c_double), ("max_abs_pivot", c_double), ("factor_flops", c_double),
+        ("min_abs_pivot", c_double), ("max_abs_pivot", c_double),
+        ("solve_launches", c_int64), ("solve_columns", c_int64), ("solve_kernel_ms", c_double),
     ]
 
     def as_dict(self):
@@ -77,6 +78,7 @@ SIGNATURES = {
                                        P_i32]),
     "hlu_get_ranks": (c_int32, [c_void_p, P_i32]),
     "hlu_get_stats": (c_int32, [c_void_p, ctypes.POINTER(Stats)]),
+    "hlu_set_timing": (c_int32, [c_void_p, c_int32]),
 }
 
 _lib = None

@@ -64,6 +64,7 @@ namespace {
 constexpr int kDefaultCap = 64;
 constexpr int kMaxRhs = 32;
 constexpr int kDotBlocks = 256;
+constexpr size_t kMaxTimedEvents = 4096;   // event pairs kept before they are harvested
 // Gram-based truncation resolves singular values down to about
 // sqrt(K u) sigma_1; smaller ones are treated as zero.
 constexpr double kFloorRel = 1e-7;
@@ -167,7 +168,12 @@ struct hlu_s {
   double eps = 0.0;
   bool factor_compute64 = false;
   hlu_stats stats{};
+  // optional timing of the persistent solve launches (event pairs in flight)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  size_t tev_used = 0;
   ~hlu_s() {
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
     for (void* p : sowned)
       if (p) (void)hipFree(p);
     if (d_perm) (void)hipFree(d_perm);
@@ -259,6 +265,7 @@ void ensure_device(hlu_s* h) {
     d.max_rhs = kMaxRhs;
     // sized for FP64; FP32 factors use the first half
     d.inv = keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc->inv_elems)));
+    d.pivots = static_cast<double*>(keep(dmalloc<double>((size_t)h->S.N)));
     d.y = static_cast<double*>(keep(dmalloc<double>((size_t)h->S.N * kMaxRhs)));
     d.tbuf = static_cast<double*>(keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc->tbuf_per_rhs) * kMaxRhs)));
     const size_t nflags = 2 * (size_t)sc->L + sc->tprod.size() + sc->dense.size() + 1;
@@ -378,6 +385,18 @@ hipError_t gather_y(hlu_s* h, const double* b, int64_t ld, int32_t nc, hipStream
   return gather_launch<double>(h->S.N, nc, h->d_perm, b, ld, h->sdev.y, h->S.N, s);
 }
 
+// Adds the durations of the recorded event pairs to the timing totals.
+void harvest_timing(hlu_s* h) {
+  for (size_t i = 0; i + 1 < h->tev_used; i += 2) {
+    HIP_OK(hipEventSynchronize(h->tev[i + 1]));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, h->tev[i], h->tev[i + 1]));
+    h->stats.solve_launches += 1;
+    h->stats.solve_kernel_ms += ms;
+  }
+  h->tev_used = 0;
+}
+
 // x = P^T U^{-1} L^{-1} P b with the persistent solve kernel (FP64 vectors).
 template <class T>
 void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, int64_t ld, hipStream_t s) {
@@ -390,7 +409,21 @@ void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, i
     const int32_t nc = std::min(kMaxRhs, nrhs - c0);
     HIP_OK(gather_y<T>(h, b + (int64_t)c0 * ld, ld, nc, s));
     h->solve_epoch = h->solve_epoch % 1000000000 + 1;
+    if (h->timing) {
+      if (h->tev_used + 2 > kMaxTimedEvents) harvest_timing(h);
+      while (h->tev.size() < h->tev_used + 2) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        h->tev.push_back(e);
+      }
+      HIP_OK(hipEventRecord(h->tev[h->tev_used], s));
+    }
     HIP_OK(solve_persistent_launch<T>(arena, dims, h->sdev, N, nc, h->solve_epoch, grid, s));
+    if (h->timing) {
+      HIP_OK(hipEventRecord(h->tev[h->tev_used + 1], s));
+      h->tev_used += 2;
+      h->stats.solve_columns += nc;
+    }
     HIP_OK(scatter_perm_launch<double>(N, nc, h->d_perm, h->sdev.y, N, x + (int64_t)c0 * ld, ld, s));
     if (h->sdev.trace) {   // debug: dump task clocks and kinds
       HIP_OK(hipStreamSynchronize(s));
@@ -431,6 +464,15 @@ void gather_stats(hlu_s* h) {
   h->stats.max_rank = maxr;
   h->stats.mean_rank = nlr ? sumr / nlr : 0.0;
   h->stats.lowrank_entries = lr_entries;
+  std::vector<double> piv(S.N);
+  HIP_OK(hipMemcpy(piv.data(), h->sdev.pivots, piv.size() * sizeof(double), hipMemcpyDeviceToHost));
+  double lo = INFINITY, hi = 0.0;
+  for (double p : piv) {
+    lo = std::min(lo, std::fabs(p));
+    hi = std::max(hi, std::fabs(p));
+  }
+  h->stats.min_abs_pivot = lo;
+  h->stats.max_abs_pivot = hi;
 }
 
 void fill_structure_stats(hlu_s* h) {
@@ -868,7 +910,19 @@ hlu_status hlu_get_ranks(hlu_handle h, int32_t* ranks) {
 hlu_status hlu_get_stats(hlu_handle h, hlu_stats* out) {
   return guard([&] {
     HLU_REQUIRE(h && out, HLU_ERR_INVALID_ARG, "hlu_get_stats: NULL argument");
+    harvest_timing(h);
     *out = h->stats;
+  });
+}
+
+hlu_status hlu_set_timing(hlu_handle h, int32_t enable) {
+  return guard([&] {
+    HLU_REQUIRE(h, HLU_ERR_INVALID_ARG, "hlu_set_timing: NULL handle");
+    harvest_timing(h);
+    h->timing = enable != 0;
+    h->stats.solve_launches = 0;
+    h->stats.solve_columns = 0;
+    h->stats.solve_kernel_ms = 0.0;
   });
 }
 

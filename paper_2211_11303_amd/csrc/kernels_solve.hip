@@ -451,7 +451,8 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
 // with the diagonal, so both share one m x m block.  Columns of the identity
 // are solved in chunks of `cols` in LDS by column-oriented substitution.
 template <class T>
-__global__ void __launch_bounds__(256) diag_inverse_kernel(const T* arena, const SLeaf* leaves, T* inv, int cols) {
+__global__ void __launch_bounds__(256) diag_inverse_kernel(const T* arena, const SLeaf* leaves, T* inv,
+                                                           double* pivots, int cols) {
   extern __shared__ double sm[];
   const SLeaf lf = leaves[blockIdx.x];
   const int m = lf.m;
@@ -459,6 +460,8 @@ __global__ void __launch_bounds__(256) diag_inverse_kernel(const T* arena, const
   double* Ts = sm;            // m x m, column-major
   double* Vs = sm + m * m;    // m x cols, row i at Vs[i * cols]
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) Ts[e] = double(arena[lf.diag + e]);
+  if (upper)
+    for (int q = threadIdx.x; q < m; q += blockDim.x) pivots[lf.row0 + q] = double(arena[lf.diag + q + (int64_t)q * m]);
   for (int c0 = 0; c0 < m; c0 += cols) {
     const int pc = min(cols, m - c0);
     for (int e = threadIdx.x; e < m * pc; e += blockDim.x) {
@@ -536,7 +539,7 @@ hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s)
     attr = true;
   }
   dim3 g(d.L, 2);
-  dev::diag_inverse_kernel<T><<<g, 256, sh, s>>>(arena, d.leaves, static_cast<T*>(d.inv), cols);
+  dev::diag_inverse_kernel<T><<<g, 256, sh, s>>>(arena, d.leaves, static_cast<T*>(d.inv), d.pivots, cols);
   return hipGetLastError();
 }
 

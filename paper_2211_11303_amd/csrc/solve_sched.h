@@ -81,6 +81,7 @@ struct SolveDev {
   const SLow* low;
   const STprod* tprod;
   void* inv;            // triangle inverses of the diagonal leaves (factor storage type)
+  double* pivots;       // U_ii of every diagonal leaf, cluster order (N)
   double* y;
   double* tbuf;
   int32_t* leaf_flag;
@@ -96,7 +97,8 @@ struct SolveDev {
 };
 
 // Both triangle inverses of every diagonal leaf (arena storage type T,
-// arithmetic in FP64), written to d.inv; run after each factorization.
+// arithmetic in FP64), written to d.inv, and the pivots U_ii to d.pivots;
+// run after each factorization.
 template <class T>
 hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s);
 

@@ -176,6 +176,12 @@ class HLU:
         L.check(L.lib().hlu_get_stats(self.handle, ctypes.byref(s)))
         return s.as_dict()
 
+    def hlu_set_timing(self, enable=True):
+        """Bracket every persistent solve launch with HIP events (resets the
+        totals that hlu_get_stats reports as solve_launches / solve_kernel_ms)."""
+        L.check(L.lib().hlu_set_timing(self.handle, 1 if enable else 0))
+        return self
+
     def hlu_get_ranks(self):
         nb = self.structure_sizes()[2]
         r = np.empty(nb, np.int32)

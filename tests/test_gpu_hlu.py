@@ -72,6 +72,13 @@ def test_untruncated_is_exact(gpu):
     H = hlu.HLU(rp, ci, va, mid, 2.0, 32).hlu_factor(0.0, prec="fp64")
     d, s = oracle_problem(4, 2.0, 32)
     assert gpu_factor_error(H, d.A, s.perm) <= 1e-9
+    # untruncated unpivoted H-LU = dense unpivoted LU of P A P^T: same pivots
+    from oracle.hmatrix import getrf_nopiv
+    Ap = d.A.toarray()[np.ix_(s.perm, s.perm)]
+    piv = np.abs(np.diag(getrf_nopiv(Ap)))
+    st = H.hlu_get_stats()
+    assert abs(st["min_abs_pivot"] - piv.min()) <= 1e-9 * piv.max()
+    assert abs(st["max_abs_pivot"] - piv.max()) <= 1e-9 * piv.max()
 
 
 @pytest.mark.parametrize("n,leaf,eps", [(5, 20, 1e-4), (4, 8, 1e-4), (3, 4, 1e-3)])
@@ -147,3 +154,22 @@ def test_persistent_solve_matches_wave_solve(gpu, n, leaf, prec, monkeypatch):
             torch.cuda.synchronize()
             assert torch.isfinite(z_p).all()
             assert (z_p - z_w).norm() <= tol * z_w.norm(), (nrhs, rep, (z_p - z_w).norm().item(), z_w.norm().item())
+
+
+def test_solve_timing_counts_launches(gpu):
+    """hlu_set_timing brackets each persistent solve launch (at most 32
+    columns each) with events; hlu_get_stats reports count, columns, time."""
+    import torch
+    hlu, inputs = _lib()
+    A, (rp, ci, va, mid) = _setup(4, 2.0, 32)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, 32).hlu_factor(1e-6, prec="fp64")
+    H.hlu_set_timing(True)
+    for nrhs in (5, 33):
+        H.hlu_solve(torch.tensor(inputs.exact_solution_cols(A.n, nrhs, seed=1), device="cuda"))
+    st = H.hlu_get_stats()
+    assert st["solve_launches"] == 3 and st["solve_columns"] == 38
+    assert st["solve_kernel_ms"] > 0
+    H.hlu_set_timing(False)
+    H.hlu_solve(torch.tensor(inputs.exact_solution_cols(A.n, 2, seed=1), device="cuda"))
+    st = H.hlu_get_stats()
+    assert st["solve_launches"] == 0 and st["solve_columns"] == 0
