@@ -42,6 +42,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-level", type=int, default=5,
                    help="cluster-tree level of the principal block the oracle sample factors")
+    p.add_argument("--batch", action="store_true",
+                   help="batched workload instead: 64 problems (8^3..24^3, kappa in [1, 10]) factored and "
+                        "solved as one batch, against the same problems run one by one")
+    p.add_argument("--batch-count", type=int, default=64)
+    p.add_argument("--batch-max-rank", type=int, default=32,
+                   help="rank capacity per low-rank block in the batched workload")
     return p.parse_args()
 
 
@@ -103,6 +109,107 @@ def cpu_baseline(n, kappa, leaf, eps, restart, tol, level):
     }
 
 
+def batch_main(args):
+    """Batched workload: problems (n, kappa) from inputs.batch_problems
+    (default_rng(7)), FP32 H-LU (eps 1e-3, rank capacity 32), FP64 GMRES(50)
+    to 1e-8 with one right-hand side each (x* seed = problem index).  Timed:
+    (a) one by one -- hlu_factor + gmres_solve per problem; (b) as one batch
+    -- hlu_factor_batch + gmres_solve_batch.  Structures are planned once
+    per mesh size before either timed region (host work shared by both)."""
+    import numpy as np
+    import torch
+    from paper_2211_11303_amd import hlu, inputs
+
+    torch.cuda.set_device(0)
+    eps, mr, prec = 1e-3, args.batch_max_rank, "fp32"
+    probs = inputs.batch_problems(args.batch_count, seed=7)
+    t = time.perf_counter()
+    data = [(n, kappa) + tuple(hlu.hlu_kuhn_assemble(n, kappa)) for n, kappa in probs]
+    protos = {}
+    for n, kappa, rp, ci, va, mid in data:
+        if n not in protos:
+            log(f"planning {n}^3")
+            protos[n] = hlu.HLU(rp, ci, va, mid, 2.0, args.leaf)
+            protos[n].hlu_workspace_bytes(eps, mr, prec)
+    mats = [hlu.SpMat(rp, ci, va) for _, _, rp, ci, va, _ in data]
+    xs = [torch.tensor(inputs.exact_solution_cols(A.n, 1, seed=p), device="cuda") for p, A in enumerate(mats)]
+    bs = [A.hlu_spmv(x) for A, x in zip(mats, xs)]
+    # device copies of the plans (first factorisation of each structure)
+    for n, H in protos.items():
+        H.hlu_factor(eps, mr, prec, allow_overflow=True)
+        H.work = None
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+
+    def handles():
+        return [hlu.HLU(rp, ci, va, share=protos[n]) for n, _, rp, ci, va, _ in data]
+
+    log("one by one")
+    seq = handles()
+    iters_seq, relres_seq = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, H in enumerate(seq):
+        H.hlu_factor(eps, mr, prec, allow_overflow=True)
+        x, info = hlu.gmres_solve(mats[p], bs[p], H, restart=args.restart, tol=args.tol, max_iters=1000,
+                                  raise_on_fail=False)
+        iters_seq.append(info[0]["iters"])
+        relres_seq.append(info[0]["relres"])
+        seq[p] = None   # frees the workspace and solve buffers
+    torch.cuda.synchronize()
+    T_seq = time.perf_counter() - t0
+
+    log("batched")
+    members = handles()
+    t1 = time.perf_counter()
+    B = hlu.HLUBatch(members, eps, max_rank=mr, prec=prec, max_rhs=1)
+    B.hlu_batch_bind_workspace()
+    bstack = B.stack(bs)
+    torch.cuda.synchronize()
+    batch_setup_s = time.perf_counter() - t1
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    _, tf = event_time(lambda: B.hlu_factor_batch(allow_overflow=True), stream)
+    xb, infos = B.gmres_solve_batch(bstack, restart=args.restart, tol=args.tol, max_iters=1000,
+                                    raise_on_fail=False)
+    torch.cuda.synchronize()
+    T_bat = time.perf_counter() - t0
+    xparts = B.unstack(xb)
+    errs = [((xp - x).norm() / x.norm()).item() for xp, x in zip(xparts, xs)]
+    iters_b = [i[0]["iters"] for i in infos]
+    caps = max(m.hlu_get_stats()["capped_blocks"] for m in members)
+    line = {
+        "metric": "batched H-LU + GMRES: problems solved per second (factor + GMRES(50) to 1e-8, 1 rhs each)",
+        "value": args.batch_count / T_bat,
+        "unit": "problems/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32-hlu+f64-gmres",
+        "data": "synthetic",
+        "config": {"workload": f"{args.batch_count} Kuhn-cube problems, n in {{8,12,16,20,24}} and kappa in "
+                               f"[1,10] from default_rng(7); eta=2, leaf={args.leaf}, eps={eps:g}, "
+                               f"rank capacity {mr}; GMRES({args.restart}) to {args.tol:g}, 1 rhs each",
+                   "count": args.batch_count, "N_total": B.n_total, "leaf": args.leaf},
+        "one_by_one_problems_per_s": args.batch_count / T_seq,
+        "speedup_vs_one_by_one": T_seq / T_bat,
+        "batched_s": T_bat,
+        "one_by_one_s": T_seq,
+        "batched_factor_s": tf,
+        "batch_factor_waves": B.factor_waves,
+        "sum_member_factor_waves": sum(protos[n].hlu_get_stats()["factor_waves"] for n, *_ in data),
+        "iters_batched": [min(iters_b), max(iters_b)],
+        "iters_equal_one_by_one": iters_b == iters_seq,
+        "relres_max": max(i[0]["relres"] for i in infos),
+        "converged": all(i[0]["converged"] for i in infos),
+        "err_vs_xstar_max": max(errs),
+        "capped_blocks": caps,
+        "workspace_gb": B.hlu_batch_workspace_bytes() / 1e9,
+        "setup_s": setup_s,
+        "batch_setup_s": batch_setup_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,6 +217,8 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
               f"supported by this build", file=sys.stderr)
         sys.exit(2)
+    if args.batch:
+        return batch_main(args)
     import numpy as np
     import torch
     from paper_2211_11303_amd import hlu, inputs

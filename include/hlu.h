@@ -56,6 +56,7 @@ typedef enum { HLU_FP64 = 0, HLU_FP32 = 1 } hlu_precision;
 
 typedef struct hlu_spmat_s* hlu_spmat;  /* device CSR of A, for y = A x      */
 typedef struct hlu_s* hlu_handle;       /* structure + H-LU of one problem    */
+typedef struct hlu_batch_s* hlu_batch;  /* independent problems run together  */
 
 /* Host CSR, 0-based, columns sorted ascending within each row. */
 typedef struct {
@@ -148,6 +149,17 @@ hlu_status hlu_spmv(hlu_spmat A, const double* d_x, double* d_y, int32_t nrhs, i
  * leaf_size indices); eta: admissibility parameter (min diam <= eta dist). */
 hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t leaf_size,
                      hlu_handle* out);
+
+/* A new handle for a matrix with exactly the sparsity pattern of proto's
+ * (same n, row_ptr and col; values may differ, e.g. another kappa on the
+ * same mesh).  It shares proto's cluster tree, block tree and task plans
+ * (read-only, reference-counted), so building it costs one pattern check.
+ * HLU_ERR_INVALID_ARG if the pattern differs. */
+hlu_status hlu_build_shared(hlu_handle proto, const hlu_csr* A, hlu_handle* out);
+
+/* Destroys the handle; its device buffers are freed, caller workspaces are
+ * not.  A handle destroyed while in a batch leaves the batch unusable
+ * (HLU_ERR_STATE) until hlu_batch_destroy. */
 void hlu_destroy(hlu_handle h);
 
 /* Device bytes hlu_factor needs for these options (plans the schedule). */
@@ -175,9 +187,10 @@ hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs,
 hlu_status hlu_apply_lu(hlu_handle h, const double* d_v, double* d_y, int32_t nrhs, int64_t ld,
                         void* stream);
 
-/* Restarted right-preconditioned flexible GMRES (Sec. 4), x0 = 0, modified
- * Gram-Schmidt, FP64 throughout; precond may be NULL.  Each of the nrhs
- * columns is solved independently (iterations batched across columns).
+/* Restarted right-preconditioned flexible GMRES (Sec. 4), x0 = 0,
+ * classical Gram-Schmidt applied twice, FP64 throughout; precond may be
+ * NULL.  Each of the nrhs columns is solved independently (its own Arnoldi
+ * process; operator and preconditioner applied to all columns per launch).
  * info: host array of nrhs entries.  d_work: caller-owned device buffer of
  * gmres_workspace_bytes(n, nrhs, restart) bytes.  Synchronises the stream.
  * Returns HLU_ERR_NOT_CONVERGED if any column missed tol (x then holds the
@@ -186,6 +199,59 @@ size_t gmres_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart);
 hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
                        hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info,
                        void* d_work, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ batch
+ * Independent problems (each an hlu_handle, of any size) factored and solved
+ * together: every launch of the batch factorisation runs the ready tasks of
+ * all problems, and one persistent launch runs the H-solves of all problems.
+ * Results equal those of the problems factored and solved one by one (the
+ * same tasks in the same per-problem order).
+ *
+ * hlu_batch_create: hs[count] distinct handles not in another batch; o: the
+ * options of every factorisation; max_rhs (1..32): columns per problem of
+ * hlu_solve_batch / gmres_solve_batch.  Plans each distinct structure once
+ * (host work); the handles stay owned by the caller and must outlive the
+ * batch.  After hlu_factor_batch every member is factored and usable on its
+ * own (hlu_solve, gmres_solve), with its factor inside the batch workspace.
+ *
+ * Stacked vectors: problem p occupies rows [row_base[p], row_base[p] + N_p)
+ * of a column of n_total rows (natural order within the problem); a block
+ * holds nrhs such columns, leading dimension n_total. */
+hlu_status hlu_batch_create(const hlu_handle* hs, int32_t count, const hlu_factor_opts* o,
+                            int32_t max_rhs, hlu_batch* out);
+void hlu_batch_destroy(hlu_batch b);
+
+/* count, n_total, row_base[count] (host, may be NULL) and the size of the
+ * merged factor schedule (waves, tasks). */
+hlu_status hlu_batch_sizes(hlu_batch b, int32_t* count, int32_t* n_total, int32_t* row_base,
+                           int64_t* factor_waves, int64_t* factor_tasks);
+
+/* Device bytes of the batch workspace (all factors, rank tables, status). */
+hlu_status hlu_batch_workspace_bytes(hlu_batch b, size_t* bytes);
+/* Caller-owned, 256-byte aligned, at least the bytes above; replaces the
+ * members' own workspaces for as long as the batch lives. */
+hlu_status hlu_batch_bind_workspace(hlu_batch b, void* d_work, size_t bytes);
+
+/* Algorithm 1, step II for every member, as one merged wave schedule.
+ * Synchronises the stream; HLU_ERR_ZERO_PIVOT / HLU_ERR_RANK_OVERFLOW as
+ * for hlu_factor (for the batch as a whole). */
+hlu_status hlu_factor_batch(hlu_batch b, void* stream);
+
+/* Algorithm 1, step III for every member in one persistent launch: d_b, d_x
+ * stacked device blocks of nrhs <= max_rhs columns (leading dimension
+ * n_total; must not overlap).  Stream-ordered. */
+hlu_status hlu_solve_batch(hlu_batch b, const double* d_b, double* d_x, int32_t nrhs, void* stream);
+
+/* gmres_solve for every member at once: stacked d_b, d_x (nrhs <= max_rhs
+ * columns, leading dimension n_total, no overlap); each (problem, column)
+ * is an independent system with its own Arnoldi process, preconditioned by
+ * the member's H-LU.  info: host array of count * nrhs entries, entry
+ * c * count + p for problem p, column c.  d_work: caller-owned device
+ * buffer of gmres_batch_workspace_bytes(b, nrhs, restart) bytes. */
+size_t gmres_batch_workspace_bytes(hlu_batch b, int32_t nrhs, int32_t restart);
+hlu_status gmres_solve_batch(hlu_batch b, const double* d_b, double* d_x, int32_t nrhs,
+                             const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work,
+                             size_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------ inspection */
 /* Sizes of the structure arrays, then a copy of them into caller-allocated

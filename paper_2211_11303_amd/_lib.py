@@ -20,6 +20,7 @@ STATUS = {
     -4: "HLU_ERR_ZERO_PIVOT", -5: "HLU_ERR_NOT_CONVERGED", -6: "HLU_ERR_STATE",
     -7: "HLU_ERR_RANK_OVERFLOW", -8: "HLU_ERR_UNSUPPORTED",
 }
+STATUS_CODES = {v: k for k, v in STATUS.items()}
 HLU_FP64, HLU_FP32 = 0, 1
 
 
@@ -79,6 +80,19 @@ SIGNATURES = {
     "hlu_get_ranks": (c_int32, [c_void_p, P_i32]),
     "hlu_get_stats": (c_int32, [c_void_p, ctypes.POINTER(Stats)]),
     "hlu_set_timing": (c_int32, [c_void_p, c_int32]),
+    "hlu_build_shared": (c_int32, [c_void_p, ctypes.POINTER(HluCsr), ctypes.POINTER(c_void_p)]),
+    "hlu_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(FactorOpts), c_int32,
+                                   ctypes.POINTER(c_void_p)]),
+    "hlu_batch_destroy": (None, [c_void_p]),
+    "hlu_batch_sizes": (c_int32, [c_void_p, P_i32, P_i32, P_i32, ctypes.POINTER(c_int64),
+                                  ctypes.POINTER(c_int64)]),
+    "hlu_batch_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "hlu_batch_bind_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "hlu_factor_batch": (c_int32, [c_void_p, c_void_p]),
+    "hlu_solve_batch": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "gmres_batch_workspace_bytes": (c_size_t, [c_void_p, c_int32, c_int32]),
+    "gmres_solve_batch": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(GmresOpts),
+                                    ctypes.POINTER(GmresInfo), c_void_p, c_size_t, c_void_p]),
 }
 
 _lib = None

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhlu.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mesh.cpp", "structure.cpp", "plan.cpp", "solve_sched.cpp", "api.cpp", "kernels_hlu.hip",
+SOURCES = ["mesh.cpp", "structure.cpp", "plan.cpp", "solve_sched.cpp", "api.cpp", "gmres.cpp", "batch.cpp",
+           "kernels_hlu.hip",
            "kernels_vec.hip", "kernels_solve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,249 @@
+// Restarted flexible GMRES (Algorithm 1, step III with a Krylov method in
+// place of the plain iteration): right preconditioning, x0 = 0, classical
+// Gram-Schmidt applied twice, Givens rotations on the host, convergence on
+// the true residual at the end of each cycle.
+//
+// The driver runs nseg independent systems at once.  Every vector block
+// holds one segment per system; dot products, norms and updates are
+// segment-wise, so each system keeps its own Arnoldi process, while the
+// operator and preconditioner are applied to the whole block in one launch
+// (the columns of one matrix, or the problems of a batch).
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "gmres.h"
+
+namespace hlu {
+
+size_t gmres_core_bytes(int64_t total, int32_t nseg, int32_t m) {
+  const size_t blk = align256((size_t)total * sizeof(double));
+  size_t b = 0;
+  b += blk * (size_t)(m + 1);   // V
+  b += blk * (size_t)m;         // Z
+  b += blk;                     // w
+  b += align256((size_t)kDotBlocks * (m + 1) * nseg * sizeof(double));   // partial dots
+  b += align256((size_t)(m + 1) * nseg * sizeof(double)) * 3;            // h, h2, y / scale
+  b += align256((size_t)nseg * sizeof(int64_t)) * 2;                     // segment offsets, lengths
+  return b;
+}
+
+void gmres_core(const GmresSystem& sys, const double* b, double* x, const hlu_gmres_opts* o, void* d_work,
+                hlu_gmres_info* info, hipStream_t s) {
+  const int32_t nseg = sys.nseg, m = o->restart;
+  const size_t blk = align256((size_t)sys.total * sizeof(double));
+  const int64_t vstride = (int64_t)(blk / sizeof(double));
+  char* wp = static_cast<char*>(d_work);
+  double* V = reinterpret_cast<double*>(wp);
+  wp += blk * (m + 1);
+  double* Z = reinterpret_cast<double*>(wp);
+  wp += blk * m;
+  double* w = reinterpret_cast<double*>(wp);
+  wp += blk;
+  double* part = reinterpret_cast<double*>(wp);
+  wp += align256((size_t)kDotBlocks * (m + 1) * nseg * sizeof(double));
+  double* dh = reinterpret_cast<double*>(wp);
+  wp += align256((size_t)(m + 1) * nseg * sizeof(double));
+  double* dh2 = reinterpret_cast<double*>(wp);
+  wp += align256((size_t)(m + 1) * nseg * sizeof(double));
+  double* dy = reinterpret_cast<double*>(wp);
+  wp += align256((size_t)(m + 1) * nseg * sizeof(double));
+  int64_t* doff = reinterpret_cast<int64_t*>(wp);
+  wp += align256((size_t)nseg * sizeof(int64_t));
+  int64_t* dlen = reinterpret_cast<int64_t*>(wp);
+  HIP_OK(hipMemcpyAsync(doff, sys.off.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dlen, sys.len.data(), nseg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  int64_t max_len = 1;
+  for (int64_t l : sys.len) max_len = std::max(max_len, l);
+
+  auto norms = [&](const double* vec, std::vector<double>* out) {
+    HIP_OK(seg_dot_launch(nseg, doff, dlen, 1, vec, vstride, vec, part, dh, s));
+    std::vector<double> t(nseg);
+    HIP_OK(hipMemcpyAsync(t.data(), dh, nseg * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    out->resize(nseg);
+    for (int c = 0; c < nseg; ++c) (*out)[c] = std::sqrt(std::max(0.0, t[c]));
+  };
+  // x = 0; residual r = b (in w)
+  HIP_OK(hipMemsetAsync(x, 0, (size_t)sys.total * sizeof(double), s));
+  HIP_OK(hipMemcpyAsync(w, b, (size_t)sys.total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> bnorm, rnorm;
+  norms(w, &bnorm);
+  rnorm = bnorm;
+  std::vector<int32_t> iters(nseg, 0);
+  std::vector<char> conv(nseg, 0);
+  for (int c = 0; c < nseg; ++c)
+    if (bnorm[c] == 0.0 || rnorm[c] <= o->tol * bnorm[c]) conv[c] = 1;
+  std::vector<double> H((size_t)(m + 1) * m * nseg), cs((size_t)m * nseg), sn((size_t)m * nseg);
+  std::vector<double> g((size_t)(m + 1) * nseg), hcol((size_t)(m + 1) * nseg), hcol2((size_t)(m + 1) * nseg);
+  std::vector<double> scale(nseg), yv((size_t)m * nseg);
+  auto Hc = [&](int i, int j, int c) -> double& { return H[((size_t)c * (m + 1) + i) * m + j]; };
+  while (true) {
+    bool any = false;
+    for (int c = 0; c < nseg; ++c)
+      if (!conv[c] && iters[c] < o->max_iters) any = true;
+    if (!any) break;
+    // V_0 = r / ||r||  (r in w)
+    for (int c = 0; c < nseg; ++c) scale[c] = (rnorm[c] > 0.0) ? 1.0 / rnorm[c] : 0.0;
+    HIP_OK(hipMemcpyAsync(dy, scale.data(), nseg * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(seg_scale_launch(nseg, doff, dlen, max_len, w, dy, V, s));
+    std::vector<char> active(nseg, 0);
+    std::vector<int> jend(nseg, 0);
+    for (int c = 0; c < nseg; ++c) {
+      active[c] = !conv[c] && iters[c] < o->max_iters;
+      for (int i = 0; i <= m; ++i) g[(size_t)c * (m + 1) + i] = 0.0;
+      g[(size_t)c * (m + 1)] = rnorm[c];
+    }
+    for (int j = 0; j < m; ++j) {
+      bool act = false;
+      for (int c = 0; c < nseg; ++c) act = act || active[c];
+      if (!act) break;
+      double* Vj = V + (int64_t)j * vstride;
+      double* Zj = Z + (int64_t)j * vstride;
+      sys.precond(Vj, Zj);
+      sys.matvec(Zj, w);
+      // classical Gram-Schmidt, twice
+      HIP_OK(seg_dot_launch(nseg, doff, dlen, j + 1, V, vstride, w, part, dh, s));
+      HIP_OK(seg_orth_launch(nseg, doff, dlen, max_len, j + 1, V, vstride, dh, w, s));
+      HIP_OK(seg_dot_launch(nseg, doff, dlen, j + 1, V, vstride, w, part, dh2, s));
+      HIP_OK(seg_orth_launch(nseg, doff, dlen, max_len, j + 1, V, vstride, dh2, w, s));
+      HIP_OK(hipMemcpyAsync(hcol.data(), dh, (size_t)(j + 1) * nseg * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipMemcpyAsync(hcol2.data(), dh2, (size_t)(j + 1) * nseg * sizeof(double), hipMemcpyDeviceToHost, s));
+      std::vector<double> wn;
+      norms(w, &wn);
+      for (int c = 0; c < nseg; ++c) {
+        scale[c] = 0.0;
+        if (!active[c]) continue;
+        for (int i = 0; i <= j; ++i) Hc(i, j, c) = hcol[(size_t)i * nseg + c] + hcol2[(size_t)i * nseg + c];
+        Hc(j + 1, j, c) = wn[c];
+        scale[c] = wn[c] > 0.0 ? 1.0 / wn[c] : 0.0;
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[(size_t)c * m + i] * Hc(i, j, c) + sn[(size_t)c * m + i] * Hc(i + 1, j, c);
+          Hc(i + 1, j, c) = -sn[(size_t)c * m + i] * Hc(i, j, c) + cs[(size_t)c * m + i] * Hc(i + 1, j, c);
+          Hc(i, j, c) = t;
+        }
+        const double den = std::hypot(Hc(j, j, c), Hc(j + 1, j, c));
+        cs[(size_t)c * m + j] = den > 0.0 ? Hc(j, j, c) / den : 1.0;
+        sn[(size_t)c * m + j] = den > 0.0 ? Hc(j + 1, j, c) / den : 0.0;
+        Hc(j, j, c) = den;
+        Hc(j + 1, j, c) = 0.0;
+        double* gc = &g[(size_t)c * (m + 1)];
+        gc[j + 1] = -sn[(size_t)c * m + j] * gc[j];
+        gc[j] = cs[(size_t)c * m + j] * gc[j];
+        iters[c]++;
+        jend[c] = j + 1;
+        if (std::fabs(gc[j + 1]) <= o->tol * bnorm[c] || iters[c] >= o->max_iters || den == 0.0) active[c] = 0;
+      }
+      HIP_OK(hipMemcpyAsync(dy, scale.data(), nseg * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_OK(seg_scale_launch(nseg, doff, dlen, max_len, w, dy, V + (int64_t)(j + 1) * vstride, s));
+    }
+    // y = H^{-1} g per system, x += Z y
+    int jmax = 0;
+    for (int c = 0; c < nseg; ++c) jmax = std::max(jmax, jend[c]);
+    std::fill(yv.begin(), yv.end(), 0.0);
+    for (int c = 0; c < nseg; ++c) {
+      const int je = jend[c];
+      for (int i = je - 1; i >= 0; --i) {
+        double t = g[(size_t)c * (m + 1) + i];
+        for (int k = i + 1; k < je; ++k) t -= Hc(i, k, c) * yv[(size_t)k * nseg + c];
+        yv[(size_t)i * nseg + c] = Hc(i, i, c) != 0.0 ? t / Hc(i, i, c) : 0.0;
+      }
+    }
+    if (jmax > 0) {
+      HIP_OK(hipMemcpyAsync(dh, yv.data(), (size_t)jmax * nseg * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_OK(seg_combine_launch(nseg, doff, dlen, max_len, jmax, Z, vstride, dh, x, s));
+    }
+    // true residual
+    sys.matvec(x, w);
+    HIP_OK(sub_launch(sys.total, b, w, s));
+    norms(w, &rnorm);
+    for (int c = 0; c < nseg; ++c)
+      if (!conv[c] && rnorm[c] <= o->tol * bnorm[c]) conv[c] = 1;
+    if (jmax == 0) break;
+  }
+  for (int c = 0; c < nseg; ++c) {
+    info[c].iters = iters[c];
+    info[c].converged = conv[c];
+    info[c].relres = bnorm[c] > 0.0 ? rnorm[c] / bnorm[c] : 0.0;
+    info[c].abs_res = rnorm[c];
+  }
+}
+
+void check_gmres_opts(const hlu_gmres_opts* o) {
+  HLU_REQUIRE(o != nullptr, HLU_ERR_INVALID_ARG, "gmres options are NULL");
+  HLU_REQUIRE(o->restart >= 1 && o->max_iters >= 1 && o->tol > 0.0, HLU_ERR_INVALID_ARG,
+              "gmres: need restart >= 1, max_iters >= 1, tol > 0");
+}
+
+}  // namespace hlu
+
+using namespace hlu;
+
+extern "C" {
+
+size_t gmres_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart) {
+  if (n <= 0 || nrhs <= 0 || restart <= 0) return 0;
+  const int64_t total = (int64_t)n * nrhs;
+  // + the right-hand side and the iterate, contiguous
+  return gmres_core_bytes(total, nrhs, restart) + 2 * align256((size_t)total * sizeof(double));
+}
+
+hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, hlu_handle precond,
+                       const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work, size_t work_bytes,
+                       void* stream) {
+  bool all_conv = true;
+  hlu_status st = guard([&] {
+    HLU_REQUIRE(A && d_b && d_x && o && info && d_work && nrhs >= 1 && ld >= A->n, HLU_ERR_INVALID_ARG,
+                "gmres_solve: bad arguments");
+    check_gmres_opts(o);
+    HLU_REQUIRE(d_b != d_x, HLU_ERR_INVALID_ARG, "gmres_solve: x must not alias b");
+    if (precond) {
+      HLU_REQUIRE(precond->factored, HLU_ERR_STATE, "gmres_solve: preconditioner not factored");
+      HLU_REQUIRE(precond->sh->S.N == A->n, HLU_ERR_INVALID_ARG, "gmres_solve: size mismatch");
+    }
+    const int32_t N = A->n;
+    const int64_t total = (int64_t)N * nrhs;
+    HLU_REQUIRE(work_bytes >= gmres_workspace_bytes(N, nrhs, o->restart), HLU_ERR_OUT_OF_MEMORY,
+                "gmres_solve: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* wp = static_cast<char*>(d_work);
+    double* bb = reinterpret_cast<double*>(wp);
+    wp += align256((size_t)total * sizeof(double));
+    double* xx = reinterpret_cast<double*>(wp);
+    wp += align256((size_t)total * sizeof(double));
+    HIP_OK(copy_cols_launch(N, nrhs, d_b, ld, bb, N, s));
+    GmresSystem sys;
+    sys.nseg = nrhs;
+    sys.total = total;
+    for (int c = 0; c < nrhs; ++c) {
+      sys.off.push_back((int64_t)c * N);
+      sys.len.push_back(N);
+    }
+    sys.matvec = [&](const double* in, double* out) {
+      HIP_OK(spmv_launch(N, A->rp, A->ci, A->val, in, out, nrhs, N, 1.0, 0.0, s));
+    };
+    sys.precond = [&](const double* in, double* out) {
+      if (precond) {
+        hlu_status ps = hlu_solve(precond, in, out, nrhs, N, s);
+        if (ps != HLU_OK) fail(ps, std::string("gmres_solve: preconditioner: ") + get_error());
+      } else {
+        HIP_OK(hipMemcpyAsync(out, in, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+    };
+    gmres_core(sys, bb, xx, o, wp, info, s);
+    HIP_OK(copy_cols_launch(N, nrhs, xx, N, d_x, ld, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int c = 0; c < nrhs; ++c)
+      if (!info[c].converged) all_conv = false;
+  });
+  if (st != HLU_OK) return st;
+  if (!all_conv) {
+    set_error("gmres_solve: not converged within max_iters");
+    return HLU_ERR_NOT_CONVERGED;
+  }
+  return HLU_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// Internal state of libhlu behind the opaque handles of include/hlu.h, and
+// the helpers shared by the C entry points (api.cpp), the batch driver
+// (batch.cpp) and the GMRES driver (gmres.cpp).
+//
+// Ownership: everything that depends only on the sparsity pattern and the
+// block tree (the tree itself, the task plans, the solve schedule, the
+// scatter targets) lives in a Shared object that every handle built on the
+// same pattern references, so equal meshes are planned once.  A handle owns
+// its matrix values, its factor state and the buffers of its own solves; the
+// factor itself lives in caller memory (a bound workspace, or a batch
+// workspace).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+#include "solve_sched.h"
+#include "structure.h"
+
+namespace hlu {
+
+constexpr int kDefaultCap = 64;             // rank capacity of a low-rank block
+constexpr int kMaxRhs = 32;                 // columns per solve launch
+constexpr int kDotBlocks = 256;             // blocks of the partial dot products
+constexpr size_t kMaxTimedEvents = 4096;    // event pairs kept before they are harvested
+// Gram-based truncation resolves singular values down to about
+// sqrt(K u) sigma_1; smaller ones are treated as zero.
+constexpr double kFloorRel = 1e-7;
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+inline size_t elem_size(int32_t prec) { return prec == HLU_FP32 ? sizeof(float) : sizeof(double); }
+
+template <class T>
+T* dmalloc(size_t n) {
+  if (n == 0) return nullptr;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) fail(HLU_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return static_cast<T*>(p);
+}
+
+template <class T>
+T* upload(const std::vector<T>& v) {
+  T* p = dmalloc<T>(v.size());
+  if (p) HIP_OK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+
+// Device memory freed with the owner.
+struct Owned {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* keep(T* p) {
+    ptrs.push_back((void*)p);
+    return p;
+  }
+  ~Owned() {
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+// Device copy of a plan's task arrays.
+struct DevArrays {
+  Owned mem;
+  DevPlan P{};
+  void load(const Plan& pl) {
+    P.getrf = mem.keep(upload(pl.getrf));
+    P.tri = mem.keep(upload(pl.tri));
+    P.gemm = mem.keep(upload(pl.gemm));
+    P.terms = mem.keep(upload(pl.terms));
+    P.trunc = mem.keep(upload(pl.trunc));
+    P.parts = mem.keep(upload(pl.parts));
+    P.fill = mem.keep(upload(pl.fill));
+    P.tile_op = mem.keep(upload(pl.gemm_tile_op));
+    P.tile_ij = mem.keep(upload(pl.gemm_tile_ij));
+  }
+};
+
+// Read-only device copy of a persistent-solve schedule.
+struct DevSched {
+  Owned mem;
+  const STask* tasks = nullptr;
+  const SLeaf* leaves = nullptr;
+  const SDense* dense = nullptr;
+  const SLow* low = nullptr;
+  const STprod* tprod = nullptr;
+  const int32_t* push0 = nullptr;
+  const int32_t* push_recs = nullptr;
+  void load(const SolveSched& sc) {
+    tasks = mem.keep(upload(sc.tasks));
+    leaves = mem.keep(upload(sc.leaves));
+    dense = mem.keep(upload(sc.dense));
+    low = mem.keep(upload(sc.low));
+    tprod = mem.keep(upload(sc.tprod));
+    push0 = mem.keep(upload(sc.push0));
+    push_recs = mem.keep(upload(sc.push_recs));
+  }
+};
+
+// Mutable buffers of persistent solves with a given schedule (columns per
+// launch <= max_rhs).
+struct SolveBufs {
+  Owned mem;
+  void* inv = nullptr;        // triangle inverses (sized for FP64)
+  double* pivots = nullptr;   // U_ii, cluster order
+  double* y = nullptr;        // N x max_rhs
+  double* tbuf = nullptr;
+  int32_t* flags = nullptr;   // 2L leaf flags, T-product flags, record flags
+  double* pbuf = nullptr;
+  int32_t* ctr = nullptr;
+  int64_t* trace = nullptr;   // debug clocks (HLU_DEBUG_SOLVE_TRACE)
+  int64_t pstride = 0;
+  int32_t max_rhs = 0;
+  int32_t epoch = 0;
+  void alloc(const SolveSched& sc, int32_t N, int32_t max_rhs);
+};
+
+// Kernel launch view of a schedule and its buffers.
+SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs& b);
+
+// Plans for one rank capacity, shared by the handles of one structure.
+// Host part built by get_bundle; device copies made by ensure_device.
+struct PlanBundle {
+  int32_t kcap = 0;
+  PlanSet ps;
+  SolveSched sc;
+  bool on_device = false;
+  DevArrays dfactor, dsolve, dapply;
+  DevSched dsc;
+  Owned mem;
+  int64_t* d_target = nullptr;   // arena element of every stored entry of A
+};
+
+struct Shared {
+  Structure S;
+  std::vector<int32_t> row_ptr, col;        // sparsity pattern of A (natural order)
+  std::vector<int32_t> nonzero_admissible;  // admissible leaves holding entries
+  int32_t max_leaf = 0;
+  Owned mem;
+  int32_t* d_perm = nullptr;
+  std::mutex mu;
+  std::map<int32_t, std::shared_ptr<PlanBundle>> bundles;
+};
+
+// Plans for capacity kcap (host work, built on first use; thread-safe).
+std::shared_ptr<PlanBundle> get_bundle(Shared& sh, int32_t kcap);
+// Device copies of the bundle's plans and schedule, the scatter targets and
+// the permutation (first call uploads; thread-safe).
+void ensure_device(Shared& sh, PlanBundle& pb);
+
+struct WorkLayout {
+  size_t arena_bytes, dims_off, status_off, total;
+};
+WorkLayout work_layout(const PlanSet& ps, int32_t prec);
+
+int32_t kcap_for(const hlu_factor_opts* o);
+void check_opts(const hlu_factor_opts* o);
+
+template <class F>
+hlu_status guard(F&& f) {
+  try {
+    f();
+    return HLU_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HLU_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return HLU_ERR_DEVICE;
+  }
+}
+
+// ------------------------------------------------------------ kernels
+template <class T>
+hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status, double eps,
+                       double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64, hipStream_t s);
+hipError_t spmv_launch(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
+                       double* y, int32_t nrhs, int64_t ld, double alpha, double beta, hipStream_t s);
+template <class T>
+hipError_t gather_launch(int32_t n, int32_t nrhs, const int32_t* perm, const double* src, int64_t lds, T* dst,
+                         int64_t ldd, hipStream_t s);
+template <class T>
+hipError_t scatter_perm_launch(int32_t n, int32_t nrhs, const int32_t* perm, const T* src, int64_t lds,
+                               double* dst, int64_t ldd, hipStream_t s);
+template <class T>
+hipError_t scatter_values_launch(int64_t nnz, const int64_t* target, const double* val, T* arena, hipStream_t s);
+template <class T>
+hipError_t zero_launch(T* p, int64_t n, hipStream_t s);
+template <class T>
+hipError_t identity_launch(T* p, int32_t n, hipStream_t s);
+hipError_t set_int_launch(int32_t* p, int32_t v, hipStream_t s);
+hipError_t zero_int_launch(int32_t* p, int32_t n, hipStream_t s);
+// segmented vector kernels of GMRES: nseg segments [off[c], off[c] + len[c])
+// of every vector block
+hipError_t seg_dot_launch(int32_t nseg, const int64_t* off, const int64_t* len, int32_t nv, const double* V,
+                          int64_t vstride, const double* w, double* part, double* out, hipStream_t s);
+hipError_t seg_orth_launch(int32_t nseg, const int64_t* off, const int64_t* len, int64_t max_len, int32_t nv,
+                           const double* V, int64_t vstride, const double* h, double* w, hipStream_t s);
+hipError_t seg_scale_launch(int32_t nseg, const int64_t* off, const int64_t* len, int64_t max_len,
+                            const double* src, const double* scale, double* dst, hipStream_t s);
+hipError_t seg_combine_launch(int32_t nseg, const int64_t* off, const int64_t* len, int64_t max_len, int32_t nz,
+                              const double* Z, int64_t zstride, const double* y, double* x, hipStream_t s);
+hipError_t sub_launch(int64_t n, const double* b, double* r, hipStream_t s);
+hipError_t copy_cols_launch(int32_t N, int32_t nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,
+                            hipStream_t s);
+
+}  // namespace hlu
+
+struct hlu_batch_s;
+
+struct hlu_spmat_s {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* val;
+};
+
+struct hlu_s {
+  std::shared_ptr<hlu::Shared> sh;
+  std::shared_ptr<hlu::PlanBundle> pb;   // plans of the capacity last asked for
+  std::vector<double> val;               // values of A (natural order, pattern of sh)
+  hlu::Owned mem;
+  double* d_val = nullptr;
+  // workspace bound by hlu_bind_workspace
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  hlu_batch_s* batch = nullptr;          // batch whose workspace holds this factor
+  // where the current factor lives (set when it is computed)
+  void* arena = nullptr;
+  int32_t* dims = nullptr;
+  int32_t* status = nullptr;
+  // own persistent solves
+  std::unique_ptr<hlu::SolveBufs> sbuf;
+  bool inv_ready = false;                // sbuf->inv holds this factor's inverses
+  // factor state
+  bool factored = false;
+  int32_t prec = HLU_FP64;
+  double eps = 0.0;
+  bool factor_compute64 = false;
+  hlu_stats stats{};
+  // optional timing of the persistent solve launches
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  size_t tev_used = 0;
+  ~hlu_s();
+};
+
+namespace hlu {
+// Factor-state helpers used by api.cpp and batch.cpp.
+void ensure_values(hlu_s* h);                       // d_val
+void ensure_targets(Shared& sh, PlanBundle& pb);    // pb.d_target
+void ensure_solve_bufs(hlu_s* h);                   // sbuf for pb's schedule
+template <class T>
+void factor_prepare(hlu_s* h, T* arena, int32_t* dims, hipStream_t s);   // A into the arena
+void gather_stats(hlu_s* h, const double* d_pivots);
+void harvest_timing(hlu_s* h);
+void record_factor(hlu_s* h, const hlu_factor_opts* o);
+void batch_forget(hlu_batch_s* b, hlu_s* h);        // a member handle is destroyed
+}  // namespace hlu

@@ -103,82 +103,85 @@ __global__ void zero_int_kernel(int32_t* p, int32_t n) {
 }
 
 // ---------------------------------------------------------------- GMRES
-// Partial dot products: for each column c < nrhs and each basis vector
-// i < nv: part[blk][i][c] = sum over this block's rows of V_i[:, c] w[:, c].
-// V_i is the block at V + i * vstride; columns have leading dimension N.
+// Every GMRES vector block holds nseg independent segments: segment c is
+// [off[c], off[c] + len[c]) (a column of one system, or one problem of a
+// batch).  Kernels run a grid (x, c): blockIdx.y picks the segment.
 constexpr int kDotBlocks = 256;
 
-__global__ void __launch_bounds__(256) multidot_kernel(int32_t N, int32_t nrhs, int32_t nv,
-                                                       const double* __restrict__ V, int64_t vstride,
-                                                       const double* __restrict__ w, double* __restrict__ part) {
+// part[blk][i][c] = sum over block blk's share of segment c of V_i w
+__global__ void __launch_bounds__(256) seg_dot_kernel(int32_t nseg, const int64_t* __restrict__ off,
+                                                      const int64_t* __restrict__ len, int32_t nv,
+                                                      const double* __restrict__ V, int64_t vstride,
+                                                      const double* __restrict__ w, double* __restrict__ part) {
   __shared__ double red[4];
-  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = blockIdx.x * per, r1 = min((int64_t)N, r0 + per);
-  for (int i = 0; i < nv; ++i)
-    for (int c = 0; c < nrhs; ++c) {
-      const double* v = V + i * vstride + (int64_t)c * N;
-      const double* ww = w + (int64_t)c * N;
-      double s = 0.0;
-      for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) s += v[r] * ww[r];
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-      __syncthreads();
-      if (threadIdx.x == 0)
-        part[((int64_t)blockIdx.x * nv + i) * nrhs + c] = red[0] + red[1] + red[2] + red[3];
-      __syncthreads();
-    }
+  const int c = blockIdx.y;
+  const int64_t o = off[c], n = len[c];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  for (int i = 0; i < nv; ++i) {
+    const double* v = V + i * vstride + o;
+    const double* ww = w + o;
+    double s = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) s += v[r] * ww[r];
+    for (int k = 32; k > 0; k >>= 1) s += __shfl_down(s, k, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[((int64_t)blockIdx.x * nv + i) * nseg + c] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
 }
 
 // out[i][c] = sum over blocks of part[blk][i][c], fixed order (deterministic)
-__global__ void finish_dot_kernel(int32_t nblk, int32_t nv, int32_t nrhs, const double* __restrict__ part,
+__global__ void finish_dot_kernel(int32_t nblk, int32_t nv, int32_t nseg, const double* __restrict__ part,
                                   double* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nv * nrhs) return;
+  if (e >= nv * nseg) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nv * nrhs + e];
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nv * nseg + e];
   out[e] = s;
 }
 
-// w[:, c] -= sum_i h[i][c] V_i[:, c]
-__global__ void orth_update_kernel(int32_t N, int32_t nrhs, int32_t nv, const double* __restrict__ V,
-                                   int64_t vstride, const double* __restrict__ h, double* __restrict__ w) {
-  const int64_t total = (int64_t)N * nrhs;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / N);
-    double s = w[e];
-    for (int i = 0; i < nv; ++i) s -= h[i * nrhs + c] * V[i * vstride + e];
-    w[e] = s;
+// w -= sum_i h[i][c] V_i on segment c
+__global__ void seg_orth_kernel(int32_t nseg, const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                                int32_t nv, const double* __restrict__ V, int64_t vstride,
+                                const double* __restrict__ h, double* __restrict__ w) {
+  const int c = blockIdx.y;
+  const int64_t o = off[c], n = len[c];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = w[o + r];
+    for (int i = 0; i < nv; ++i) s -= h[i * nseg + c] * V[i * vstride + o + r];
+    w[o + r] = s;
   }
 }
 
-// dst[:, c] = scale[c] * src[:, c]   (scale read on the device)
-__global__ void scale_cols_kernel(int32_t N, int32_t nrhs, const double* __restrict__ src,
-                                  const double* __restrict__ scale, double* __restrict__ dst) {
-  const int64_t total = (int64_t)N * nrhs;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
-    dst[e] = scale[e / N] * src[e];
+// dst = scale[c] src on segment c (scale read on the device)
+__global__ void seg_scale_kernel(int32_t nseg, const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                                 const double* __restrict__ src, const double* __restrict__ scale,
+                                 double* __restrict__ dst) {
+  const int c = blockIdx.y;
+  const int64_t o = off[c], n = len[c];
+  const double a = scale[c];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    dst[o + r] = a * src[o + r];
 }
 
-// x[:, c] (ld) += sum_i y[i][c] Z_i[:, c]
-__global__ void combine_kernel(int32_t N, int32_t nrhs, int32_t nz, const double* __restrict__ Z, int64_t zstride,
-                               const double* __restrict__ y, double* __restrict__ x, int64_t ldx) {
-  const int64_t total = (int64_t)N * nrhs;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / N), r = (int)(e % N);
+// x += sum_i y[i][c] Z_i on segment c
+__global__ void seg_combine_kernel(int32_t nseg, const int64_t* __restrict__ off, const int64_t* __restrict__ len,
+                                   int32_t nz, const double* __restrict__ Z, int64_t zstride,
+                                   const double* __restrict__ y, double* __restrict__ x) {
+  const int c = blockIdx.y;
+  const int64_t o = off[c], n = len[c];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int i = 0; i < nz; ++i) s += y[i * nrhs + c] * Z[i * zstride + e];
-    x[r + c * ldx] += s;
+    for (int i = 0; i < nz; ++i) s += y[i * nseg + c] * Z[i * zstride + o + r];
+    x[o + r] += s;
   }
 }
 
-// r[:, c] = b[:, c] - r[:, c]  (r holds A x on entry); b has leading dim ldb
-__global__ void residual_kernel(int32_t N, int32_t nrhs, const double* __restrict__ b, int64_t ldb,
-                                double* __restrict__ r) {
-  const int64_t total = (int64_t)N * nrhs;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / N), i = (int)(e % N);
-    r[e] = b[i + c * ldb] - r[e];
-  }
+// r = b - r  (r holds A x on entry)
+__global__ void sub_kernel(int64_t n, const double* __restrict__ b, double* __restrict__ r) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    r[e] = b[e] - r[e];
 }
 
 __global__ void copy_cols_kernel(int32_t N, int32_t nrhs, const double* __restrict__ src, int64_t lds,
@@ -257,30 +260,35 @@ INST(double)
 #undef INST
 
 // GMRES helpers
-hipError_t multidot_launch(int32_t N, int32_t nrhs, int32_t nv, const double* V, int64_t vstride, const double* w,
-                           double* part, double* out, hipStream_t s) {
-  dev::multidot_kernel<<<dev::kDotBlocks, 256, 0, s>>>(N, nrhs, nv, V, vstride, w, part);
-  const int e = nv * nrhs;
-  dev::finish_dot_kernel<<<(e + 255) / 256, 256, 0, s>>>(dev::kDotBlocks, nv, nrhs, part, out);
+static inline dim3 seg_grid(int32_t nseg, int64_t max_len) {
+  int64_t gx = (max_len + 255) / 256;
+  gx = gx < 1 ? 1 : (gx > 1024 ? 1024 : gx);
+  return dim3((unsigned)gx, (unsigned)nseg);
+}
+hipError_t seg_dot_launch(int32_t nseg, const int64_t* off, const int64_t* len, int32_t nv, const double* V,
+                          int64_t vstride, const double* w, double* part, double* out, hipStream_t s) {
+  dev::seg_dot_kernel<<<dim3(dev::kDotBlocks, nseg), 256, 0, s>>>(nseg, off, len, nv, V, vstride, w, part);
+  const int e = nv * nseg;
+  dev::finish_dot_kernel<<<(e + 255) / 256, 256, 0, s>>>(dev::kDotBlocks, nv, nseg, part, out);
   return hipGetLastError();
 }
-hipError_t orth_update_launch(int32_t N, int32_t nrhs, int32_t nv, const double* V, int64_t vstride, const double* h,
-                              double* w, hipStream_t s) {
-  dev::orth_update_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, nv, V, vstride, h, w);
+hipError_t seg_orth_launch(int32_t nseg, const int64_t* off, const int64_t* len, int64_t max_len, int32_t nv,
+                           const double* V, int64_t vstride, const double* h, double* w, hipStream_t s) {
+  dev::seg_orth_kernel<<<seg_grid(nseg, max_len), 256, 0, s>>>(nseg, off, len, nv, V, vstride, h, w);
   return hipGetLastError();
 }
-hipError_t scale_cols_launch(int32_t N, int32_t nrhs, const double* src, const double* scale, double* dst,
-                             hipStream_t s) {
-  dev::scale_cols_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, src, scale, dst);
+hipError_t seg_scale_launch(int32_t nseg, const int64_t* off, const int64_t* len, int64_t max_len,
+                            const double* src, const double* scale, double* dst, hipStream_t s) {
+  dev::seg_scale_kernel<<<seg_grid(nseg, max_len), 256, 0, s>>>(nseg, off, len, src, scale, dst);
   return hipGetLastError();
 }
-hipError_t combine_launch(int32_t N, int32_t nrhs, int32_t nz, const double* Z, int64_t zstride, const double* y,
-                          double* x, int64_t ldx, hipStream_t s) {
-  dev::combine_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, nz, Z, zstride, y, x, ldx);
+hipError_t seg_combine_launch(int32_t nseg, const int64_t* off, const int64_t* len, int64_t max_len, int32_t nz,
+                              const double* Z, int64_t zstride, const double* y, double* x, hipStream_t s) {
+  dev::seg_combine_kernel<<<seg_grid(nseg, max_len), 256, 0, s>>>(nseg, off, len, nz, Z, zstride, y, x);
   return hipGetLastError();
 }
-hipError_t residual_launch(int32_t N, int32_t nrhs, const double* b, int64_t ldb, double* r, hipStream_t s) {
-  dev::residual_kernel<<<grid_for((int64_t)N * nrhs), 256, 0, s>>>(N, nrhs, b, ldb, r);
+hipError_t sub_launch(int64_t n, const double* b, double* r, hipStream_t s) {
+  dev::sub_kernel<<<grid_for(n), 256, 0, s>>>(n, b, r);
   return hipGetLastError();
 }
 hipError_t copy_cols_launch(int32_t N, int32_t nrhs, const double* src, int64_t lds, double* dst, int64_t ldd,

@@ -103,16 +103,22 @@ class SpMat:
 class HLU:
     """hlu_build + workspace + hlu_factor / hlu_solve / hlu_apply_lu."""
 
-    def __init__(self, row_ptr, col, val, mid2, eta=2.0, leaf=64):
+    def __init__(self, row_ptr, col, val, mid2=None, eta=2.0, leaf=64, share=None):
+        """hlu_build; with share=<HLU of the same sparsity pattern>,
+        hlu_build_shared (mid2, eta and leaf are then the prototype's)."""
         self._rp = np.ascontiguousarray(row_ptr, np.int32)
         self._ci = np.ascontiguousarray(col, np.int32)
         self._va = np.ascontiguousarray(val, np.float64)
-        mid = np.ascontiguousarray(mid2, np.int32)
         csr = L.HluCsr(len(self._rp) - 1, len(self._ci), _ptr(self._rp, ctypes.c_int32),
                        _ptr(self._ci, ctypes.c_int32), _ptr(self._va, ctypes.c_double))
         h = ctypes.c_void_p()
-        L.check(L.lib().hlu_build(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), float(eta), int(leaf),
-                                  ctypes.byref(h)))
+        if share is not None:
+            L.check(L.lib().hlu_build_shared(share.handle, ctypes.byref(csr), ctypes.byref(h)))
+            eta, leaf = share.eta, share.leaf
+        else:
+            mid = np.ascontiguousarray(mid2, np.int32)
+            L.check(L.lib().hlu_build(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), float(eta), int(leaf),
+                                      ctypes.byref(h)))
         self.handle = h
         self._destroy = L.lib().hlu_destroy
         self.n = len(self._rp) - 1
@@ -228,3 +234,107 @@ def gmres_solve(A, b, precond=None, restart=50, tol=1e-8, max_iters=1000, stream
     if st != L.HLU_OK and (raise_on_fail or st != -5):
         L.check(st)
     return x.reshape(b.shape), infos
+
+
+def _check_gmres(st, raise_on_fail):
+    if st != L.HLU_OK and (raise_on_fail or st != -5):
+        L.check(st)
+
+
+# -------------------------------------------------------------------- batch
+class HLUBatch:
+    """hlu_batch_create / bind / hlu_factor_batch / hlu_solve_batch /
+    gmres_solve_batch over member HLU handles.  Stacked vectors are torch
+    tensors of shape (nrhs, n_total); problem p holds columns
+    [row_base[p], row_base[p] + N_p)."""
+
+    def __init__(self, members, eps, max_rank=0, prec="fp32", max_rhs=1):
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(self.members))(*[m.handle.value for m in self.members])
+        o = HLU._opts(eps, max_rank, prec)
+        b = ctypes.c_void_p()
+        L.check(L.lib().hlu_batch_create(arr, len(self.members), ctypes.byref(o), int(max_rhs), ctypes.byref(b)))
+        self.handle = b
+        self._destroy = L.lib().hlu_batch_destroy
+        self.prec = prec
+        self.max_rhs = max_rhs
+        count, ntot = ctypes.c_int32(), ctypes.c_int32()
+        self.row_base = np.empty(len(self.members), np.int32)
+        waves, tasks = ctypes.c_int64(), ctypes.c_int64()
+        L.check(L.lib().hlu_batch_sizes(b, ctypes.byref(count), ctypes.byref(ntot),
+                                        _ptr(self.row_base, ctypes.c_int32), ctypes.byref(waves),
+                                        ctypes.byref(tasks)))
+        self.n_total = ntot.value
+        self.factor_waves = waves.value
+        self.factor_tasks = tasks.value
+        self.work = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def hlu_batch_workspace_bytes(self):
+        n = ctypes.c_size_t()
+        L.check(L.lib().hlu_batch_workspace_bytes(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def hlu_batch_bind_workspace(self, work=None):
+        torch = _torch()
+        nbytes = self.hlu_batch_workspace_bytes()
+        if work is None:
+            work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.work = work
+        L.check(L.lib().hlu_batch_bind_workspace(self.handle, _dev_ptr(work), work.numel()))
+        return self
+
+    def hlu_factor_batch(self, stream=None, allow_overflow=False):
+        if self.work is None:
+            self.hlu_batch_bind_workspace()
+        st = L.lib().hlu_factor_batch(self.handle, _stream(stream))
+        if st == -7 and allow_overflow:
+            st = L.HLU_OK
+        L.check(st)
+        for m in self.members:
+            m.prec = self.prec
+        return self
+
+    def stack(self, parts):
+        """List of (nrhs, N_p) tensors -> one (nrhs, n_total) tensor."""
+        torch = _torch()
+        return torch.cat([p.reshape(-1, p.shape[-1]) for p in parts], dim=1).contiguous()
+
+    def unstack(self, x):
+        out = []
+        for p, m in enumerate(self.members):
+            r0 = int(self.row_base[p])
+            out.append(x[:, r0:r0 + m.n])
+        return out
+
+    def hlu_solve_batch(self, b, stream=None):
+        torch = _torch()
+        b2, nrhs = _as_block(b, self.n_total)
+        x = torch.empty_like(b2)
+        L.check(L.lib().hlu_solve_batch(self.handle, _dev_ptr(b2), _dev_ptr(x), nrhs, _stream(stream)))
+        return x.reshape(b.shape)
+
+    def gmres_solve_batch(self, b, restart=50, tol=1e-8, max_iters=1000, stream=None, work=None,
+                          raise_on_fail=True):
+        """Returns (x, infos): infos[p][c] is the record of problem p,
+        column c."""
+        torch = _torch()
+        b2, nrhs = _as_block(b, self.n_total)
+        x = torch.zeros_like(b2)
+        nbytes = L.lib().gmres_batch_workspace_bytes(self.handle, nrhs, restart)
+        if work is None or work.numel() < nbytes:
+            work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        o = L.GmresOpts(int(restart), int(max_iters), float(tol))
+        P = len(self.members)
+        info = (L.GmresInfo * (P * nrhs))()
+        st = L.lib().gmres_solve_batch(self.handle, _dev_ptr(b2), _dev_ptr(x), nrhs, ctypes.byref(o), info,
+                                       _dev_ptr(work), work.numel(), _stream(stream))
+        infos = [[dict(iters=info[c * P + p].iters, converged=bool(info[c * P + p].converged),
+                       relres=info[c * P + p].relres, abs_res=info[c * P + p].abs_res) for c in range(nrhs)]
+                 for p in range(P)]
+        _check_gmres(st, raise_on_fail)
+        return x.reshape(b.shape), infos

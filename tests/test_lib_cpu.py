@@ -108,3 +108,27 @@ def test_plan_sizes_reported():
     assert b32 < b64
     st = h.hlu_get_stats()
     assert st["factor_waves"] > 0 and st["factor_tasks"] > 0 and st["solve_waves"] > 0
+
+
+def test_build_shared_pattern_rules():
+    """hlu_build_shared accepts another kappa on the same mesh (same plans,
+    same structure) and rejects a different pattern."""
+    from paper_2211_11303_amd import _lib as L
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(4, 2.0)
+    proto = hlu.HLU(rp, ci, va, mid, 2.0, 32)
+    rp2, ci2, va2, _ = hlu.hlu_kuhn_assemble(4, 7.0)
+    h2 = hlu.HLU(rp2, ci2, va2, share=proto)
+    a, b = proto.hlu_export_structure(), h2.hlu_export_structure()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert h2.hlu_workspace_bytes(1e-6) == proto.hlu_workspace_bytes(1e-6)
+    rp3, ci3, va3, _ = hlu.hlu_kuhn_assemble(5, 2.0)
+    with pytest.raises(L.HluError) as e:
+        hlu.HLU(rp3, ci3, va3, share=proto)
+    assert e.value.status == -1
+    moved = ci2.copy()
+    moved[3] = moved[3] - 1 if moved[3] - 1 != moved[2] else moved[3]
+    if not np.array_equal(moved, ci2):
+        with pytest.raises(L.HluError):
+            hlu.HLU(rp2, moved, va2, share=proto)
