@@ -46,6 +46,13 @@ def parse():
                    help="batched workload instead: 64 problems (8^3..24^3, kappa in [1, 10]) factored and "
                         "solved as one batch, against the same problems run one by one")
     p.add_argument("--batch-count", type=int, default=64)
+    p.add_argument("--serve", action="store_true",
+                   help="serving workload instead: Poisson arrivals of solve requests answered by hlu_server")
+    p.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
+    p.add_argument("--serve-count", type=int, default=400)
+    p.add_argument("--serve-sizes", type=str, default="8,12,16,20,24")
+    p.add_argument("--serve-workers", type=int, default=4)
+    p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--batch-max-rank", type=int, default=32,
                    help="rank capacity per low-rank block in the batched workload")
     return p.parse_args()
@@ -210,6 +217,97 @@ def batch_main(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_main(args):
+    """Serving workload: requests from inputs.serving_requests (default_rng(11),
+    Poisson arrivals at --serve-rate, n from --serve-sizes, kappa in 1..16,
+    1..32 right-hand sides, x* seed = 1000 + request index), answered by
+    hlu_server (FP32 H-LU eps 1e-3, rank capacity 32, FP64 GMRES(50) to 1e-8,
+    factor cache per (n, kappa), continuous batching).  Latency is measured
+    by the server from submission to completion (host wall clock)."""
+    import numpy as np
+    import scipy.sparse as sp
+    from paper_2211_11303_amd import hlu, inputs
+
+    sizes = tuple(int(v) for v in args.serve_sizes.split(","))
+    reqs = inputs.serving_requests(args.serve_count, args.serve_rate, seed=11, sizes=sizes)
+    t = time.perf_counter()
+    mats = {}
+    for r in reqs:
+        key = (r["n"], r["kappa"])
+        if key not in mats:
+            rp, ci, va, _ = hlu.hlu_kuhn_assemble(r["n"], r["kappa"])
+            mats[key] = sp.csr_matrix((va, ci, rp), shape=(len(rp) - 1, len(rp) - 1))
+    rhs = []
+    for r in reqs:
+        A = mats[(r["n"], r["kappa"])]
+        xs = inputs.exact_solution_cols(A.shape[0], r["nrhs"], seed=r["seed"])
+        rhs.append((xs, np.ascontiguousarray((A @ xs.T).T)))
+    srv = hlu.Server(workers=args.serve_workers, max_batch_rhs=32, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
+                     eta=2.0, leaf=args.leaf, eps=1e-3, max_rank=32, prec="fp32", restart=args.restart,
+                     max_iters=1000, tol=args.tol)
+    for n in sizes:
+        log(f"planning {n}^3")
+        srv.hlu_server_prepare(n)
+    setup_s = time.perf_counter() - t
+    log(f"serving {len(reqs)} requests at {args.serve_rate}/s")
+    tickets = []
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        delay = t0 + r["t"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.hlu_server_submit(r["n"], r["kappa"], rhs[i][1]))
+        if i % 100 == 99:
+            log(f"submitted {i + 1}")
+    lat, que, errs, rel, iters, failed = [], [], [], [], [], 0
+    for i, tk in enumerate(tickets):
+        x, infos, q, l = srv.hlu_server_wait(tk, raise_on_fail=False)
+        lat.append(l)
+        que.append(q)
+        if not all(f["converged"] for f in infos):
+            failed += 1
+        xs = rhs[i][0]
+        errs.append(float(np.max(np.linalg.norm(x - xs, axis=1) / np.linalg.norm(xs, axis=1))))
+        rel.append(max(f["relres"] for f in infos))
+        iters += [f["iters"] for f in infos]
+        if i % 100 == 99:
+            log(f"answered {i + 1}")
+    T = time.perf_counter() - t0
+    st = srv.hlu_server_get_stats()
+    srv.close()
+    nrhs_total = sum(r["nrhs"] for r in reqs)
+    lat = np.asarray(lat)
+    line = {
+        "metric": "H-LU preconditioned GMRES serving: p50/p99 request latency and solves/s",
+        "value": nrhs_total / T,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32-hlu+f64-gmres",
+        "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} Poisson requests at {args.serve_rate:g}/s (default_rng(11)), n in "
+                               f"{list(sizes)}, kappa in 1..16, 1..32 rhs; FP32 H-LU eps 1e-3 rank capacity 32, "
+                               f"GMRES({args.restart}) to {args.tol:g}; {args.serve_workers} workers, "
+                               f"budget {args.serve_budget_gb:g} GB",
+                   "requests": len(reqs), "rate": args.serve_rate, "sizes": list(sizes)},
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "p50_queue_s": float(np.percentile(que, 50)),
+        "requests_per_s": len(reqs) / T,
+        "wall_s": T,
+        "rhs_total": nrhs_total,
+        "not_converged": failed,
+        "relres_max": max(rel),
+        "err_vs_xstar_max": max(errs),
+        "iters": [min(iters), max(iters)],
+        "cache_hit_rate": st["cache_hits"] / max(1, st["gmres_calls"]),
+        "server": st,
+        "peak_gb": st["peak_bytes"] / 1e9,
+        "setup_s": setup_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -219,6 +317,8 @@ def main():
         sys.exit(2)
     if args.batch:
         return batch_main(args)
+    if args.serve:
+        return serve_main(args)
     import numpy as np
     import torch
     from paper_2211_11303_amd import hlu, inputs

@@ -165,6 +165,11 @@ void hlu_destroy(hlu_handle h);
 /* Device bytes hlu_factor needs for these options (plans the schedule). */
 hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
 
+/* All device bytes a factored handle holds for these options: the bound
+ * workspace plus the library-owned buffers of its own solves and its matrix
+ * values (shared plans excluded).  For admission by device-memory budget. */
+hlu_status hlu_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
+
 /* Hands the library a caller-owned device buffer of at least the bytes
  * reported above (256-byte aligned).  It stays in use until re-bound or the
  * handle is destroyed. */
@@ -252,6 +257,69 @@ size_t gmres_batch_workspace_bytes(hlu_batch b, int32_t nrhs, int32_t restart);
 hlu_status gmres_solve_batch(hlu_batch b, const double* d_b, double* d_x, int32_t nrhs,
                              const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work,
                              size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop on one GPU for the Kuhn-cube problem: each request names a
+ * mesh (n) and kappa and brings nrhs right-hand sides; it is answered by
+ * FP64 GMRES preconditioned with the H-LU of A = K - kappa^2 M.
+ *   - Factorisations are cached per (n, kappa) in device memory; structures
+ *     and plans are built once per n.
+ *   - Admission by device bytes: a request starts only when its factor (if
+ *     not cached) and its GMRES buffers fit hbm_budget next to everything in
+ *     use; idle cached factors are evicted least recently used first.  A
+ *     request that cannot fit even into an empty cache fails with
+ *     HLU_ERR_OUT_OF_MEMORY.
+ *   - Continuous batching: a free worker takes the oldest admissible request
+ *     together with every queued request for the same factor (up to
+ *     max_batch_rhs columns in all) and answers them with one GMRES call;
+ *     each column keeps its own Krylov process, so a result is the same
+ *     alone and in the mix.
+ *   - Overlap: each of the `workers` threads owns a HIP stream (default
+ *     priority), so factorisations and solves of different requests run on
+ *     the device concurrently.
+ * Device memory of the cache and of the workers' GMRES buffers is owned by
+ * the server (the workers keep their largest buffers for reuse). */
+typedef struct hlu_server_s* hlu_server;
+typedef struct {
+  int32_t workers;         /* worker threads = requests in flight, 1..16         */
+  int32_t max_batch_rhs;   /* columns per GMRES call (and per request), 1..32    */
+  size_t hbm_budget;       /* device bytes for cached factors + GMRES buffers    */
+  double eta;              /* admissibility parameter                            */
+  int32_t leaf;            /* leaf size of the cluster trees                     */
+  hlu_factor_opts factor;  /* options of every factorisation                     */
+  hlu_gmres_opts gmres;    /* options of every solve                             */
+} hlu_server_opts;
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t factorizations;      /* factors computed (cache misses)                */
+  int64_t cache_hits;          /* GMRES calls served by a cached factor          */
+  int64_t evictions;
+  int64_t gmres_calls;
+  int64_t coalesced_requests;  /* requests that shared a GMRES call              */
+  size_t bytes_in_use, peak_bytes;  /* admitted device bytes, now and at peak    */
+  int32_t cached_factors;
+} hlu_server_stats;
+
+hlu_status hlu_server_create(const hlu_server_opts* o, hlu_server* out);
+/* Builds and plans the structure of mesh n now (host work that the first
+ * request for n would otherwise pay). */
+hlu_status hlu_server_prepare(hlu_server s, int32_t n);
+/* Queues a request; returns at once with a ticket.  b: host, N x nrhs
+ * column-major (leading dimension N = 7n^3 - 9n^2 + 3n, natural order); x:
+ * host output of the same shape; info: host output [nrhs].  b, x and info
+ * are borrowed until hlu_server_wait returns for the ticket. */
+hlu_status hlu_server_submit(hlu_server s, int32_t n, double kappa, int32_t nrhs, const double* b,
+                             double* x, hlu_gmres_info* info, int64_t* ticket);
+/* Blocks until the request is answered (timeout_s < 0: no limit; on timeout
+ * HLU_ERR_STATE and the ticket stays valid).  Returns the request's status
+ * (HLU_ERR_NOT_CONVERGED if a column missed tol) and, if non-NULL, the host
+ * wall-clock seconds from submission to start of service and to completion.
+ * The ticket is released. */
+hlu_status hlu_server_wait(hlu_server s, int64_t ticket, double timeout_s, double* queued_s,
+                           double* latency_s);
+hlu_status hlu_server_get_stats(hlu_server s, hlu_server_stats* out);
+/* Answers every queued request, stops the workers, frees the cache. */
+void hlu_server_destroy(hlu_server s);
 
 /* ------------------------------------------------------------ inspection */
 /* Sizes of the structure arrays, then a copy of them into caller-allocated

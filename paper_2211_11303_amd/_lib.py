@@ -55,6 +55,21 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("workers", c_int32), ("max_batch_rhs", c_int32), ("hbm_budget", c_size_t), ("eta", c_double),
+                ("leaf", c_int32), ("factor", FactorOpts), ("gmres", GmresOpts)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("failed", c_int64),
+                ("factorizations", c_int64), ("cache_hits", c_int64), ("evictions", c_int64),
+                ("gmres_calls", c_int64), ("coalesced_requests", c_int64), ("bytes_in_use", c_size_t),
+                ("peak_bytes", c_size_t), ("cached_factors", c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "hlu_last_error": (ctypes.c_char_p, []),
@@ -93,6 +108,14 @@ SIGNATURES = {
     "gmres_batch_workspace_bytes": (c_size_t, [c_void_p, c_int32, c_int32]),
     "gmres_solve_batch": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(GmresOpts),
                                     ctypes.POINTER(GmresInfo), c_void_p, c_size_t, c_void_p]),
+    "hlu_device_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
+    "hlu_server_create": (c_int32, [ctypes.POINTER(ServerOpts), ctypes.POINTER(c_void_p)]),
+    "hlu_server_prepare": (c_int32, [c_void_p, c_int32]),
+    "hlu_server_submit": (c_int32, [c_void_p, c_int32, c_double, c_int32, c_void_p, c_void_p,
+                                    ctypes.POINTER(GmresInfo), ctypes.POINTER(c_int64)]),
+    "hlu_server_wait": (c_int32, [c_void_p, c_int64, c_double, ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
+    "hlu_server_get_stats": (c_int32, [c_void_p, ctypes.POINTER(ServerStats)]),
+    "hlu_server_destroy": (None, [c_void_p]),
 }
 
 _lib = None

@@ -88,6 +88,16 @@ void SolveBufs::alloc(const SolveSched& sc, int32_t N, int32_t rhs) {
   epoch = 0;
 }
 
+size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t rhs) {
+  size_t b = 0;
+  b += (size_t)std::max<int64_t>(1, sc.inv_elems) * sizeof(double);
+  b += (size_t)N * sizeof(double) * (1 + rhs);
+  b += (size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs * sizeof(double);
+  b += (2 * (size_t)sc.L + sc.tprod.size() + sc.dense.size() + 1) * sizeof(int32_t);
+  b += std::max<size_t>(1, sc.dense.size()) * (size_t)sc.max_m * rhs * sizeof(double);
+  return b + 4 * sizeof(int32_t);
+}
+
 SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs& b) {
   SolveDev v{};
   v.tasks = d.tasks;
@@ -521,6 +531,16 @@ hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* b
     h->stats.factor_waves = (int64_t)h->pb->ps.factor.waves.size();
     h->stats.factor_tasks = h->pb->ps.factor.num_tasks;
     h->stats.solve_waves = (int64_t)h->pb->ps.fwd_bwd.waves.size();
+  });
+}
+
+hlu_status hlu_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes) {
+  return guard([&] {
+    HLU_REQUIRE(h && bytes, HLU_ERR_INVALID_ARG, "hlu_device_bytes: NULL argument");
+    check_opts(o);
+    use_bundle(h, kcap_for(o));
+    const size_t ws = work_layout(h->pb->ps, o->prec).total;
+    *bytes = ws + solve_buffer_bytes(h->pb->sc, h->sh->S.N, kMaxRhs) + h->val.size() * sizeof(double);
   });
 }
 

@@ -122,6 +122,9 @@ struct SolveBufs {
   void alloc(const SolveSched& sc, int32_t N, int32_t max_rhs);
 };
 
+// Device bytes SolveBufs::alloc takes for this schedule.
+size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t max_rhs);
+
 // Kernel launch view of a schedule and its buffers.
 SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs& b);
 

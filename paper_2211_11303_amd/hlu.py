@@ -338,3 +338,62 @@ class HLUBatch:
                  for p in range(P)]
         _check_gmres(st, raise_on_fail)
         return x.reshape(b.shape), infos
+
+
+# ------------------------------------------------------------------ serving
+class Server:
+    """hlu_server_*: request loop with a factor cache per (n, kappa),
+    admission by device bytes and continuous batching of right-hand sides.
+    Right-hand sides and results are host numpy arrays of shape (nrhs, N)."""
+
+    def __init__(self, workers=4, max_batch_rhs=32, hbm_budget=200 << 30, eta=2.0, leaf=64, eps=1e-3,
+                 max_rank=32, prec="fp32", restart=50, max_iters=1000, tol=1e-8):
+        o = L.ServerOpts(int(workers), int(max_batch_rhs), int(hbm_budget), float(eta), int(leaf),
+                         L.FactorOpts(float(eps), int(max_rank), PREC[prec]),
+                         L.GmresOpts(int(restart), int(max_iters), float(tol)))
+        h = ctypes.c_void_p()
+        L.check(L.lib().hlu_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._destroy = L.lib().hlu_server_destroy
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def hlu_server_prepare(self, n):
+        L.check(L.lib().hlu_server_prepare(self.handle, int(n)))
+
+    def hlu_server_submit(self, n, kappa, b):
+        """b: (nrhs, N) float64 host array.  Returns a ticket."""
+        b = np.ascontiguousarray(b, np.float64)
+        if b.ndim == 1:
+            b = b.reshape(1, -1)
+        x = np.empty_like(b)
+        info = (L.GmresInfo * b.shape[0])()
+        t = ctypes.c_int64()
+        L.check(L.lib().hlu_server_submit(self.handle, int(n), float(kappa), b.shape[0],
+                                          b.ctypes.data_as(ctypes.c_void_p), x.ctypes.data_as(ctypes.c_void_p),
+                                          info, ctypes.byref(t)))
+        self._live[t.value] = (b, x, info)
+        return t.value
+
+    def hlu_server_wait(self, ticket, timeout=-1.0, raise_on_fail=True):
+        """Returns (x, infos, queued_s, latency_s)."""
+        q, lat = ctypes.c_double(), ctypes.c_double()
+        st = L.lib().hlu_server_wait(self.handle, ticket, float(timeout), ctypes.byref(q), ctypes.byref(lat))
+        if st == -6 and timeout >= 0:
+            L.check(st)
+        b, x, info = self._live.pop(ticket)
+        infos = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, abs_res=i.abs_res) for i in info]
+        _check_gmres(st, raise_on_fail)
+        return x, infos, q.value, lat.value
+
+    def hlu_server_get_stats(self):
+        s = L.ServerStats()
+        L.check(L.lib().hlu_server_get_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()

@@ -1,0 +1,93 @@
+"""Serving runtime (hlu_server_*): continuous batching, admission by device
+bytes, cache eviction.
+
+Each GMRES column keeps its own Krylov process and every kernel computes a
+column with the same arithmetic whatever its companions, so a request's
+result is expected to be the same alone and in a mix: the bar is equal
+iteration counts and |x_mix - x_alone| <= 1e-14 |x_alone| per request."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _csr(n, kappa):
+    import scipy.sparse as sp
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, _ = hlu.hlu_kuhn_assemble(n, kappa)
+    return sp.csr_matrix((va, ci, rp), shape=(len(rp) - 1, len(rp) - 1))
+
+
+def _request_set():
+    from paper_2211_11303_amd import inputs
+    reqs = []
+    # repeated (n, kappa) pairs so that requests share factors and GMRES calls
+    for i, (n, kappa, nrhs) in enumerate([(4, 2.0, 1), (5, 3.0, 2), (4, 2.0, 3), (6, 1.5, 1), (5, 3.0, 1),
+                                          (4, 2.0, 2), (4, 7.0, 1), (6, 1.5, 4), (5, 3.0, 3), (4, 2.0, 1)]):
+        N = inputs.num_interior_edges(n)
+        xs = inputs.exact_solution_cols(N, nrhs, seed=100 + i)
+        A = _csr(n, kappa)
+        reqs.append(dict(n=n, kappa=kappa, xs=xs, b=np.stack([A @ x for x in xs]), A=A))
+    return reqs
+
+
+def test_result_same_alone_and_in_mix(gpu):
+    from paper_2211_11303_amd import hlu
+    reqs = _request_set()
+    srv = hlu.Server(workers=3, max_batch_rhs=8, hbm_budget=8 << 30, leaf=32, eps=1e-6, prec="fp64",
+                     restart=30, tol=1e-10)
+    for n in (4, 5, 6):
+        srv.hlu_server_prepare(n)
+    tickets = [srv.hlu_server_submit(r["n"], r["kappa"], r["b"]) for r in reqs]
+    mix = [srv.hlu_server_wait(t) for t in tickets]
+    st = srv.hlu_server_get_stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["factorizations"] == 4          # distinct (n, kappa) pairs
+    assert st["gmres_calls"] < len(reqs)      # some requests shared a call
+    for r, (x, infos, q, lat) in zip(reqs, mix):
+        for c in range(len(x)):
+            assert infos[c]["converged"]
+            assert np.linalg.norm(r["A"] @ x[c] - r["b"][c]) <= 1e-10 * np.linalg.norm(r["b"][c])
+        assert lat >= q >= 0
+    # each request alone, on a fresh server
+    for r, (x, infos, _, _) in zip(reqs, mix):
+        one = hlu.Server(workers=1, max_batch_rhs=8, hbm_budget=8 << 30, leaf=32, eps=1e-6, prec="fp64",
+                         restart=30, tol=1e-10)
+        xa, ia, _, _ = one.hlu_server_wait(one.hlu_server_submit(r["n"], r["kappa"], r["b"]))
+        one.close()
+        assert [i["iters"] for i in ia] == [i["iters"] for i in infos]
+        assert np.abs(xa - x).max() <= 1e-14 * np.abs(xa).max()
+
+
+def test_admission_evicts_and_rejects(gpu):
+    from paper_2211_11303_amd import hlu, inputs
+    from paper_2211_11303_amd import _lib as L
+    # footprint of one 6^3 factor, to size a budget that holds just one
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(6, 1.0)
+    import ctypes
+    H = hlu.HLU(rp, ci, va, mid, 2.0, 32)
+    o = L.FactorOpts(1e-6, 32, L.HLU_FP64)
+    nb = ctypes.c_size_t()
+    L.check(L.lib().hlu_device_bytes(H.handle, ctypes.byref(o), ctypes.byref(nb)))
+    budget = int(nb.value * 1.6)
+    srv = hlu.Server(workers=2, max_batch_rhs=4, hbm_budget=budget, leaf=32, eps=1e-6, max_rank=32,
+                     prec="fp64", restart=30, tol=1e-10)
+    N = inputs.num_interior_edges(6)
+    tickets = []
+    for i, kappa in enumerate([1.0, 2.0, 3.0, 1.0]):
+        b = _csr(6, kappa) @ inputs.exact_solution_cols(N, 1, seed=i)[0]
+        tickets.append(srv.hlu_server_submit(6, kappa, b))
+    for t in tickets:
+        x, infos, _, _ = srv.hlu_server_wait(t)
+        assert infos[0]["converged"]
+    st = srv.hlu_server_get_stats()
+    assert st["peak_bytes"] <= budget
+    assert st["evictions"] >= 2 and st["factorizations"] >= 3
+    # a mesh whose factor can never fit the budget is refused, not queued forever
+    big = inputs.num_interior_edges(12)
+    t = srv.hlu_server_submit(12, 1.0, np.ones(big))
+    with pytest.raises(L.HluError) as e:
+        srv.hlu_server_wait(t)
+    assert e.value.status == L.STATUS_CODES["HLU_ERR_OUT_OF_MEMORY"]
+    srv.close()
