@@ -84,7 +84,7 @@ void SolveBufs::alloc(const SolveSched& sc, int32_t N, int32_t rhs) {
   pbuf = mem.keep(dmalloc<double>(std::max<size_t>(1, sc.dense.size()) * (size_t)pstride));
   ctr = mem.keep(dmalloc<int32_t>(4));
   HIP_OK(hipMemset(ctr, 0, 4 * sizeof(int32_t)));
-  if (getenv("HLU_DEBUG_SOLVE_TRACE")) trace = mem.keep(dmalloc<int64_t>(8 * std::max<size_t>(1, sc.tasks.size())));
+  if (getenv("HLU_DEBUG_SOLVE_TRACE")) trace = mem.keep(dmalloc<int64_t>(12 * std::max<size_t>(1, sc.tasks.size())));
   epoch = 0;
 }
 
@@ -107,6 +107,7 @@ SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs
   v.tprod = d.tprod;
   v.push0 = d.push0;
   v.push_recs = d.push_recs;
+  v.leaf_tq = d.leaf_tq;
   v.inv = b.inv;
   v.pivots = b.pivots;
   v.y = b.y;
@@ -321,12 +322,12 @@ void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, i
     HIP_OK(scatter_perm_launch<double>(N, nc, h->sh->d_perm, sb.y, N, x + (int64_t)c0 * ld, ld, s));
     if (sb.trace) {   // debug: dump task clocks and kinds
       HIP_OK(hipStreamSynchronize(s));
-      std::vector<int64_t> tr(8 * (size_t)d.ntasks);
+      std::vector<int64_t> tr(12 * (size_t)d.ntasks);
       HIP_OK(hipMemcpy(tr.data(), sb.trace, tr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
       if (FILE* f = fopen(getenv("HLU_DEBUG_SOLVE_TRACE"), "wb")) {
         for (int32_t t = 0; t < d.ntasks; ++t) {
           fwrite(&sc.tasks[t], sizeof(STask), 1, f);   // kind, idx (int32 each)
-          fwrite(tr.data() + 8 * t, 8 * sizeof(int64_t), 1, f);
+          fwrite(tr.data() + 12 * t, 12 * sizeof(int64_t), 1, f);
         }
         fclose(f);
       }

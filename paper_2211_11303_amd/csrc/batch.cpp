@@ -170,7 +170,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
                   const std::vector<int32_t>& d, const std::vector<int32_t>& o, SolveSched* out) {
   SolveSched& M = *out;
   const size_t np = S.size();
-  std::vector<int32_t> LB(np), DB(np), LWB(np), TPB(np), PB(np), PRB(np);
+  std::vector<int32_t> LB(np), DB(np), LWB(np), TPB(np), PB(np), PRB(np), TQB(np);
   std::vector<int64_t> TOFF(np), INVB(np);
   int32_t Ltot = 0;
   for (size_t p = 0; p < np; ++p) {
@@ -208,6 +208,8 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
     }
     for (size_t i = 0; i + 1 < s.push0.size(); ++i) M.push0.push_back(s.push0[i] + PRB[p]);
     for (int32_t r : s.push_recs) M.push_recs.push_back(r + DB[p]);
+    TQB[p] = (int32_t)M.leaf_tq.size();
+    for (int32_t q : s.leaf_tq) M.leaf_tq.push_back(q + TPB[p]);
     M.tbuf_per_rhs += s.tbuf_per_rhs;
     M.inv_elems += s.inv_elems;
     M.max_m = std::max(M.max_m, s.max_m);
@@ -225,6 +227,8 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
       lf.d0 += DB[p];
       lf.l0 += LWB[p];
       if (lf.next_rec >= 0) lf.next_rec += DB[p];
+      if (lf.prev_rec >= 0) lf.prev_rec += DB[p];
+      lf.tq0 += TQB[p];
       const int32_t dst = q < s.L ? LB[p] + q : Ltot + LB[p] + (q - s.L);
       M.leaves[dst] = lf;
     }

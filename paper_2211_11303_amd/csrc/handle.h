@@ -93,6 +93,7 @@ struct DevSched {
   const STprod* tprod = nullptr;
   const int32_t* push0 = nullptr;
   const int32_t* push_recs = nullptr;
+  const int32_t* leaf_tq = nullptr;
   void load(const SolveSched& sc) {
     tasks = mem.keep(upload(sc.tasks));
     leaves = mem.keep(upload(sc.leaves));
@@ -101,6 +102,7 @@ struct DevSched {
     tprod = mem.keep(upload(sc.tprod));
     push0 = mem.keep(upload(sc.push0));
     push_recs = mem.keep(upload(sc.push_recs));
+    leaf_tq = mem.keep(upload(sc.leaf_tq));
   }
 };
 

@@ -22,8 +22,9 @@ constexpr int kSolveThreads = 256;
 constexpr int kMaxRhsTile = 8;          // columns per register tile of the triangular solve
 constexpr int kSpinLimit = 1 << 25;     // bounded waits; on overflow the error flag is set
 // debug trace per task: claim, solve start, end, workgroup, low-rank done,
-// triangle done, product done, flags stored
-constexpr int kTraceFields = 8;
+// triangle done, product done, flags stored, batched low-rank started,
+// batched low-rank done, (unused) x2
+constexpr int kTraceFields = 12;
 
 struct SolveArgs {
   const STask* tasks;
@@ -39,6 +40,7 @@ struct SolveArgs {
   int32_t* ctr;         // [0] claim counter, [1] finished forward tasks, [2] error
   const int32_t* push0; // push task -> first record in push_recs
   const int32_t* push_recs;
+  const int32_t* leaf_tq; // T-product chunks computed by leaf tasks
   double* pbuf;         // partial-sum records, pstride doubles each (m x nrhs, ld m)
   int32_t* pflag;       // one per record
   int64_t pstride;
@@ -196,20 +198,154 @@ __device__ void dense_contrib(const SolveArgs& a, const T* arena, const SDense& 
   mm_sub<T>(arena + D.off, D.ld, a.y + D.col0, 1, a.N, m, D.ncols, nrhs, r, As, Bs);
 }
 
+// r -= X_b[rows of this leaf] T_b with T_b the sum of the block's chunk
+// products (summed into the LDS area Ts first when there are several).
 template <class T>
 __device__ void low_contrib(const SolveArgs& a, const T* arena, const SLow& Lw, int m, int nrhs, double* r,
-                            double* As, double* Bs) {
+                            double* As, double* Bs, double* Ts) {
   const STprod tp = a.tprod[Lw.tp];
   const int k = a.dims[tp.slot];
-  const double* Tb = a.tbuf + tp.toff * a.max_rhs;
-  mm_sub<T>(arena + Lw.xoff, Lw.ldx, Tb, 1, tp.cap, m, k, nrhs, r, As, Bs);
+  if (Lw.ntp == 1) {
+    const double* Tb = a.tbuf + tp.toff * a.max_rhs;
+    mm_sub<T>(arena + Lw.xoff, Lw.ldx, Tb, 1, tp.cap, m, k, nrhs, r, As, Bs);
+    return;
+  }
+  for (int e = threadIdx.x; e < k * nrhs; e += blockDim.x) {
+    const int kk = e % k, c = e / k;
+    double sum = 0.0;
+    for (int q = 0; q < Lw.ntp; ++q) sum += cload(a.tbuf + a.tprod[Lw.tp + q].toff * a.max_rhs + kk + c * tp.cap);
+    Ts[kk + c * k] = sum;
+  }
+  __syncthreads();
+  mm_sub<T, true>(arena + Lw.xoff, Lw.ldx, Ts, 1, k, m, k, nrhs, r, As, Bs);
 }
 
-constexpr int kMaxContrib = 256;   // contributions per leaf task checked for early readiness
+// r -= sum over the low-rank contributions t < 256 (of at most kMaxChunks
+// chunks) of this leaf of X_t T_t, as one product of the concatenated matrices
+// [X_1 .. X_G] [T_1; ..; T_G]: every column kk of every X_t is a "virtual
+// column", in schedule order.  Virtual columns go through LDS in fixed
+// windows of 64 (so the summation order depends on the ranks only, not on
+// timing); before a window the task waits for the T products it reads.
+// Each thread issues all of a window's loads before writing LDS, so a
+// window costs one memory round trip instead of one per contribution.
+// scr: LDS scratch of at least 2816 doubles, free during the call.
+constexpr int kVCols = 1024;   // virtual columns per table window
+constexpr int kMaxChunks = 4;  // contributions with more chunks go one by one
+// Returns true if some contribution was left for the caller (more than 256,
+// or more than kMaxChunks chunks).
+template <class T>
+__device__ bool low_batched(const SolveArgs& a, const T* arena, const SLeaf& lf, int m, int nrhs, double* r,
+                            double* As, double* Bs, double* scr) {
+  constexpr int kPer = 16;
+  int* kpre = reinterpret_cast<int*>(scr);                   // [257] column offsets of the contributions
+  int64_t* colX = reinterpret_cast<int64_t*>(scr + 256);     // [kVCols] arena index of X column
+  int64_t* colT = reinterpret_cast<int64_t*>(scr + 1280);    // [kVCols] tbuf index of T row
+  int* colC = reinterpret_cast<int*>(scr + 2304);            // [kVCols] T column stride
+  const int nl = min(lf.nl, 256);
+  const int t0 = threadIdx.x;
+  int k1 = 0, kt = 0;   // rank; virtual columns (rank x chunks)
+  SLow Lw{};
+  STprod tp{};
+  if (t0 < nl) {
+    Lw = a.low[lf.l0 + t0];
+    if (Lw.ntp <= kMaxChunks) {
+      tp = a.tprod[Lw.tp];
+      k1 = a.dims[tp.slot];
+      kt = k1 * Lw.ntp;
+    }
+  }
+  kpre[t0 + 1] = kt;
+  if (t0 == 0) kpre[0] = 0;
+  const bool left = __syncthreads_or(t0 < nl && Lw.ntp > kMaxChunks) || lf.nl > 256;
+  for (int d = 1; d < 256; d <<= 1) {   // inclusive scan of 256 entries
+    const int v = t0 >= d ? kpre[t0 + 1 - d] : 0;
+    __syncthreads();
+    kpre[t0 + 1] += v;
+    __syncthreads();
+  }
+  const int vtot = kpre[256];
+  const int my0 = kpre[t0], my1 = kpre[t0 + 1];
+  for (int w0 = 0; w0 < vtot; w0 += kVCols) {
+    // table of this window's virtual columns, written by their contributions
+    // (chunk q of a contribution repeats its X columns against T chunk q)
+    for (int q = 0; q < Lw.ntp && kt > 0; ++q) {
+      const int64_t tb = (q == 0 ? tp.toff : a.tprod[Lw.tp + q].toff) * a.max_rhs;
+      for (int kk = 0; kk < k1; ++kk) {
+        const int v = my0 + q * k1 + kk - w0;
+        if (v >= 0 && v < kVCols) {
+          colX[v] = Lw.xoff + (int64_t)kk * Lw.ldx;
+          colT[v] = tb + kk;
+          colC[v] = tp.cap;
+        }
+      }
+    }
+    __syncthreads();
+    const int wn = min(kVCols, vtot - w0);
+    for (int v0 = 0; v0 < wn; v0 += kKC) {
+      const int vc = min(kKC, wn - v0);
+      // the T products of the contributions overlapping these columns
+      if (kt > 0 && my0 < w0 + v0 + vc && my1 > w0 + v0)
+        for (int q = 0; q < Lw.ntp; ++q) spin_eq(a.tp_flag + Lw.tp + q, a.epoch, a.ctr + 2);
+      acquire_all();
+      // T rows and the first X pass are loaded together, then written
+      double tr[8];
+      int td[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = threadIdx.x + u * kSolveThreads;
+        td[u] = -1;
+        tr[u] = 0.0;
+        if (e < vc * nrhs) {
+          const int vv = e % vc, c = e / vc;
+          tr[u] = cload(a.tbuf + colT[v0 + vv] + (int64_t)c * colC[v0 + vv]);
+          td[u] = c * kKC + vv;
+        }
+      }
+      for (int b0 = 0; b0 < m * vc; b0 += 16 * kSolveThreads) {
+        double xr[16];
+        int xd[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = b0 + threadIdx.x + u * kSolveThreads;
+          xd[u] = -1;
+          xr[u] = 0.0;
+          if (e < m * vc) {
+            const int i = e % m, vv = e / m;
+            xr[u] = double(arena[colX[v0 + vv] + i]);
+            xd[u] = vv * 128 + i;
+          }
+        }
+        if (b0 == 0) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (td[u] >= 0) Bs[td[u]] = tr[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (xd[u] >= 0) As[xd[u]] = xr[u];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int o = threadIdx.x + q * kSolveThreads;
+        if (o < m * nrhs) {
+          const int i = o % m, c = o / m;
+          double sum = 0.0;
+#pragma unroll 8
+          for (int vv = 0; vv < vc; ++vv) sum += As[vv * 128 + i] * Bs[c * kKC + vv];
+          r[q] -= sum;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  return left;
+}
+
 
 template <class T>
 __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s, bool forward, double* acc,
-                         int* ready, double* As, double* Bs, double* Dg) {
+                         double* As, double* Bs, double* Dg) {
   const SLeaf lf = a.leaves[s];
   const int m = lf.m, nrhs = a.nrhs;
   const int ldacc = a.max_rhs;
@@ -226,19 +362,18 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s
     const int o = threadIdx.x + q * kSolveThreads;
     r[q] = (o < m * nrhs) ? cload(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N) : 0.0;
   }
-  // low-rank contributions: those whose T product is complete first, then
-  // wait for the rest
+  // low-rank contributions in schedule order (sorted by when their T
+  // products complete): the first 256 together, then the others one by one (acc is free until the dense records are
+  // summed; the LDS area of the diagonal inverses until they are staged)
   const int nl = lf.nl;
-  for (int t = threadIdx.x; t < nl && t < kMaxContrib; t += blockDim.x)
-    ready[t] = load_relaxed(a.tp_flag + a.low[lf.l0 + t].tp) == a.epoch ? 1 : 0;
-  acquire_all();
-  for (int t = 0; t < nl; ++t)
-    if (t < kMaxContrib && ready[t]) low_contrib<T>(a, arena, a.low[lf.l0 + t], m, nrhs, r, As, Bs);
-  for (int t = 0; t < nl; ++t) {
-    if (t < kMaxContrib && ready[t]) continue;
+  stamp(a, 8);
+  const bool rest = low_batched<T>(a, arena, lf, m, nrhs, r, As, Bs, acc);
+  stamp(a, 9);
+  for (int t = rest ? 0 : nl; t < nl; ++t) {
     const SLow Lw = a.low[lf.l0 + t];
-    wait_one(a, a.tp_flag + Lw.tp, a.epoch);
-    low_contrib<T>(a, arena, Lw, m, nrhs, r, As, Bs);
+    if (t < 256 && Lw.ntp <= kMaxChunks) continue;
+    for (int q = 0; q < Lw.ntp; ++q) wait_one(a, a.tp_flag + Lw.tp + q, a.epoch);
+    low_contrib<T>(a, arena, Lw, m, nrhs, r, As, Bs, Dg);
   }
   stamp(a, 4);
   // stage factor data of the critical section before waiting on the
@@ -258,26 +393,40 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s
     }
   }
   __syncthreads();
-  // dense contributions: wait for every partial-sum record of this row,
-  // then add them in record order
-  for (int t = threadIdx.x; t < lf.nd; t += blockDim.x) spin_eq(a.pflag + lf.d0 + t, a.epoch, a.ctr + 2);
+  // dense contributions: the partial-sum records of this row in record
+  // order, except the one the preceding leaf task forms, which comes last
+  for (int t = threadIdx.x; t < lf.nd; t += blockDim.x)
+    if (lf.d0 + t != lf.prev_rec) spin_eq(a.pflag + lf.d0 + t, a.epoch, a.ctr + 2);
   acquire_all();
   for (int t0 = 0; t0 < lf.nd; t0 += 4) {
     // four records' loads in flight together
     double v[4][kPer];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double* P = a.pbuf + (int64_t)(lf.d0 + t0 + u) * a.pstride;
+      const int rec = lf.d0 + t0 + u;
+      const double* P = a.pbuf + (int64_t)rec * a.pstride;
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
         const int o = threadIdx.x + q * kSolveThreads;
-        v[u][q] = (t0 + u < lf.nd && o < m * nrhs) ? cload(P + o) : 0.0;
+        v[u][q] = (t0 + u < lf.nd && rec != lf.prev_rec && o < m * nrhs) ? cload(P + o) : 0.0;
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int q = 0; q < kPer; ++q) r[q] -= v[u][q];
+  }
+  if (lf.prev_rec >= 0) {
+    wait_one(a, a.pflag + lf.prev_rec, a.epoch);
+    const double* P = a.pbuf + (int64_t)lf.prev_rec * a.pstride;
+    double v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int o = threadIdx.x + q * kSolveThreads;
+      v[q] = o < m * nrhs ? cload(P + o) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) r[q] -= v[q];
   }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
@@ -320,18 +469,47 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s
       const int o = threadIdx.x + q * kSolveThreads;
       if (o < D.m * nrhs) cstore(P + o, pr[q]);
     }
-    stamp(a, 6);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_s_waitcnt(0);
-      __hip_atomic_store(a.pflag + lf.next_rec, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.leaf_flag + s, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    stamp(a, 7);
-    return;
   }
-  publish(a.leaf_flag + s, a.epoch);
+  // T-product chunks of exactly this leaf's rows that the next leaf needs:
+  // T = Y[rows of this leaf]^T y_j, Y staged in the (now free) inverse area
+  for (int q = 0; q < lf.ntq; ++q) {
+    const STprod tp = a.tprod[a.leaf_tq[lf.tq0 + q]];
+    const int k = a.dims[tp.slot];
+    const T* Y = arena + tp.yoff;
+    const bool staged = m * k <= 64 * 64;
+    __syncthreads();
+    if (staged)
+      for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+        const int i = e % m, kk = e / m;
+        Dg[i + kk * m] = double(Y[i + (int64_t)kk * tp.ldy]);
+      }
+    __syncthreads();
+    double* Tb = a.tbuf + tp.toff * a.max_rhs;
+    for (int o = threadIdx.x; o < k * nrhs; o += blockDim.x) {
+      const int kk = o % k, c = o / k;
+      double sum = 0.0;
+      if (staged) {
+#pragma unroll 8
+        for (int i = 0; i < m; ++i) sum += Dg[i + kk * m] * acc[i * ldacc + c];
+      } else {
+        for (int i = 0; i < m; ++i) sum += double(Y[i + (int64_t)kk * tp.ldy]) * acc[i * ldacc + c];
+      }
+      cstore(Tb + kk + c * tp.cap, sum);
+    }
+  }
+  stamp(a, 6);
+  // every wave's stores complete, then the flags of all results of this task
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lf.next_rec >= 0)
+      __hip_atomic_store(a.pflag + lf.next_rec, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int q = 0; q < lf.ntq; ++q)
+      __hip_atomic_store(a.tp_flag + a.leaf_tq[lf.tq0 + q], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.leaf_flag + s, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  stamp(a, 7);
 }
 
 // Partial-sum records of dense blocks whose column cluster this task's leaf
@@ -368,18 +546,23 @@ __device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forw
   double* Tb = a.tbuf + tp.toff * a.max_rhs;
   const T* Y = arena + tp.yoff;
   const int nout = k * nrhs;     // <= 64 * 32 = 8 * 256
+  // rows per stage: as many as the staging areas hold (Y: As, 128 x kKC
+  // doubles; y: Bs and the inverse area behind it, 32 x kKC + 64 x 64), so
+  // that each thread has many loads in flight per round trip
+  int R = 256;
+  while (R > kKC && (R * k > 128 * kKC || R * nrhs > 32 * kKC + 64 * 64)) R >>= 1;
   double s[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) s[q] = 0.0;
-  for (int r0 = 0; r0 < tp.ncols; r0 += kKC) {
-    const int rc = min(kKC, tp.ncols - r0);
+  for (int r0 = 0; r0 < tp.ncols; r0 += R) {
+    const int rc = min(R, tp.ncols - r0);
     for (int e = threadIdx.x; e < rc * k; e += blockDim.x) {
       const int r = e % rc, kk = e / rc;
-      As[kk * kKC + r] = double(Y[r0 + r + (int64_t)kk * tp.ldy]);
+      As[kk * R + r] = double(Y[r0 + r + (int64_t)kk * tp.ldy]);
     }
     for (int e = threadIdx.x; e < rc * nrhs; e += blockDim.x) {
       const int r = e % rc, c = e / rc;
-      Bs[c * kKC + r] = cload(a.y + tp.col0 + r0 + r + (int64_t)c * a.N);
+      Bs[c * R + r] = cload(a.y + tp.col0 + r0 + r + (int64_t)c * a.N);
     }
     __syncthreads();
 #pragma unroll
@@ -389,7 +572,7 @@ __device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forw
         const int kk = o % k, c = o / k;
         double sum = 0.0;
 #pragma unroll 8
-        for (int r = 0; r < rc; ++r) sum += As[kk * kKC + r] * Bs[c * kKC + r];
+        for (int r = 0; r < rc; ++r) sum += As[kk * R + r] * Bs[c * R + r];
         s[q] += sum;
       }
     }
@@ -412,7 +595,6 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
   // doubles): 144 KB
   extern __shared__ double smem[];
   __shared__ int s_task;
-  __shared__ int ready[kMaxContrib];
   double* acc = smem;
   double* As = acc + 128 * 32;
   double* Bs = As + 128 * kKC;
@@ -430,9 +612,9 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
       a.trace[kTraceFields * t + 3] = blockIdx.x;
     }
     switch (task.kind) {
-      case kFwdLeaf: run_leaf<T>(a, arena, inv, task.idx, true, acc, ready, As, Bs, Dg); break;
+      case kFwdLeaf: run_leaf<T>(a, arena, inv, task.idx, true, acc, As, Bs, Dg); break;
       case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
-      case kBwdLeaf: run_leaf<T>(a, arena, inv, task.idx, false, acc, ready, As, Bs, Dg); break;
+      case kBwdLeaf: run_leaf<T>(a, arena, inv, task.idx, false, acc, As, Bs, Dg); break;
       case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
       case kFwdPush: run_push<T>(a, arena, task.idx, true, As, Bs); break;
       case kBwdPush: run_push<T>(a, arena, task.idx, false, As, Bs); break;
@@ -511,7 +693,7 @@ hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const So
                                    int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s) {
   dev::solve_reset_kernel<<<1, 64, 0, s>>>(d.ctr);
   dev::SolveArgs a{d.tasks, d.leaves, d.dense, d.low, d.tprod, dims, d.y, d.tbuf, d.leaf_flag, d.tp_flag,
-                   d.ctr, d.push0, d.push_recs, d.pbuf, d.pflag, d.pstride, d.trace,
+                   d.ctr, d.push0, d.push_recs, d.leaf_tq, d.pbuf, d.pflag, d.pstride, d.trace,
                    d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch, 0};
   // acc 128 x 32, A staging 128 x kKC, B staging 32 x kKC, inverses 64 x 64
   const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC + 64 * 64) * sizeof(double);

@@ -20,6 +20,7 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
   for (int32_t l = 0; l < L; ++l) leaf_of_cluster[S.leaf_clusters[l]] = l;
   std::vector<std::vector<int32_t>> tp_after(2 * L);   // T-products to run after leaf task
   std::vector<int32_t> tp_need;                        // sweep position of the first consumer
+  std::vector<std::vector<int32_t>> by_leaf(2 * L);    // chunks computed by leaf tasks
   int64_t toff = 0;
   for (size_t b = 0; b < S.leaves.size(); ++b) {
     const BlockNode& B = S.blocks[S.leaves[b]];
@@ -48,30 +49,56 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
         dl[side + f].push_back(d);
       }
     } else {
-      STprod t{};
-      t.yoff = st.yoff[b];
-      t.ldy = cc.size();
-      t.col0 = cc.begin;
-      t.ncols = cc.size();
-      t.slot = st.slot[b];
-      t.lf0 = cc.leaf_first;
-      t.lf1 = cc.leaf_last;
-      t.cap = st.cap[b];
-      t.toff = toff;
-      toff += t.cap;
-      const int32_t tp = (int32_t)sc.tprod.size();
-      sc.tprod.push_back(t);
-      // forward: ready after the last leaf of sigma; backward: after the first.
-      // The key is the first row leaf that needs it in sweep order.
-      if (lower) tp_after[cc.leaf_last - 1].push_back(tp);
-      else tp_after[L + cc.leaf_first].push_back(tp);
-      tp_need.push_back(lower ? rc.leaf_first : L - rc.leaf_last);
+      // row chunks of whole leaves of sigma, each about kTprodChunkRows.  If
+      // rho starts within kNearLeaves leaves of the sweep after sigma's
+      // completing leaf p, the chunk of leaf p alone is computed by p's own
+      // leaf task (a separate task would sit on the sweep's critical path).
+      const int32_t p_end = lower ? cc.leaf_last - 1 : cc.leaf_first;
+      const bool next_needs = lower ? rc.leaf_first - cc.leaf_last < kNearLeaves
+                                    : cc.leaf_first - rc.leaf_last < kNearLeaves;
+      const int32_t tp0 = (int32_t)sc.tprod.size();
+      for (int32_t f0 = cc.leaf_first; f0 < cc.leaf_last;) {
+        const int32_t r0 = S.clusters[S.leaf_clusters[f0]].begin;
+        int32_t f1 = f0 + 1;
+        const bool alone = next_needs && f0 == p_end;
+        while (!alone && f1 < cc.leaf_last && S.clusters[S.leaf_clusters[f1]].end - r0 <= kTprodChunkRows &&
+               !(next_needs && f1 == p_end))
+          ++f1;
+        const int32_t r1 = S.clusters[S.leaf_clusters[f1 - 1]].end;
+        STprod t{};
+        t.yoff = st.yoff[b] + (r0 - cc.begin);
+        t.ldy = cc.size();
+        t.col0 = r0;
+        t.ncols = r1 - r0;
+        t.slot = st.slot[b];
+        t.lf0 = f0;
+        t.lf1 = f1;
+        t.cap = st.cap[b];
+        t.toff = toff;
+        toff += t.cap;
+        const int32_t tp = (int32_t)sc.tprod.size();
+        sc.tprod.push_back(t);
+        tp_need.push_back(lower ? rc.leaf_first : L - rc.leaf_last);
+        if (alone) {
+          by_leaf[(lower ? 0 : L) + p_end].push_back(tp);
+        } else {
+          // forward: ready after the chunk's last leaf; backward: after its
+          // first.  The key is the first row leaf that needs it in sweep order.
+          if (lower) tp_after[f1 - 1].push_back(tp);
+          else tp_after[L + f0].push_back(tp);
+        }
+        f0 = f1;
+      }
+      const int32_t ntp = (int32_t)sc.tprod.size() - tp0;
       for (int32_t f = rc.leaf_first; f < rc.leaf_last; ++f) {
         const ClusterNode& lc = S.clusters[S.leaf_clusters[f]];
         SLow w{};
         w.xoff = st.off[b] + (lc.begin - rc.begin);
         w.ldx = rc.size();
-        w.tp = tp;
+        w.tp = tp0;
+        w.ntp = ntp;
+        // sweep position at which the block's product is complete
+        w.pad = lower ? cc.leaf_last : L - cc.leaf_first;
         ll[side + f].push_back(w);
       }
     }
@@ -96,16 +123,23 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
     lf.d0 = (int32_t)sc.dense.size();
     lf.nd = (int32_t)dl[s].size();
     sc.dense.insert(sc.dense.end(), dl[s].begin(), dl[s].end());
+    // contributions in the order their products complete (the leaf task
+    // accumulates them in this order, waiting only when it reaches one)
+    std::stable_sort(ll[s].begin(), ll[s].end(), [](const SLow& x, const SLow& y) { return x.pad < y.pad; });
+    for (SLow& w : ll[s]) w.pad = 0;
     lf.l0 = (int32_t)sc.low.size();
     lf.nl = (int32_t)ll[s].size();
     sc.low.insert(sc.low.end(), ll[s].begin(), ll[s].end());
+    lf.tq0 = (int32_t)sc.leaf_tq.size();
+    lf.ntq = (int32_t)by_leaf[s].size();
+    sc.leaf_tq.insert(sc.leaf_tq.end(), by_leaf[s].begin(), by_leaf[s].end());
     sc.max_m = std::max(sc.max_m, lf.m);
   }
   // producers of the dense records: the leaf task of the preceding leaf for
   // the block coupling neighbours, otherwise the push task of the leaf that
   // completes sigma
   std::vector<std::vector<int32_t>> push(2 * L);
-  for (int32_t s = 0; s < 2 * L; ++s) sc.leaves[s].next_rec = -1;
+  for (int32_t s = 0; s < 2 * L; ++s) sc.leaves[s].next_rec = sc.leaves[s].prev_rec = -1;
   for (int32_t s = 0; s < 2 * L; ++s) {
     const bool fwd = s < L;
     const int32_t j = s % L;
@@ -115,8 +149,12 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
       const int32_t prod = fwd ? d.lf1 - 1 : d.lf0;     // leaf that completes sigma
       const bool neighbour = (d.lf1 - d.lf0 == 1) && (fwd ? prod == j - 1 : prod == j + 1);
       const int32_t ps = (fwd ? 0 : L) + prod;
-      if (neighbour && sc.leaves[ps].next_rec < 0) sc.leaves[ps].next_rec = r;
-      else push[ps].push_back(r);
+      if (neighbour && sc.leaves[ps].next_rec < 0) {
+        sc.leaves[ps].next_rec = r;
+        sc.leaves[s].prev_rec = r;
+      } else {
+        push[ps].push_back(r);
+      }
     }
   }
   // Work released by one leaf is queued in the order its consumers come in

@@ -29,7 +29,10 @@ struct SLeaf {
   int32_t d0, nd;      // dense contributions (partial-sum records) of this row
   int32_t l0, nl;      // low-rank contributions
   int32_t next_rec;    // dense record this leaf task computes after solving (-1: none)
-  int32_t pad;
+  int32_t prev_rec;    // record of this row formed by the preceding leaf task (-1: none)
+  int32_t tq0, ntq;    // T-product chunks this leaf task computes after solving
+                       // (leaf_tq[tq0 .. tq0 + ntq)): chunks of exactly this leaf's
+                       // rows whose block is needed within kNearLeaves leaves
 };
 struct SDense {        // block rows of leaf j: off + i + k*ld, k < ncols
   int64_t off;
@@ -38,15 +41,22 @@ struct SDense {        // block rows of leaf j: off + i + k*ld, k < ncols
   int32_t row0;        // first row of leaf j
   int32_t pad;
 };
-struct SLow {          // X rows of leaf j: xoff + i + kk*ldx
+struct SLow {          // X rows of leaf j: xoff + i + kk*ldx; T = sum of ntp chunk products from tp
   int64_t xoff;
-  int32_t ldx, tp;
+  int32_t ldx, tp, ntp, pad;
 };
-struct STprod {        // T = Y^T y[cols]: Y at yoff + r + kk*ldy
+// One row chunk of a low-rank block's product T = Y^T y[sigma]: the chunk
+// covers the leaves [lf0, lf1) of sigma, rows [col0, col0 + ncols); Y of
+// the chunk at yoff + r + kk*ldy.  The chunks of a block are summed by the
+// consumer, so a long sigma is reduced by several workgroups, each as soon
+// as its own leaves are solved.
+struct STprod {
   int64_t yoff;
-  int64_t toff;        // T (cap x nrhs, leading dimension cap) in the T buffer
+  int64_t toff;        // chunk product (cap x nrhs, leading dimension cap) in the T buffer
   int32_t ldy, col0, ncols, slot, lf0, lf1, cap, pad;
 };
+constexpr int32_t kTprodChunkRows = 1 << 30; // rows of sigma per T-product chunk (no row split)
+constexpr int32_t kNearLeaves = 4;          // consumers this close get the chunk from the leaf task
 constexpr int32_t kPushChunk = 2;   // partial-sum records per push task
 enum STaskKind : int32_t { kFwdLeaf = 0, kFwdTprod = 1, kBwdLeaf = 2, kBwdTprod = 3, kFwdPush = 4, kBwdPush = 5 };
 struct STask {
@@ -62,6 +72,7 @@ struct SolveSched {
   std::vector<STask> tasks;       // claim order
   std::vector<int32_t> push0;     // per push task: first record in push_recs (size #push + 1)
   std::vector<int32_t> push_recs; // dense records computed by push tasks
+  std::vector<int32_t> leaf_tq;   // T-product chunks computed by leaf tasks
   int32_t n_fwd_tasks = 0;
   int64_t tbuf_per_rhs = 0;       // doubles of the T buffer per right-hand side
   int64_t inv_elems = 0;          // elements of the inverse buffer (sum of m^2 over leaves)
@@ -89,6 +100,7 @@ struct SolveDev {
   int32_t* ctr;
   const int32_t* push0;
   const int32_t* push_recs;
+  const int32_t* leaf_tq;
   double* pbuf;
   int32_t* pflag;
   int64_t pstride;
