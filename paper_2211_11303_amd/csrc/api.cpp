@@ -74,6 +74,7 @@ void ensure_device(Shared& sh, PlanBundle& pb) {
 void SolveBufs::alloc(const SolveSched& sc, int32_t N, int32_t rhs) {
   max_rhs = rhs;
   inv = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.inv_elems)));   // sized for FP64
+  nm = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.nm_elems)));
   pivots = mem.keep(dmalloc<double>((size_t)N));
   y = mem.keep(dmalloc<double>((size_t)N * rhs));
   tbuf = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs));
@@ -91,6 +92,7 @@ void SolveBufs::alloc(const SolveSched& sc, int32_t N, int32_t rhs) {
 size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t rhs) {
   size_t b = 0;
   b += (size_t)std::max<int64_t>(1, sc.inv_elems) * sizeof(double);
+  b += (size_t)std::max<int64_t>(1, sc.nm_elems) * sizeof(double);
   b += (size_t)N * sizeof(double) * (1 + rhs);
   b += (size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs * sizeof(double);
   b += (2 * (size_t)sc.L + sc.tprod.size() + sc.dense.size() + 1) * sizeof(int32_t);
@@ -109,6 +111,7 @@ SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs
   v.push_recs = d.push_recs;
   v.leaf_tq = d.leaf_tq;
   v.inv = b.inv;
+  v.nm = b.nm;
   v.pivots = b.pivots;
   v.y = b.y;
   v.tbuf = b.tbuf;

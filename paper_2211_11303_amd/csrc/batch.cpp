@@ -171,7 +171,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
   SolveSched& M = *out;
   const size_t np = S.size();
   std::vector<int32_t> LB(np), DB(np), LWB(np), TPB(np), PB(np), PRB(np), TQB(np);
-  std::vector<int64_t> TOFF(np), INVB(np);
+  std::vector<int64_t> TOFF(np), INVB(np), NMB(np);
   int32_t Ltot = 0;
   for (size_t p = 0; p < np; ++p) {
     const SolveSched& s = *S[p];
@@ -183,6 +183,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
     PRB[p] = (int32_t)M.push_recs.size();
     TOFF[p] = M.tbuf_per_rhs;
     INVB[p] = M.inv_elems;
+    NMB[p] = M.nm_elems;
     Ltot += s.L;
     for (SDense r : s.dense) {
       r.off += a[p];
@@ -212,6 +213,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
     for (int32_t q : s.leaf_tq) M.leaf_tq.push_back(q + TPB[p]);
     M.tbuf_per_rhs += s.tbuf_per_rhs;
     M.inv_elems += s.inv_elems;
+    M.nm_elems += s.nm_elems;
     M.max_m = std::max(M.max_m, s.max_m);
   }
   M.push0.push_back((int32_t)M.push_recs.size());
@@ -229,6 +231,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
       if (lf.next_rec >= 0) lf.next_rec += DB[p];
       if (lf.prev_rec >= 0) lf.prev_rec += DB[p];
       lf.tq0 += TQB[p];
+      if (lf.nm >= 0) lf.nm += NMB[p];
       const int32_t dst = q < s.L ? LB[p] + q : Ltot + LB[p] + (q - s.L);
       M.leaves[dst] = lf;
     }

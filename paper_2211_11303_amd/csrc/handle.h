@@ -111,6 +111,7 @@ struct DevSched {
 struct SolveBufs {
   Owned mem;
   void* inv = nullptr;        // triangle inverses (sized for FP64)
+  void* nm = nullptr;         // neighbour blocks times inverses (sized for FP64)
   double* pivots = nullptr;   // U_ii, cluster order
   double* y = nullptr;        // N x max_rhs
   double* tbuf = nullptr;

@@ -18,6 +18,9 @@
 namespace hlu {
 namespace dev {
 
+typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int kMaxTilesPerWave = 6;   // (192 / 16) row tiles x 2 column tiles / 4 wavefronts
+
 constexpr int kSolveThreads = 256;
 constexpr int kMaxRhsTile = 8;          // columns per register tile of the triangular solve
 constexpr int kSpinLimit = 1 << 25;     // bounded waits; on overflow the error flag is set
@@ -344,8 +347,8 @@ __device__ bool low_batched(const SolveArgs& a, const T* arena, const SLeaf& lf,
 
 
 template <class T>
-__device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s, bool forward, double* acc,
-                         double* As, double* Bs, double* Dg) {
+__device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, const T* nm, int s, bool forward,
+                         double* acc, double* As, double* Bs, double* Dg) {
   const SLeaf lf = a.leaves[s];
   const int m = lf.m, nrhs = a.nrhs;
   const int ldacc = a.max_rhs;
@@ -386,7 +389,13 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s
   SDense Dn{};
   const bool next_lds = lf.next_rec >= 0 && a.dense[lf.next_rec].m <= 128 && a.dense[lf.next_rec].ncols <= kKC;
   if (lf.next_rec >= 0) Dn = a.dense[lf.next_rec];
-  if (next_lds) {
+  const bool fused = lf.nm >= 0;   // record formed from r with (D Inv), see below
+  if (fused) {
+    for (int e = threadIdx.x; e < Dn.m * m; e += blockDim.x) {
+      const int i = e % Dn.m, k = e / Dn.m;
+      As[k * 128 + i] = double(nm[lf.nm + e]);
+    }
+  } else if (next_lds) {
     for (int e = threadIdx.x; e < Dn.m * Dn.ncols; e += blockDim.x) {
       const int i = e % Dn.m, k = e / Dn.m;
       As[k * 128 + i] = double(arena[Dn.off + i + (int64_t)k * Dn.ld]);
@@ -435,12 +444,73 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, int s
   }
   stamp(a, 1);
   __syncthreads();
-  if (diag_lds) apply_inverse<double>(Dg, m, forward, acc, ldacc, nrhs);
-  else apply_inverse<T>(inv + lf.inv, m, forward, acc, ldacc, nrhs);
-  stamp(a, 5);
-  for (int o = threadIdx.x; o < m * nrhs; o += blockDim.x)
-    cstore(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N, acc[(o % m) * ldacc + o / m]);
-  if (lf.next_rec >= 0) {
+  if (fused) {
+    // y_j = Inv r_j and the neighbour record P = (D Inv) r_j as one product
+    // [Inv; D Inv] r_j on the FP64 matrix cores (16 x 16 x 4 tiles): the
+    // stacked rows (m + rows of the record <= 192) in 16-row tiles, the
+    // columns in 16-column tiles, tiles dealt round robin to the wavefronts.
+    // Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k;
+    // result register r of lane l is D[l/16 + 4r][l%16].
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rows = m + Dn.m;
+    const int rt_n = (rows + 15) >> 4, ct_n = (nrhs + 15) >> 4, ks_n = (m + 3) >> 2;
+    const int ntiles = rt_n * ct_n;
+    // tile t = wave + 4 it: with ct_n in {1, 2} all of a wavefront's tiles
+    // share one column tile, so one B operand feeds all its MFMAs per step
+    const int ct = wave % ct_n;
+    const int j = 16 * ct + (lane & 15), kl = lane >> 4;
+    double4_t dacc[kMaxTilesPerWave];
+#pragma unroll
+    for (int it = 0; it < kMaxTilesPerWave; ++it) dacc[it] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int ks = 0; ks < ks_n; ++ks) {
+      const int k = 4 * ks + kl;
+      const double bv = (k < m && j < nrhs) ? acc[k * ldacc + j] : 0.0;
+#pragma unroll
+      for (int it = 0; it < kMaxTilesPerWave; ++it) {
+        const int t = wave + 4 * it;   // uniform within the wavefront
+        if (t < ntiles) {
+          const int i = 16 * (t / ct_n) + (lane & 15);
+          double av = 0.0;
+          if (k < m) {
+            if (i < m) av = forward ? (i > k ? Dg[i + k * m] : (i == k ? 1.0 : 0.0)) : (i <= k ? Dg[i + k * m] : 0.0);
+            else if (i < rows) av = As[k * 128 + (i - m)];
+          }
+          dacc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, dacc[it], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    double* P = a.pbuf + (int64_t)lf.next_rec * a.pstride;
+#pragma unroll
+    for (int it = 0; it < kMaxTilesPerWave; ++it) {
+      const int t = wave + 4 * it;
+      if (t < ntiles) {
+        const int rt = t / ct_n;
+        const int col = 16 * ct + (lane & 15);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int row = 16 * rt + (lane >> 4) + 4 * rr;
+          const double v = dacc[it][rr];
+          if (col < nrhs && row < m) {
+            acc[row * ldacc + col] = v;
+            cstore(a.y + lf.row0 + row + (int64_t)col * a.N, v);
+          } else if (col < nrhs && row < rows) {
+            cstore(P + (row - m) + col * Dn.m, v);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    stamp(a, 5);
+  } else {
+    if (diag_lds) apply_inverse<double>(Dg, m, forward, acc, ldacc, nrhs);
+    else apply_inverse<T>(inv + lf.inv, m, forward, acc, ldacc, nrhs);
+    stamp(a, 5);
+    for (int o = threadIdx.x; o < m * nrhs; o += blockDim.x)
+      cstore(a.y + lf.row0 + (o % m) + (int64_t)(o / m) * a.N, acc[(o % m) * ldacc + o / m]);
+  }
+  if (lf.next_rec >= 0 && !fused) {
     // the neighbouring row's dense block times this solution row (both in LDS)
     const SDense& D = Dn;
     double pr[kPer];
@@ -588,7 +658,7 @@ __device__ void run_tprod(const SolveArgs& a, const T* arena, int tpi, bool forw
 
 template <class T>
 __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T* arena, const T* inv,
-                                                                        SolveArgs a0) {
+                                                                        const T* nm, SolveArgs a0) {
   SolveArgs a = a0;
   // LDS: acc (128 x 32 doubles), A staging (128 x kKC doubles), B staging
   // (32 x kKC doubles), triangle inverses of a leaf up to 64 rows (64 x 64
@@ -612,9 +682,9 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
       a.trace[kTraceFields * t + 3] = blockIdx.x;
     }
     switch (task.kind) {
-      case kFwdLeaf: run_leaf<T>(a, arena, inv, task.idx, true, acc, As, Bs, Dg); break;
+      case kFwdLeaf: run_leaf<T>(a, arena, inv, nm, task.idx, true, acc, As, Bs, Dg); break;
       case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
-      case kBwdLeaf: run_leaf<T>(a, arena, inv, task.idx, false, acc, As, Bs, Dg); break;
+      case kBwdLeaf: run_leaf<T>(a, arena, inv, nm, task.idx, false, acc, As, Bs, Dg); break;
       case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
       case kFwdPush: run_push<T>(a, arena, task.idx, true, As, Bs); break;
       case kBwdPush: run_push<T>(a, arena, task.idx, false, As, Bs); break;
@@ -682,6 +752,40 @@ __global__ void __launch_bounds__(256) diag_inverse_kernel(const T* arena, const
   }
 }
 
+// For every leaf task with a neighbour record (lf.nm >= 0): the record's
+// block D (rows of the next leaf x this leaf) times this leaf's triangle
+// inverse (forward: unit lower L^{-1}; backward: U^{-1}), in FP64, stored in
+// the factor's type.  One workgroup per leaf task; D and the inverse in LDS.
+template <class T>
+__global__ void __launch_bounds__(256) next_inverse_kernel(const T* arena, const SLeaf* leaves,
+                                                           const SDense* dense, const T* inv, T* nm, int L) {
+  extern __shared__ double sm[];
+  const int s = blockIdx.x;
+  const SLeaf lf = leaves[s];
+  if (lf.nm < 0) return;
+  const bool forward = s < L;
+  const SDense d = dense[lf.next_rec];
+  const int m = lf.m, dm = d.m;
+  double* Ds = sm;              // dm x m, leading dimension dm (<= 128 x 64)
+  double* Is = sm + 128 * 64;   // m x m (<= 64 x 64)
+  for (int e = threadIdx.x; e < dm * m; e += blockDim.x) {
+    const int i = e % dm, k = e / dm;
+    Ds[e] = double(arena[d.off + i + (int64_t)k * d.ld]);
+  }
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int q = e % m, k = e / m;
+    const double v = double(inv[lf.inv + e]);
+    Is[e] = forward ? (q > k ? v : (q == k ? 1.0 : 0.0)) : (q <= k ? v : 0.0);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < dm * m; e += blockDim.x) {
+    const int i = e % dm, k = e / dm;
+    double sum = 0.0;
+    for (int q = 0; q < m; ++q) sum += Ds[i + q * dm] * Is[q + k * m];
+    nm[lf.nm + e] = T(sum);
+  }
+}
+
 __global__ void solve_reset_kernel(int32_t* ctr) {
   if (threadIdx.x < 2) ctr[threadIdx.x] = 0;
 }
@@ -703,7 +807,8 @@ hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const So
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     attr = true;
   }
-  dev::solve_persistent_kernel<T><<<grid, dev::kSolveThreads, sh, s>>>(arena, static_cast<const T*>(d.inv), a);
+  dev::solve_persistent_kernel<T><<<grid, dev::kSolveThreads, sh, s>>>(arena, static_cast<const T*>(d.inv),
+                                                                       static_cast<const T*>(d.nm), a);
   return hipGetLastError();
 }
 
@@ -722,6 +827,16 @@ hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s)
   }
   dim3 g(d.L, 2);
   dev::diag_inverse_kernel<T><<<g, 256, sh, s>>>(arena, d.leaves, static_cast<T*>(d.inv), d.pivots, cols);
+  // neighbour blocks times the inverses (96 KB of LDS)
+  constexpr size_t kNmLds = (128 * 64 + 64 * 64) * sizeof(double);
+  static bool attr2 = false;
+  if (!attr2) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::next_inverse_kernel<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmLds);
+    attr2 = true;
+  }
+  dev::next_inverse_kernel<T><<<2 * d.L, 256, kNmLds, s>>>(arena, d.leaves, d.dense, static_cast<const T*>(d.inv),
+                                                          static_cast<T*>(d.nm), d.L);
   return hipGetLastError();
 }
 

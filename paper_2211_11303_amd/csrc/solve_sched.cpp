@@ -161,6 +161,17 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
   // the sweep (forward: ascending rows, backward: descending), and the
   // records are split into tasks of kPushChunk so that several workgroups
   // form them together.
+  // neighbour block times the inverse, for leaves up to 64 rows whose
+  // neighbour record has at most 128 rows
+  for (int32_t s = 0; s < 2 * L; ++s) {
+    SLeaf& lf = sc.leaves[s];
+    lf.nm = -1;
+    if (lf.next_rec < 0) continue;
+    const SDense& d = sc.dense[lf.next_rec];
+    if (lf.m > 64 || d.m > 128 || d.ncols != lf.m) continue;
+    lf.nm = sc.nm_elems;
+    sc.nm_elems += (int64_t)d.m * lf.m;
+  }
   auto emit = [&](int32_t s, int32_t push_kind, int32_t tp_kind) {
     const bool fwd = s < L;
     std::vector<int32_t>& pr = push[s];

@@ -33,6 +33,9 @@ struct SLeaf {
   int32_t tq0, ntq;    // T-product chunks this leaf task computes after solving
                        // (leaf_tq[tq0 .. tq0 + ntq)): chunks of exactly this leaf's
                        // rows whose block is needed within kNearLeaves leaves
+  int64_t nm;          // next_rec's block times this leaf's triangle inverse in the
+                       // NM buffer (rows of the record x m, leading dimension = rows;
+                       // -1: formed from the solution instead)
 };
 struct SDense {        // block rows of leaf j: off + i + k*ld, k < ncols
   int64_t off;
@@ -76,6 +79,7 @@ struct SolveSched {
   int32_t n_fwd_tasks = 0;
   int64_t tbuf_per_rhs = 0;       // doubles of the T buffer per right-hand side
   int64_t inv_elems = 0;          // elements of the inverse buffer (sum of m^2 over leaves)
+  int64_t nm_elems = 0;           // elements of the NM buffer
   int32_t max_m = 0;
   // algorithmic element reads of one application (both sweeps), for the
   // roofline: dense entries read + low-rank capacity entries touched is
@@ -92,6 +96,7 @@ struct SolveDev {
   const SLow* low;
   const STprod* tprod;
   void* inv;            // triangle inverses of the diagonal leaves (factor storage type)
+  void* nm;             // neighbour blocks times the inverses (factor storage type)
   double* pivots;       // U_ii of every diagonal leaf, cluster order (N)
   double* y;
   double* tbuf;
@@ -110,7 +115,8 @@ struct SolveDev {
 
 // Both triangle inverses of every diagonal leaf (arena storage type T,
 // arithmetic in FP64), written to d.inv, and the pivots U_ii to d.pivots;
-// run after each factorization.
+// then, for every leaf task with a neighbour record, that record's block
+// times the leaf's inverse (d.nm).  Run after each factorization.
 template <class T>
 hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s);
 
