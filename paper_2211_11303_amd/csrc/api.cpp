@@ -233,6 +233,31 @@ void harvest_timing(hlu_s* h) {
   h->tev_used = 0;
 }
 
+int64_t* trunc_trace_buffer(size_t* ops);
+
+// Debug: writes the per-op truncation trace of the last factorisation to
+// the file named by HLU_DEBUG_TRUNC_TRACE.
+void dump_trunc_trace(const Plan& pl) {
+  const char* path = getenv("HLU_DEBUG_TRUNC_TRACE");
+  size_t cap = 0;
+  int64_t* buf = trunc_trace_buffer(&cap);
+  if (!path || !buf) return;
+  const size_t n = std::min(cap, pl.trunc.size());
+  std::vector<int64_t> t(6 * n);
+  HIP_OK(hipMemcpy(t.data(), buf, t.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (FILE* f = fopen(path, "wb")) {
+    fwrite(t.data(), sizeof(int64_t), t.size(), f);
+    fclose(f);
+  }
+  if (FILE* f = fopen((std::string(path) + ".waves").c_str(), "wb")) {
+    for (const Wave& w : pl.waves) {
+      const int32_t v[2] = {w.begin[kTrunc], w.count[kTrunc]};
+      fwrite(v, sizeof(v), 1, f);
+    }
+    fclose(f);
+  }
+}
+
 void record_factor(hlu_s* h, const hlu_factor_opts* o) {
   h->prec = o->prec;
   h->eps = o->eps;
@@ -579,6 +604,7 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     h->factored = true;
     gather_stats(h, h->sbuf->pivots);
     h->stats.capped_blocks = status[1];
+    dump_trunc_trace(h->pb->ps.factor);
     if (status[1] > 0 && o->max_rank == 0) {
       set_error("hlu_factor: a truncated rank exceeded the block capacity");
       overflow = HLU_ERR_RANK_OVERFLOW;

@@ -5,6 +5,8 @@
 // inside the truncation is always FP64.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <cstdint>
 
 #include "plan.h"
@@ -494,10 +496,13 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
   return A;
 }
 
+constexpr int kCompressMin = 8;         // S larger than this is compressed before the eigensolver
+constexpr double kCompressTol = 0.003;  // relative pivot tolerance of that compression, in units of eps
+
 template <class T>
 __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops, const TruncPart* parts,
                                                     int32_t* dims, double eps, double floor_rel,
-                                                    int32_t* status) {
+                                                    int32_t* status, int64_t* trace, int32_t op_base) {
   __shared__ double bufG[kKMax * kLd];
   __shared__ double bufR[kKMax * kLd];
   __shared__ double bufS[kKMax * kLd];
@@ -513,6 +518,8 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
 
   const TruncOp op = ops[blockIdx.x];
   const double tol2 = floor_rel * floor_rel;
+  const int64_t t_start = trace ? (int64_t)wall_clock64() : 0;
+  int rounds = 0, k_first = -1, r1_first = -1;
   if (threadIdx.x == 0) {
     s_r = dims[op.slot];
     s_part = 0;
@@ -580,6 +587,10 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
     if (threadIdx.x == 0) s_r1 = r1c;
     __syncthreads();
     const int r1 = s_r1;
+    if (k_first < 0) {
+      k_first = K;
+      r1_first = r1;
+    }
     int rnew = 0;
     if (r1 > 0) {
       // (2) T1 = Gy R^T -> G buffer; S = R T1 -> S buffer
@@ -607,11 +618,57 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         }
       }
       __syncthreads();
-      // (3) eigen-decomposition of S
-      double* Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red);
-      double* Free = (Sres == bufS) ? bufG : bufS;
-      for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = fmax(Sres[k * kLd + k], 0.0);
+      // (3) eigen-decomposition of S.  S is PSD and only eigenpairs above
+      // (eps sigma_1)^2 are kept, so S is first compressed by a pivoted
+      // Cholesky S ~ R2^T R2 (r2 x r1) whose dropped Schur complement is far
+      // below that threshold; the eigenpairs come from the small M = R2 R2^T
+      // (r2 x r2): S u = lambda u with u = R2^T v / sqrt(lambda).  When the
+      // compression does not pay, S (kept in the W buffer) goes to Jacobi.
+      double* Sres;
+      double* Free;
+      for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) bufW[(e / r1) * kLd + e % r1] = bufS[(e / r1) * kLd + e % r1];
       __syncthreads();
+      int r2 = r1;
+      if (r1 > kCompressMin) {
+        const double ts = kCompressTol * fmax(eps, floor_rel);
+        r2 = pivoted_cholesky(bufS, bufG, r1, ts * ts, sel, dvec, chosen, s_int, s_dbl);
+      }
+      if (r2 <= kKMax / 2 && r2 + 2 < r1) {
+        // M = R2 R2^T in columns [0, 32) of the S buffer; Jacobi double
+        // buffer in columns [32, 64); eigenvectors V -> W buffer
+        for (int e = threadIdx.x; e < r2 * r2; e += blockDim.x) {
+          const int k = e / r2, l = e % r2;
+          double v = 0.0;
+          for (int j = 0; j < r1; ++j) v += bufG[k * kLd + j] * bufG[l * kLd + j];
+          bufS[k * kLd + l] = v;
+        }
+        __syncthreads();
+        double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red);
+        for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = k < r2 ? fmax(Mres[k * kLd + k], 0.0) : 0.0;
+        __syncthreads();
+        // eigenvectors of S, r1 x r2 -> S buffer, then into the W buffer
+        for (int e = threadIdx.x; e < r1 * r2; e += blockDim.x) {
+          const int i = e / r2, c = e % r2;
+          double v = 0.0;
+          if (mu[c] > 0.0) {
+            for (int k = 0; k < r2; ++k) v += bufG[k * kLd + i] * bufW[k * kLd + c];
+            v /= sqrt(mu[c]);
+          }
+          bufS[i * kLd + c] = v;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < r1 * r2; e += blockDim.x) bufW[(e / r2) * kLd + e % r2] = bufS[(e / r2) * kLd + e % r2];
+        __syncthreads();
+        Sres = bufS;
+        Free = bufG;
+      } else {
+        for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) bufS[(e / r1) * kLd + e % r1] = bufW[(e / r1) * kLd + e % r1];
+        __syncthreads();
+        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red);
+        Free = (Sres == bufS) ? bufG : bufS;
+        for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = fmax(Sres[k * kLd + k], 0.0);
+        __syncthreads();
+      }
       for (int k = threadIdx.x; k < r1; k += blockDim.x) {
         int rank = 0;
         for (int l = 0; l < r1; ++l)
@@ -677,14 +734,40 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       s_r = 0;
     }
     __syncthreads();
+    ++rounds;
     if (s_done) break;
   }
   if (threadIdx.x == 0) dims[op.slot] = s_r;
+  if (trace && threadIdx.x == 0) {   // debug: per-op size and clocks
+    int64_t* t = trace + 6 * ((int64_t)op_base + blockIdx.x);
+    t[0] = op.m;
+    t[1] = op.n;
+    t[2] = rounds | (k_first << 8) | ((int64_t)r1_first << 20);
+    t[3] = s_r;
+    t[4] = t_start;
+    t[5] = (int64_t)wall_clock64();
+  }
 }
 
 }  // namespace dev
 
 // ------------------------------------------------------------ launchers
+
+// Debug (HLU_DEBUG_TRUNC_TRACE): per truncation op of a factor plan, the
+// block size, rounds, final rank and clocks.  Allocated on first use.
+constexpr int64_t kTruncTraceOps = 12 << 20;
+int64_t* trunc_trace_buffer(size_t* ops) {
+  static int64_t* buf = nullptr;
+  static bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (getenv("HLU_DEBUG_TRUNC_TRACE") &&
+        hipMalloc(&buf, (size_t)kTruncTraceOps * 6 * sizeof(int64_t)) != hipSuccess)
+      buf = nullptr;
+  }
+  if (ops) *ops = (size_t)kTruncTraceOps;
+  return buf;
+}
 
 template <class T, class C>
 hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
@@ -719,8 +802,10 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
                                                       tile_base, dims);
   }
   if (w.count[kTrunc] > 0) {
+    int64_t* tr = trunc_trace_buffer(nullptr);
+    if (tr && w.begin[kTrunc] + w.count[kTrunc] > kTruncTraceOps) tr = nullptr;
     dev::trunc_kernel<T><<<w.count[kTrunc], 256, 0, s>>>(arena, P.trunc + w.begin[kTrunc], P.parts, dims,
-                                                          eps, floor_rel, status);
+                                                          eps, floor_rel, status, tr, w.begin[kTrunc]);
   }
   return hipGetLastError();
 }
