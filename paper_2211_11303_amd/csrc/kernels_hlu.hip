@@ -390,8 +390,11 @@ __device__ int pivoted_cholesky(double* G, double* R, int K, double tol2, int* p
 // the indices round-robin; the rotations of the n/2 disjoint pairs are
 // computed first, then A' = J^T A J is written to B (double buffering) and
 // W <- W J.  Returns the buffer that holds the final A.
+// Cyclic Jacobi on the symmetric n x n matrix A (eigenvalues left on the
+// diagonal of the returned buffer, eigenvectors accumulated in W), until the
+// squared off-diagonal Frobenius norm is at most off_rel times the total.
 __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, int* pk, int* pfirst,
-                          double* red) {
+                          double* red, double off_rel) {
   const int np = n + (n & 1);
   const int npair = np / 2;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) W[(e / n) * kLd + e % n] = (e / n == e % n) ? 1.0 : 0.0;
@@ -416,7 +419,7 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
     const double offs = red[0] + red[1] + red[2] + red[3];
     const double tots = red[4] + red[5] + red[6] + red[7];
     __syncthreads();
-    if (tots == 0.0 || offs <= 1e-26 * tots) break;
+    if (tots == 0.0 || offs <= off_rel * tots) break;
     for (int r = 0; r < np - 1; ++r) {
       for (int k = threadIdx.x; k < npair; k += blockDim.x) {
         int p, q;
@@ -518,6 +521,11 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
 
   const TruncOp op = ops[blockIdx.x];
   const double tol2 = floor_rel * floor_rel;
+  // Jacobi stops when the remaining off-diagonal part of the core is far
+  // below the truncation threshold: (0.01 eps)^4 relative in squared
+  // Frobenius norm (eigenvalues of the core are squared singular values)
+  const double te = 0.01 * fmax(eps, floor_rel);
+  const double off_rel = fmax(1e-26, te * te * te * te);
   const int64_t t_start = trace ? (int64_t)wall_clock64() : 0;
   int rounds = 0, k_first = -1, r1_first = -1;
   if (threadIdx.x == 0) {
@@ -643,7 +651,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
           bufS[k * kLd + l] = v;
         }
         __syncthreads();
-        double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red);
+        double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel);
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = k < r2 ? fmax(Mres[k * kLd + k], 0.0) : 0.0;
         __syncthreads();
         // eigenvectors of S, r1 x r2 -> S buffer, then into the W buffer
@@ -664,7 +672,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       } else {
         for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) bufS[(e / r1) * kLd + e % r1] = bufW[(e / r1) * kLd + e % r1];
         __syncthreads();
-        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red);
+        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red, off_rel);
         Free = (Sres == bufS) ? bufG : bufS;
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = fmax(Sres[k * kLd + k], 0.0);
         __syncthreads();
