@@ -12,7 +12,9 @@ A step is one GMRES(50) solve of the workload's right-hand sides (8 columns
 for each of the seeds 0, 1, 2: 24 columns, iterated together) with the
 cached FP32 H-LU preconditioner (SpMV, H-solves, orthogonalisation, true
 residual).  value = right-hand sides solved per second.  The FP32 and FP64
-factorisations are timed separately (HIP events) and reported beside it.
+factorisations are timed separately (HIP events) and reported beside it,
+with the same steps for the FP64 H-LU and for FP32 factors computed with
+FP64 task arithmetic, and one solve of the same columns at kappa = 16.
 
 Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -38,7 +40,12 @@ def parse():
     p.add_argument("--nrhs", type=int, default=8)
     p.add_argument("--restart", type=int, default=50)
     p.add_argument("--tol", type=float, default=1e-8)
-    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 H-LU comparison")
+    p.add_argument("--no-fp64", action="store_true",
+                   help="skip the FP64 and FP32-storage/FP64-arithmetic H-LU comparisons")
+    p.add_argument("--kappa2", type=float, default=16.0,
+                   help="second wavenumber of the workload (near a cavity resonance at 32^3): one GMRES "
+                        "call per precision, reported beside the timed steps (0: skip)")
+    p.add_argument("--kappa2-max-iters", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-level", type=int, default=5,
                    help="cluster-tree level of the principal block the oracle sample factors")
@@ -318,6 +325,45 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def second_kappa(args, H1, Xs, stream):
+    """The same mesh, structure and x* columns at kappa = args.kappa2 (near
+    the cavity eigenvalue 26 pi^2 at kappa = 16): one factorisation (timed
+    after a first one) and one GMRES call, capped at --kappa2-max-iters
+    iterations, per precision, and for FP32 once more at eps / 10;
+    reported, not part of the timed steps."""
+    import torch
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, _ = hlu.hlu_kuhn_assemble(args.n, args.kappa2)
+    A2 = hlu.SpMat(rp, ci, va)
+    H2 = hlu.HLU(rp, ci, va, share=H1)
+    B2 = A2.hlu_spmv(Xs)
+    out = {"kappa": args.kappa2, "max_iters": args.kappa2_max_iters}
+    runs = [("fp32", args.eps)] if args.no_fp64 else [("fp32", args.eps), ("fp64", args.eps),
+                                                      ("fp32", args.eps / 10)]
+    for prec, eps in runs:
+        key = prec if eps == args.eps else f"{prec}_eps{eps:g}"
+        log(f"kappa {args.kappa2:g} {prec} eps {eps:g}: factorisations")
+        H2.hlu_factor(eps, prec=prec, allow_overflow=True)
+        _, tf = event_time(lambda: H2.hlu_factor(eps, prec=prec, allow_overflow=True), stream)
+        log(f"kappa {args.kappa2:g} {prec} eps {eps:g}: factor {tf:.2f}s; GMRES (at most "
+            f"{args.kappa2_max_iters} iterations)")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, infos = hlu.gmres_solve(A2, B2, H2, restart=args.restart, tol=args.tol,
+                                   max_iters=args.kappa2_max_iters, raise_on_fail=False)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        st = H2.hlu_get_stats()
+        it = [i["iters"] for i in infos]
+        log(f"kappa {args.kappa2:g} {prec} eps {eps:g}: iters {min(it)}..{max(it)}, {T:.2f}s")
+        out[key] = {"eps": eps, "factor_s": tf, "solves_per_s": Xs.shape[0] / T, "iters": [min(it), max(it)],
+                     "converged": all(i["converged"] for i in infos),
+                     "relres_max": max(i["relres"] for i in infos),
+                     "err_vs_xstar_max": ((x - Xs).norm(dim=1) / Xs.norm(dim=1)).max().item(),
+                     "ranks": {"max": st["max_rank"], "mean": st["mean_rank"]}}
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -369,7 +415,7 @@ def main():
                                raise_on_fail=False)
 
     result = {}
-    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp64"]):
+    for prec in (["fp32"] if args.no_fp64 else ["fp32", "fp32-acc64", "fp64"]):
         tf, st = factor(prec)
         for w in range(args.warmup):
             solve_batch(w)
@@ -450,6 +496,13 @@ def main():
                      "err_vs_xstar_max_fp64": r64["err_xstar_max"],
                      "ranks_fp64": {"max": r64["max_rank"], "mean": r64["mean_rank"]},
                      "fp32_over_fp64_solves": r32["solves_per_s"] / r64["solves_per_s"]})
+        ra = result["fp32-acc64"]
+        line["fp32_storage_fp64_tasks"] = {
+            "factor_s": ra["factor_s"], "solves_per_s": ra["solves_per_s"], "iters": sorted(set(ra["iters"])),
+            "relres_max": ra["relres_max"], "err_vs_xstar_max": ra["err_xstar_max"],
+            "ranks": {"max": ra["max_rank"], "mean": ra["mean_rank"]}}
+    if args.kappa2 > 0:
+        line["kappa2"] = second_kappa(args, H, X[0], stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args.n, args.kappa, args.leaf, args.eps, args.restart, args.tol,

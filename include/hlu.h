@@ -52,7 +52,13 @@ typedef enum {
   HLU_ERR_UNSUPPORTED = -8     /* input outside what this build handles       */
 } hlu_status;
 
-typedef enum { HLU_FP64 = 0, HLU_FP32 = 1 } hlu_precision;
+/* Precision of an H-LU.  HLU_FP64: factors stored and computed in FP64.
+ * HLU_FP32: factors stored in FP32 and the dense factor tasks (leaf LU,
+ * triangular solves, products) computed in FP32.  HLU_FP32_ACC64: factors
+ * stored in FP32, the dense factor tasks computed in FP64 and rounded to
+ * FP32 when stored.  In every mode the truncation's small dense algebra is
+ * FP64, and the H-solves read the stored factors and accumulate in FP64. */
+typedef enum { HLU_FP64 = 0, HLU_FP32 = 1, HLU_FP32_ACC64 = 2 } hlu_precision;
 
 typedef struct hlu_spmat_s* hlu_spmat;  /* device CSR of A, for y = A x      */
 typedef struct hlu_s* hlu_handle;       /* structure + H-LU of one problem    */
@@ -277,6 +283,16 @@ hlu_status gmres_solve_batch(hlu_batch b, const double* d_b, double* d_x, int32_
  *   - Overlap: each of the `workers` threads owns a HIP stream (default
  *     priority), so factorisations and solves of different requests run on
  *     the device concurrently.
+ *   - Refinement (refine_iters > 0): a GMRES call first runs at most
+ *     refine_iters iterations.  Columns that have not converged by then
+ *     (near a resonance of the cavity the factor at eps is too coarse a
+ *     preconditioner) make the worker refactor the cached factor in place
+ *     with eps multiplied by refine_eps_factor (0 < factor < 1), at most
+ *     max_refines times per factor and not below 1e-7, and solve those
+ *     columns again with the full gmres.max_iters.  Columns that converged
+ *     keep their first result, so a result still does not depend on its
+ *     companions; it does depend on whether the cached factor was refined
+ *     by an earlier request.  The refined factor stays cached.
  * Device memory of the cache and of the workers' GMRES buffers is owned by
  * the server (the workers keep their largest buffers for reuse). */
 typedef struct hlu_server_s* hlu_server;
@@ -288,6 +304,9 @@ typedef struct {
   int32_t leaf;            /* leaf size of the cluster trees                     */
   hlu_factor_opts factor;  /* options of every factorisation                     */
   hlu_gmres_opts gmres;    /* options of every solve                             */
+  int32_t refine_iters;    /* 0: no refinement; else iterations of a first try   */
+  int32_t max_refines;     /* refactorisations per cached factor, >= 0           */
+  double refine_eps_factor;/* eps multiplier per refinement, in (0, 1)          */
 } hlu_server_opts;
 typedef struct {
   int64_t submitted, completed, failed;
@@ -298,6 +317,7 @@ typedef struct {
   int64_t coalesced_requests;  /* requests that shared a GMRES call              */
   size_t bytes_in_use, peak_bytes;  /* admitted device bytes, now and at peak    */
   int32_t cached_factors;
+  int64_t refinements;         /* refactorisations at a smaller eps               */
 } hlu_server_stats;
 
 hlu_status hlu_server_create(const hlu_server_opts* o, hlu_server* out);

@@ -21,7 +21,7 @@ STATUS = {
     -7: "HLU_ERR_RANK_OVERFLOW", -8: "HLU_ERR_UNSUPPORTED",
 }
 STATUS_CODES = {v: k for k, v in STATUS.items()}
-HLU_FP64, HLU_FP32 = 0, 1
+HLU_FP64, HLU_FP32, HLU_FP32_ACC64 = 0, 1, 2
 
 
 class HluCsr(ctypes.Structure):
@@ -57,14 +57,15 @@ class Stats(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("workers", c_int32), ("max_batch_rhs", c_int32), ("hbm_budget", c_size_t), ("eta", c_double),
-                ("leaf", c_int32), ("factor", FactorOpts), ("gmres", GmresOpts)]
+                ("leaf", c_int32), ("factor", FactorOpts), ("gmres", GmresOpts), ("refine_iters", c_int32),
+                ("max_refines", c_int32), ("refine_eps_factor", c_double)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_int64), ("completed", c_int64), ("failed", c_int64),
                 ("factorizations", c_int64), ("cache_hits", c_int64), ("evictions", c_int64),
                 ("gmres_calls", c_int64), ("coalesced_requests", c_int64), ("bytes_in_use", c_size_t),
-                ("peak_bytes", c_size_t), ("cached_factors", c_int32)]
+                ("peak_bytes", c_size_t), ("cached_factors", c_int32), ("refinements", c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

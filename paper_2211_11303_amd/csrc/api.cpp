@@ -44,7 +44,8 @@ void check_opts(const hlu_factor_opts* o) {
   HLU_REQUIRE(o != nullptr, HLU_ERR_INVALID_ARG, "factor options are NULL");
   HLU_REQUIRE(o->eps >= 0.0 && std::isfinite(o->eps), HLU_ERR_INVALID_ARG, "eps must be finite and >= 0");
   HLU_REQUIRE(o->max_rank >= 0, HLU_ERR_INVALID_ARG, "max_rank must be >= 0");
-  HLU_REQUIRE(o->prec == HLU_FP32 || o->prec == HLU_FP64, HLU_ERR_INVALID_ARG, "prec must be HLU_FP32 or HLU_FP64");
+  HLU_REQUIRE(o->prec == HLU_FP32 || o->prec == HLU_FP64 || o->prec == HLU_FP32_ACC64, HLU_ERR_INVALID_ARG,
+              "prec must be HLU_FP64, HLU_FP32 or HLU_FP32_ACC64");
 }
 
 std::shared_ptr<PlanBundle> get_bundle(Shared& sh, int32_t kcap) {
@@ -243,7 +244,7 @@ void dump_trunc_trace(const Plan& pl) {
   int64_t* buf = trunc_trace_buffer(&cap);
   if (!path || !buf) return;
   const size_t n = std::min(cap, pl.trunc.size());
-  std::vector<int64_t> t(6 * n);
+  std::vector<int64_t> t((size_t)kTruncTraceFields * n);
   HIP_OK(hipMemcpy(t.data(), buf, t.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
   if (FILE* f = fopen(path, "wb")) {
     fwrite(t.data(), sizeof(int64_t), t.size(), f);
@@ -261,7 +262,7 @@ void dump_trunc_trace(const Plan& pl) {
 void record_factor(hlu_s* h, const hlu_factor_opts* o) {
   h->prec = o->prec;
   h->eps = o->eps;
-  h->factor_compute64 = (o->prec == HLU_FP64);
+  h->factor_compute64 = fp64_tasks(o->prec);
   const PlanSet& ps = h->pb->ps;
   h->stats.workspace_bytes = (int64_t)work_layout(ps, o->prec).total;
   h->stats.factor_waves = (int64_t)ps.factor.waves.size();
@@ -595,7 +596,7 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     h->factored = false;
     record_factor(h, o);
-    if (o->prec == HLU_FP32) factor_impl<float>(h, s);
+    if (fp32_storage(o->prec)) factor_impl<float>(h, s);
     else factor_impl<double>(h, s);
     HIP_OK(hipStreamSynchronize(s));
     int32_t status[2];
@@ -620,11 +621,11 @@ hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs,
     hipStream_t s = (hipStream_t)stream;
     const char* e = getenv("HLU_DEBUG_WAVE_SOLVE");
     if (e && e[0] == '1') {   // the planned wave form of the same solve, for cross-checks
-      if (h->prec == HLU_FP32)
+      if (fp32_storage(h->prec))
         solve_impl<float>(h, h->pb->ps.fwd_bwd, h->pb->dsolve, d_b, d_x, nrhs, ld, s);
       else
         solve_impl<double>(h, h->pb->ps.fwd_bwd, h->pb->dsolve, d_b, d_x, nrhs, ld, s);
-    } else if (h->prec == HLU_FP32) {
+    } else if (fp32_storage(h->prec)) {
       solve_persistent_impl<float>(h, d_b, d_x, nrhs, ld, s);
     } else {
       solve_persistent_impl<double>(h, d_b, d_x, nrhs, ld, s);
@@ -638,7 +639,7 @@ hlu_status hlu_apply_lu(hlu_handle h, const double* d_v, double* d_y, int32_t nr
                 "hlu_apply_lu: bad arguments");
     HLU_REQUIRE(h->factored, HLU_ERR_STATE, "hlu_apply_lu: handle is not factored");
     hipStream_t s = (hipStream_t)stream;
-    if (h->prec == HLU_FP32)
+    if (fp32_storage(h->prec))
       solve_impl<float>(h, h->pb->ps.apply, h->pb->dapply, d_v, d_y, nrhs, ld, s);
     else
       solve_impl<double>(h, h->pb->ps.apply, h->pb->dapply, d_v, d_y, nrhs, ld, s);

@@ -283,7 +283,7 @@ void factor_batch_impl(hlu_batch_s* b, hipStream_t s) {
   for (size_t p = 0; p < b->hs.size(); ++p)
     factor_prepare<T>(b->hs[p], reinterpret_cast<T*>(base + b->arena_off[p]), dims + b->slot_base[p], s);
   HIP_OK(zero_int_launch(status, 64, s));
-  const bool compute64 = b->opts.prec == HLU_FP64;
+  const bool compute64 = fp64_tasks(b->opts.prec);
   int32_t tile_base = 0;
   for (const Wave& w : b->plan.waves) {
     HIP_OK(launch_wave<T>(reinterpret_cast<T*>(base), b->dplan.P, w, dims, status, b->opts.eps, kFloorRel,
@@ -309,7 +309,7 @@ void solve_batch_impl(hlu_batch_s* b, const double* x_in, double* x_out, int32_t
 }
 
 void solve_batch(hlu_batch_s* b, const double* in, double* out, int32_t nrhs, hipStream_t s) {
-  if (b->opts.prec == HLU_FP32) solve_batch_impl<float>(b, in, out, nrhs, s);
+  if (fp32_storage(b->opts.prec)) solve_batch_impl<float>(b, in, out, nrhs, s);
   else solve_batch_impl<double>(b, in, out, nrhs, s);
 }
 
@@ -447,7 +447,7 @@ hlu_status hlu_factor_batch(hlu_batch b, void* stream) {
       h->factored = false;
       record_factor(h, &b->opts);
     }
-    if (b->opts.prec == HLU_FP32) factor_batch_impl<float>(b, s);
+    if (fp32_storage(b->opts.prec)) factor_batch_impl<float>(b, s);
     else factor_batch_impl<double>(b, s);
     HIP_OK(hipStreamSynchronize(s));
     int32_t status[2];

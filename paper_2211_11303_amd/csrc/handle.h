@@ -34,7 +34,11 @@ constexpr size_t kMaxTimedEvents = 4096;    // event pairs kept before they are 
 constexpr double kFloorRel = 1e-7;
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
-inline size_t elem_size(int32_t prec) { return prec == HLU_FP32 ? sizeof(float) : sizeof(double); }
+// Factor storage in FP32 (HLU_FP32, HLU_FP32_ACC64) or FP64; dense factor
+// tasks in FP64 arithmetic (HLU_FP64, HLU_FP32_ACC64) or FP32.
+inline bool fp32_storage(int32_t prec) { return prec != HLU_FP64; }
+inline bool fp64_tasks(int32_t prec) { return prec != HLU_FP32; }
+inline size_t elem_size(int32_t prec) { return fp32_storage(prec) ? sizeof(float) : sizeof(double); }
 
 template <class T>
 T* dmalloc(size_t n) {

@@ -394,7 +394,7 @@ __device__ int pivoted_cholesky(double* G, double* R, int K, double tol2, int* p
 // diagonal of the returned buffer, eigenvectors accumulated in W), until the
 // squared off-diagonal Frobenius norm is at most off_rel times the total.
 __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, int* pk, int* pfirst,
-                          double* red, double off_rel) {
+                          double* red, double off_rel, int* sweeps) {
   const int np = n + (n & 1);
   const int npair = np / 2;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) W[(e / n) * kLd + e % n] = (e / n == e % n) ? 1.0 : 0.0;
@@ -420,6 +420,7 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
     const double tots = red[4] + red[5] + red[6] + red[7];
     __syncthreads();
     if (tots == 0.0 || offs <= off_rel * tots) break;
+    ++*sweeps;
     for (int r = 0; r < np - 1; ++r) {
       for (int k = threadIdx.x; k < npair; k += blockDim.x) {
         int p, q;
@@ -527,7 +528,17 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   const double te = 0.01 * fmax(eps, floor_rel);
   const double off_rel = fmax(1e-26, te * te * te * te);
   const int64_t t_start = trace ? (int64_t)wall_clock64() : 0;
-  int rounds = 0, k_first = -1, r1_first = -1;
+  int rounds = 0, k_first = -1, r1_first = -1, sweeps = 0;
+  // debug: clocks per phase (thread 0, after the phase's closing barrier)
+  int64_t ph[6] = {0, 0, 0, 0, 0, 0};
+  int64_t t_last = t_start;
+  auto mark = [&](int i) {
+    if (trace) {
+      const int64_t t = (int64_t)wall_clock64();
+      ph[i] += t - t_last;
+      t_last = t;
+    }
+  };
   if (threadIdx.x == 0) {
     s_r = dims[op.slot];
     s_part = 0;
@@ -591,9 +602,11 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       bufS[a * kLd + b] *= dinv[a] * dinv[b];
     }
     __syncthreads();
+    mark(0);
     const int r1c = pivoted_cholesky(bufG, bufR, K, tol2, piv, dvec, chosen, s_int, s_dbl);
     if (threadIdx.x == 0) s_r1 = r1c;
     __syncthreads();
+    mark(1);
     const int r1 = s_r1;
     if (k_first < 0) {
       k_first = K;
@@ -641,6 +654,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         const double ts = kCompressTol * fmax(eps, floor_rel);
         r2 = pivoted_cholesky(bufS, bufG, r1, ts * ts, sel, dvec, chosen, s_int, s_dbl);
       }
+      mark(2);
       if (r2 <= kKMax / 2 && r2 + 2 < r1) {
         // M = R2 R2^T in columns [0, 32) of the S buffer; Jacobi double
         // buffer in columns [32, 64); eigenvectors V -> W buffer
@@ -651,7 +665,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
           bufS[k * kLd + l] = v;
         }
         __syncthreads();
-        double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel);
+        double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel, &sweeps);
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = k < r2 ? fmax(Mres[k * kLd + k], 0.0) : 0.0;
         __syncthreads();
         // eigenvectors of S, r1 x r2 -> S buffer, then into the W buffer
@@ -672,11 +686,12 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       } else {
         for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) bufS[(e / r1) * kLd + e % r1] = bufW[(e / r1) * kLd + e % r1];
         __syncthreads();
-        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red, off_rel);
+        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red, off_rel, &sweeps);
         Free = (Sres == bufS) ? bufG : bufS;
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = fmax(Sres[k * kLd + k], 0.0);
         __syncthreads();
       }
+      mark(3);
       for (int k = threadIdx.x; k < r1; k += blockDim.x) {
         int rank = 0;
         for (int l = 0; l < r1; ++l)
@@ -715,6 +730,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         Sres[a * kLd + c] = v;
       }
       __syncthreads();
+      mark(4);
       // (5) X_C = Xa[:, piv] Z ; Y_C = Ya Ty (row tiles staged in the R buffer)
       for (int pass = 0; pass < 2; ++pass) {
         const ColSrc* src = pass == 0 ? xs : ys;
@@ -738,6 +754,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
           __syncthreads();
         }
       }
+      mark(5);
     } else if (threadIdx.x == 0) {
       s_r = 0;
     }
@@ -747,13 +764,14 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   }
   if (threadIdx.x == 0) dims[op.slot] = s_r;
   if (trace && threadIdx.x == 0) {   // debug: per-op size and clocks
-    int64_t* t = trace + 6 * ((int64_t)op_base + blockIdx.x);
+    int64_t* t = trace + kTruncTraceFields * ((int64_t)op_base + blockIdx.x);
     t[0] = op.m;
     t[1] = op.n;
-    t[2] = rounds | (k_first << 8) | ((int64_t)r1_first << 20);
-    t[3] = s_r;
+    t[2] = rounds | ((int64_t)(k_first & 0xfff) << 8) | ((int64_t)(r1_first & 0xfff) << 20);
+    t[3] = s_r | ((int64_t)sweeps << 16);
     t[4] = t_start;
     t[5] = (int64_t)wall_clock64();
+    for (int i = 0; i < 6; ++i) t[6 + i] = ph[i];
   }
 }
 
@@ -770,7 +788,7 @@ int64_t* trunc_trace_buffer(size_t* ops) {
   if (!tried) {
     tried = true;
     if (getenv("HLU_DEBUG_TRUNC_TRACE") &&
-        hipMalloc(&buf, (size_t)kTruncTraceOps * 6 * sizeof(int64_t)) != hipSuccess)
+        hipMalloc(&buf, (size_t)kTruncTraceOps * kTruncTraceFields * sizeof(int64_t)) != hipSuccess)
       buf = nullptr;
   }
   if (ops) *ops = (size_t)kTruncTraceOps;

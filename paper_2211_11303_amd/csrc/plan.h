@@ -56,6 +56,11 @@ struct TruncOp {     // low-rank C (X: m x cap, Y: n x cap, rank dims[slot])
   int64_t xoff, yoff;
   int32_t m, n, ldx, ldy, slot, cap, p0, np;
 };
+// Debug trace of a truncation op: m, n, rounds | K << 8 | r1 << 20, final
+// rank | Jacobi sweeps << 16, start and end clocks, then the clocks spent in
+// the Gram products, the pivoted Cholesky, the core and its compression,
+// the eigensolver, the rank choice with the small products, the rebuild.
+constexpr int kTruncTraceFields = 12;
 
 struct FillOp {
   MatRef M;

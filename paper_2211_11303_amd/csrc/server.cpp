@@ -14,6 +14,9 @@
 //    own Krylov process, so a result does not depend on its companions.
 //  * Overlap: each worker owns a HIP stream, so the factorisations and
 //    solves of different requests run on the device at the same time.
+//  * Refinement: columns that a cached factor does not bring to tol within
+//    a first budget of iterations get that factor refactored at a smaller
+//    eps and are solved again.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -68,6 +71,8 @@ struct Entry {
   hlu_spmat A = nullptr;
   hlu::Owned mem;            // device CSR and workspace
   size_t bytes = 0;
+  double eps = 0;            // truncation tolerance of the current factor
+  int32_t refines = 0;       // refactorisations at a smaller eps so far
   bool ready = false, busy = false;
   int64_t last_use = 0;
 };
@@ -96,7 +101,7 @@ namespace {
 using hlu::fail;
 
 size_t gmres_bytes(const hlu_server_s* S, int32_t N, int32_t k) {
-  return gmres_workspace_bytes(N, k, S->o.gmres.restart) + 2 * hlu::align256((size_t)N * k * sizeof(double));
+  return gmres_workspace_bytes(N, k, S->o.gmres.restart) + 3 * hlu::align256((size_t)N * k * sizeof(double));
 }
 
 // Plans mesh n if new (caller holds plan_mu, not mu).
@@ -196,6 +201,7 @@ bool pick(hlu_server_s* S, Job* job) {
       ne->n = r->n;
       ne->kappa = r->kappa;
       ne->bytes = m.factor_bytes;
+      ne->eps = S->o.factor.eps;
       e = ne.get();
       S->cache[key] = std::move(ne);
     }
@@ -210,6 +216,22 @@ bool pick(hlu_server_s* S, Job* job) {
     return true;
   }
   return false;
+}
+
+constexpr double kMinRefineEps = 1e-7;   // the truncation's resolution floor
+
+// (Re)factorisation of a built entry at its eps on stream s (outside mu);
+// with a rank cap, blocks at the cap are accepted.
+void refactor_entry(hlu_server_s* S, Entry* e, hipStream_t s) {
+  hlu_factor_opts fo = S->o.factor;
+  fo.eps = e->eps;
+  hlu_status st = hlu_factor(e->h, &fo, s);
+  if (st == HLU_ERR_RANK_OVERFLOW && fo.max_rank > 0) st = HLU_OK;
+  if (st != HLU_OK) fail(st, hlu::get_error());
+}
+
+bool can_refine(const hlu_server_s* S, const Entry* e) {
+  return S->o.refine_iters > 0 && e->refines < S->o.max_refines && e->eps > kMinRefineEps;
 }
 
 // Factorisation of entry e on stream s (outside mu).
@@ -231,9 +253,8 @@ void factor_entry(hlu_server_s* S, Entry* e, const Mesh& m, hipStream_t s) {
   if (st != HLU_OK) fail(st, hlu::get_error());
   void* work = e->mem.keep(hlu::dmalloc<char>(ws));
   st = hlu_bind_workspace(e->h, work, ws);
-  if (st == HLU_OK) st = hlu_factor(e->h, &S->o.factor, s);
-  if (st == HLU_ERR_RANK_OVERFLOW && S->o.factor.max_rank > 0) st = HLU_OK;
-  if (st != HLU_OK && st != HLU_ERR_RANK_OVERFLOW) fail(st, hlu::get_error());
+  if (st != HLU_OK) fail(st, hlu::get_error());
+  refactor_entry(S, e, s);
 }
 
 // Device buffers of one worker's GMRES calls, grown on demand and kept (a
@@ -242,6 +263,7 @@ struct WorkerBufs {
   std::unique_ptr<hlu::Owned> mem;
   double* db = nullptr;
   double* dx = nullptr;
+  double* dt = nullptr;   // results of the columns solved again after a refinement
   void* work = nullptr;
   size_t vec_elems = 0, work_bytes = 0;
   void reserve(size_t elems, size_t wb) {
@@ -252,6 +274,7 @@ struct WorkerBufs {
     work_bytes = std::max(wb, work_bytes);
     db = mem->keep(hlu::dmalloc<double>(vec_elems));
     dx = mem->keep(hlu::dmalloc<double>(vec_elems));
+    dt = mem->keep(hlu::dmalloc<double>(vec_elems));
     work = mem->keep(hlu::dmalloc<char>(work_bytes));
   }
 };
@@ -269,6 +292,7 @@ void run_job(hlu_server_s* S, Job& job, hipStream_t s, WorkerBufs& wb) {
   }
   const int32_t N = m->N;
   bool factored_now = false;
+  int64_t refined = 0;
   status = hlu::guard([&] {
     if (!e->ready) {
       factor_entry(S, e, *m, s);
@@ -284,8 +308,48 @@ void run_job(hlu_server_s* S, Job& job, hipStream_t s, WorkerBufs& wb) {
                             s));
       c += r->nrhs;
     }
-    hlu_status g = gmres_solve(e->A, db, dx, job.cols, N, e->h, &S->o.gmres, info.data(), wb.work, wbytes, s);
+    // first try: a limited budget if the factor can still be refined
+    hlu_gmres_opts go = S->o.gmres;
+    bool capped = can_refine(S, e) && S->o.refine_iters < go.max_iters;
+    if (capped) go.max_iters = S->o.refine_iters;
+    hlu_status g = gmres_solve(e->A, db, dx, job.cols, N, e->h, &go, info.data(), wb.work, wbytes, s);
     if (g != HLU_OK && g != HLU_ERR_NOT_CONVERGED) fail(g, hlu::get_error());
+    // columns that missed tol: refactor at a smaller eps (or, when that is
+    // no longer allowed, lift the iteration cap) and solve them again
+    while (g == HLU_ERR_NOT_CONVERGED) {
+      std::vector<int32_t> open;
+      for (int32_t k = 0; k < job.cols; ++k)
+        if (!info[k].converged) open.push_back(k);
+      if (open.empty()) break;
+      if (can_refine(S, e)) {
+        e->eps = std::max(e->eps * S->o.refine_eps_factor, kMinRefineEps);
+        e->refines++;
+        refactor_entry(S, e, s);
+        refined++;
+      } else if (!capped) {
+        break;
+      }
+      go = S->o.gmres;
+      capped = can_refine(S, e) && S->o.refine_iters < go.max_iters;
+      if (capped) go.max_iters = S->o.refine_iters;
+      // right-hand sides of the open columns, packed, from the requests
+      std::vector<const double*> src;
+      for (Request* r : job.group)
+        for (int32_t k = 0; k < r->nrhs; ++k) src.push_back(r->b + (size_t)k * N);
+      const int32_t no = (int32_t)open.size();
+      for (int32_t i = 0; i < no; ++i)
+        HIP_OK(hipMemcpyAsync(db + (size_t)i * N, src[open[i]], (size_t)N * sizeof(double), hipMemcpyHostToDevice,
+                              s));
+      std::vector<hlu_gmres_info> io(no);
+      const size_t wbo = gmres_workspace_bytes(N, no, go.restart);
+      g = gmres_solve(e->A, db, wb.dt, no, N, e->h, &go, io.data(), wb.work, wbo, s);
+      if (g != HLU_OK && g != HLU_ERR_NOT_CONVERGED) fail(g, hlu::get_error());
+      for (int32_t i = 0; i < no; ++i) {
+        HIP_OK(hipMemcpyAsync(dx + (size_t)open[i] * N, wb.dt + (size_t)i * N, (size_t)N * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+        info[open[i]] = io[i];
+      }
+    }
     c = 0;
     for (Request* r : job.group) {
       HIP_OK(hipMemcpyAsync(r->x, dx + (size_t)c * N, (size_t)N * r->nrhs * sizeof(double), hipMemcpyDeviceToHost,
@@ -300,6 +364,7 @@ void run_job(hlu_server_s* S, Job& job, hipStream_t s, WorkerBufs& wb) {
   e->last_use = ++S->tick;
   if (factored_now) S->st.factorizations++;
   else S->st.cache_hits++;
+  S->st.refinements += refined;
   S->st.gmres_calls++;
   if (job.group.size() > 1) S->st.coalesced_requests += (int64_t)job.group.size();
   if (status != HLU_OK) {
@@ -375,6 +440,9 @@ hlu_status hlu_server_create(const hlu_server_opts* o, hlu_server* out) {
     check_opts(&o->factor);
     HLU_REQUIRE(o->gmres.restart >= 1 && o->gmres.max_iters >= 1 && o->gmres.tol > 0, HLU_ERR_INVALID_ARG,
                 "hlu_server_create: bad GMRES options");
+    HLU_REQUIRE(o->refine_iters >= 0 && (o->refine_iters == 0 || (o->max_refines >= 0 && o->refine_eps_factor > 0 &&
+                                                                   o->refine_eps_factor < 1)),
+                HLU_ERR_INVALID_ARG, "hlu_server_create: bad refinement options");
     auto S = std::make_unique<hlu_server_s>();
     S->o = *o;
     HIP_OK(hipGetDevice(&S->device));

@@ -11,7 +11,7 @@ import numpy as np
 
 from . import _lib as L
 
-PREC = {"fp64": L.HLU_FP64, "fp32": L.HLU_FP32}
+PREC = {"fp64": L.HLU_FP64, "fp32": L.HLU_FP32, "fp32-acc64": L.HLU_FP32_ACC64}
 
 
 def _torch():
@@ -344,13 +344,18 @@ class HLUBatch:
 class Server:
     """hlu_server_*: request loop with a factor cache per (n, kappa),
     admission by device bytes and continuous batching of right-hand sides.
-    Right-hand sides and results are host numpy arrays of shape (nrhs, N)."""
+    Right-hand sides and results are host numpy arrays of shape (nrhs, N).
+    refine_iters > 0: columns not converged after that many iterations make
+    the cached factor be refactored with eps * refine_eps_factor (at most
+    max_refines times) and are solved again."""
 
     def __init__(self, workers=4, max_batch_rhs=32, hbm_budget=200 << 30, eta=2.0, leaf=64, eps=1e-3,
-                 max_rank=32, prec="fp32", restart=50, max_iters=1000, tol=1e-8):
+                 max_rank=32, prec="fp32", restart=50, max_iters=1000, tol=1e-8, refine_iters=0, max_refines=2,
+                 refine_eps_factor=0.1):
         o = L.ServerOpts(int(workers), int(max_batch_rhs), int(hbm_budget), float(eta), int(leaf),
                          L.FactorOpts(float(eps), int(max_rank), PREC[prec]),
-                         L.GmresOpts(int(restart), int(max_iters), float(tol)))
+                         L.GmresOpts(int(restart), int(max_iters), float(tol)), int(refine_iters), int(max_refines),
+                         float(refine_eps_factor))
         h = ctypes.c_void_p()
         L.check(L.lib().hlu_server_create(ctypes.byref(o), ctypes.byref(h)))
         self.handle = h

@@ -44,7 +44,7 @@ def _rhs(batch, members, nrhs, seed):
     return xs, bs, batch.stack(bs)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32-acc64"])
 def test_batch_equals_one_by_one(gpu, prec):
     import torch
     from paper_2211_11303_amd import hlu

@@ -38,7 +38,7 @@ def test_spmv(gpu, n, nrhs):
     assert np.abs(Y2.cpu().numpy() - (2 * ref - X)).max() <= 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32-acc64"])
 def test_cfg0_parity(gpu, prec):
     """4^3 cubes, kappa 2, leaf 32, eps 1e-6, GMRES(30) to 1e-10, seeds 0..9."""
     import torch

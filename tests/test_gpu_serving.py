@@ -91,3 +91,48 @@ def test_admission_evicts_and_rejects(gpu):
         srv.hlu_server_wait(t)
     assert e.value.status == L.STATUS_CODES["HLU_ERR_OUT_OF_MEMORY"]
     srv.close()
+
+
+def _near_resonant_kappa(n, rel_gap):
+    """kappa with kappa^2 just below the fourth non-zero eigenvalue of the
+    discrete cavity problem K u = lambda M u (dense, small n)."""
+    import scipy.linalg as sl
+    from paper_2211_11303_amd import hlu
+    K = _csr(n, 0.0).toarray()
+    M = K - _csr(n, 1.0).toarray()
+    w = sl.eigh(K, M, eigvals_only=True)
+    w = w[w > 1e-6 * w.max()]
+    return float(np.sqrt(w[3] * (1.0 - rel_gap)))
+
+
+def test_refinement_near_resonance(gpu):
+    """kappa^2 0.1% below a cavity eigenvalue: with eps = 0.1 (leaf 8) GMRES
+    needs about 50 iterations, more than the first-try budget of 20, so the
+    server refactors at eps = 1e-3 and the request converges in about 10.  A
+    later request for the same (n, kappa) is served by the refined factor."""
+    from paper_2211_11303_amd import inputs
+    from paper_2211_11303_amd import hlu
+    n = 4
+    kappa = _near_resonant_kappa(n, 1e-3)
+    A = _csr(n, kappa)
+    N = inputs.num_interior_edges(n)
+    b = np.stack([A @ x for x in inputs.exact_solution_cols(N, 2, seed=5)])
+    common = dict(workers=1, max_batch_rhs=8, hbm_budget=4 << 30, leaf=8, eps=0.1, prec="fp64", restart=30,
+                  max_iters=300, tol=1e-10)
+    plain = hlu.Server(**common)
+    xp, ip, _, _ = plain.hlu_server_wait(plain.hlu_server_submit(n, kappa, b))
+    plain.close()
+    assert all(i["converged"] for i in ip) and min(i["iters"] for i in ip) > 20, ip
+    srv = hlu.Server(refine_iters=20, max_refines=2, refine_eps_factor=0.01, **common)
+    x, infos, _, _ = srv.hlu_server_wait(srv.hlu_server_submit(n, kappa, b))
+    st = srv.hlu_server_get_stats()
+    assert st["refinements"] == 1 and st["factorizations"] == 1, st
+    for c in range(2):
+        assert infos[c]["converged"] and infos[c]["iters"] <= 20, infos
+        assert np.linalg.norm(A @ x[c] - b[c]) <= 1e-10 * np.linalg.norm(b[c])
+    x2, i2, _, _ = srv.hlu_server_wait(srv.hlu_server_submit(n, kappa, b[:1]))
+    st = srv.hlu_server_get_stats()
+    srv.close()
+    assert st["refinements"] == 1 and st["cache_hits"] == 1, st
+    assert i2[0]["iters"] == infos[0]["iters"]
+    assert np.abs(x2[0] - x[0]).max() <= 1e-14 * np.abs(x[0]).max()

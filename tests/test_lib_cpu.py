@@ -106,6 +106,8 @@ def test_plan_sizes_reported():
     b64 = h.hlu_workspace_bytes(1e-6, prec="fp64")
     b32 = h.hlu_workspace_bytes(1e-6, prec="fp32")
     assert b32 < b64
+    # FP32 storage whatever the arithmetic of the dense tasks
+    assert h.hlu_workspace_bytes(1e-6, prec="fp32-acc64") == b32
     st = h.hlu_get_stats()
     assert st["factor_waves"] > 0 and st["factor_tasks"] > 0 and st["solve_waves"] > 0
 
@@ -132,3 +134,14 @@ def test_build_shared_pattern_rules():
     if not np.array_equal(moved, ci2):
         with pytest.raises(L.HluError):
             hlu.HLU(rp2, moved, va2, share=proto)
+
+
+def test_server_rejects_bad_refinement_options():
+    """Refinement options are checked before any device work."""
+    from paper_2211_11303_amd import _lib as L
+    from paper_2211_11303_amd import hlu
+    for kw in (dict(refine_iters=-1), dict(refine_iters=10, refine_eps_factor=1.0),
+               dict(refine_iters=10, refine_eps_factor=0.0), dict(refine_iters=10, max_refines=-1)):
+        with pytest.raises(L.HluError) as e:
+            hlu.Server(**kw)
+        assert e.value.status == L.STATUS_CODES["HLU_ERR_INVALID_ARG"], kw
