@@ -46,6 +46,9 @@ def parse():
                    help="second wavenumber of the workload (near a cavity resonance at 32^3): one GMRES "
                         "call per precision, reported beside the timed steps (0: skip)")
     p.add_argument("--kappa2-max-iters", type=int, default=300)
+    p.add_argument("--copy-probe-gib", type=float, default=0.0,
+                   help="first run one plain device-to-device copy of this many GiB, whose HBM counter "
+                        "readings calibrate those of the solve kernel under rocprofv3 --pmc")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-level", type=int, default=5,
                    help="cluster-tree level of the principal block the oracle sample factors")
@@ -60,6 +63,8 @@ def parse():
     p.add_argument("--serve-sizes", type=str, default="8,12,16,20,24")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--serve-budget-gb", type=float, default=200.0)
+    p.add_argument("--serve-refine-iters", type=int, default=100,
+                   help="first-try GMRES iterations before a cached factor is refined (0: never refine)")
     p.add_argument("--serve-warm", action="store_true",
                    help="factor every (n, kappa) of the request list before the timed arrivals (steady state)")
     p.add_argument("--batch-max-rank", type=int, default=32,
@@ -231,8 +236,10 @@ def serve_main(args):
     Poisson arrivals at --serve-rate, n from --serve-sizes, kappa in 1..16,
     1..32 right-hand sides, x* seed = 1000 + request index), answered by
     hlu_server (FP32 H-LU eps 1e-3, rank capacity 32, FP64 GMRES(50) to 1e-8,
-    factor cache per (n, kappa), continuous batching).  Latency is measured
-    by the server from submission to completion (host wall clock)."""
+    factor cache per (n, kappa), continuous batching, refinement of a factor
+    whose columns miss tol within --serve-refine-iters iterations).  Latency
+    is measured by the server from submission to completion (host wall
+    clock)."""
     import numpy as np
     import scipy.sparse as sp
     from paper_2211_11303_amd import hlu, inputs
@@ -253,7 +260,8 @@ def serve_main(args):
         rhs.append((xs, np.ascontiguousarray((A @ xs.T).T)))
     srv = hlu.Server(workers=args.serve_workers, max_batch_rhs=32, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
                      eta=2.0, leaf=args.leaf, eps=1e-3, max_rank=32, prec="fp32", restart=args.restart,
-                     max_iters=1000, tol=args.tol)
+                     max_iters=1000, tol=args.tol, refine_iters=args.serve_refine_iters, max_refines=2,
+                     refine_eps_factor=0.1)
     for n in sizes:
         log(f"planning {n}^3")
         srv.hlu_server_prepare(n)
@@ -275,13 +283,15 @@ def serve_main(args):
         tickets.append(srv.hlu_server_submit(r["n"], r["kappa"], rhs[i][1]))
         if i % 100 == 99:
             log(f"submitted {i + 1}")
-    lat, que, errs, rel, iters, failed = [], [], [], [], [], 0
+    lat, que, errs, rel, iters, failed, failed_req = [], [], [], [], [], 0, []
     for i, tk in enumerate(tickets):
         x, infos, q, l = srv.hlu_server_wait(tk, raise_on_fail=False)
         lat.append(l)
         que.append(q)
         if not all(f["converged"] for f in infos):
             failed += 1
+            failed_req.append({"n": reqs[i]["n"], "kappa": reqs[i]["kappa"], "nrhs": reqs[i]["nrhs"],
+                               "iters": max(f["iters"] for f in infos), "relres": max(f["relres"] for f in infos)})
         xs = rhs[i][0]
         errs.append(float(np.max(np.linalg.norm(x - xs, axis=1) / np.linalg.norm(xs, axis=1))))
         rel.append(max(f["relres"] for f in infos))
@@ -303,7 +313,8 @@ def serve_main(args):
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} Poisson requests at {args.serve_rate:g}/s (default_rng(11)), n in "
                                f"{list(sizes)}, kappa in 1..16, 1..32 rhs; FP32 H-LU eps 1e-3 rank capacity 32, "
-                               f"GMRES({args.restart}) to {args.tol:g}; {args.serve_workers} workers, "
+                               f"GMRES({args.restart}) to {args.tol:g}, refinement after {args.serve_refine_iters} "
+                               f"iterations (eps x 0.1, at most twice); {args.serve_workers} workers, "
                                f"budget {args.serve_budget_gb:g} GB" + ("; cache warmed" if args.serve_warm else ""),
                    "requests": len(reqs), "rate": args.serve_rate, "sizes": list(sizes)},
         "p50_latency_s": float(np.percentile(lat, 50)),
@@ -313,6 +324,8 @@ def serve_main(args):
         "wall_s": T,
         "rhs_total": nrhs_total,
         "not_converged": failed,
+        "not_converged_requests": failed_req[:10],
+        "refine_iters": args.serve_refine_iters,
         "relres_max": max(rel),
         "err_vs_xstar_max": max(errs),
         "iters": [min(iters), max(iters)],
@@ -381,6 +394,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_probe_gib > 0:
+        nb = int(args.copy_probe_gib * (1 << 30))
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes read and {nb} bytes written by one copy kernel")
+        del src, dst
     t = time.perf_counter()
     log(f"assembling n={args.n}")
     rp, ci, va, mid = hlu.hlu_kuhn_assemble(args.n, args.kappa)

@@ -229,6 +229,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
       lf.d0 += DB[p];
       lf.l0 += LWB[p];
       if (lf.next_rec >= 0) lf.next_rec += DB[p];
+      if (lf.next_rec2 >= 0) lf.next_rec2 += DB[p];
       if (lf.prev_rec >= 0) lf.prev_rec += DB[p];
       lf.tq0 += TQB[p];
       if (lf.nm >= 0) lf.nm += NMB[p];

@@ -19,14 +19,15 @@ namespace hlu {
 namespace dev {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
-constexpr int kMaxTilesPerWave = 6;   // (192 / 16) row tiles x 2 column tiles / 4 wavefronts
+constexpr int kRecTilesPerWave = 4;   // neighbour record: (128 / 16) row tiles x 2 column tiles / 4 wavefronts
+constexpr int kSolTilesPerWave = 2;   // solution rows: (64 / 16) row tiles x 2 column tiles / 4 wavefronts
 
 constexpr int kSolveThreads = 256;
 constexpr int kMaxRhsTile = 8;          // columns per register tile of the triangular solve
 constexpr int kSpinLimit = 1 << 25;     // bounded waits; on overflow the error flag is set
 // debug trace per task: claim, solve start, end, workgroup, low-rank done,
 // triangle done, product done, flags stored, batched low-rank started,
-// batched low-rank done, (unused) x2
+// batched low-rank done, neighbour record published (fused form), (unused)
 constexpr int kTraceFields = 12;
 
 struct SolveArgs {
@@ -390,9 +391,10 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, const
   const bool next_lds = lf.next_rec >= 0 && a.dense[lf.next_rec].m <= 128 && a.dense[lf.next_rec].ncols <= kKC;
   if (lf.next_rec >= 0) Dn = a.dense[lf.next_rec];
   const bool fused = lf.nm >= 0;   // record formed from r with (D Inv), see below
+  const int rec_rows = lf.nm_rows;   // rows of the neighbour record(s) in the fused form
   if (fused) {
-    for (int e = threadIdx.x; e < Dn.m * m; e += blockDim.x) {
-      const int i = e % Dn.m, k = e / Dn.m;
+    for (int e = threadIdx.x; e < rec_rows * m; e += blockDim.x) {
+      const int i = e % rec_rows, k = e / rec_rows;
       As[k * 128 + i] = double(nm[lf.nm + e]);
     }
   } else if (next_lds) {
@@ -445,58 +447,103 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, const
   stamp(a, 1);
   __syncthreads();
   if (fused) {
-    // y_j = Inv r_j and the neighbour record P = (D Inv) r_j as one product
-    // [Inv; D Inv] r_j on the FP64 matrix cores (16 x 16 x 4 tiles): the
-    // stacked rows (m + rows of the record <= 192) in 16-row tiles, the
-    // columns in 16-column tiles, tiles dealt round robin to the wavefronts.
+    // the neighbour record P = (D Inv) r_j (with the second neighbour's
+    // record stacked below it) first, then y_j = Inv r_j, both on
+    // the FP64 matrix cores (16 x 16 x 4 tiles; columns in 16-column tiles,
+    // tiles dealt round robin to the wavefronts).  P is stored and its flag
+    // set before y_j is formed: the next leaf task waits for P only, so the
+    // solution rows, their stores and the T-product chunks of this task
+    // overlap with the next task.
     // Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k;
     // result register r of lane l is D[l/16 + 4r][l%16].
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rows = m + Dn.m;
-    const int rt_n = (rows + 15) >> 4, ct_n = (nrhs + 15) >> 4, ks_n = (m + 3) >> 2;
-    const int ntiles = rt_n * ct_n;
+    const int ct_n = (nrhs + 15) >> 4, ks_n = (m + 3) >> 2;
     // tile t = wave + 4 it: with ct_n in {1, 2} all of a wavefront's tiles
     // share one column tile, so one B operand feeds all its MFMAs per step
     const int ct = wave % ct_n;
     const int j = 16 * ct + (lane & 15), kl = lane >> 4;
-    double4_t dacc[kMaxTilesPerWave];
+    const int col = 16 * ct + (lane & 15);
+    {
+      const int ntiles = ((rec_rows + 15) >> 4) * ct_n;
+      double4_t dacc[kRecTilesPerWave];
 #pragma unroll
-    for (int it = 0; it < kMaxTilesPerWave; ++it) dacc[it] = double4_t{0.0, 0.0, 0.0, 0.0};
+      for (int it = 0; it < kRecTilesPerWave; ++it) dacc[it] = double4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
-    for (int ks = 0; ks < ks_n; ++ks) {
-      const int k = 4 * ks + kl;
-      const double bv = (k < m && j < nrhs) ? acc[k * ldacc + j] : 0.0;
+      for (int ks = 0; ks < ks_n; ++ks) {
+        const int k = 4 * ks + kl;
+        const double bv = (k < m && j < nrhs) ? acc[k * ldacc + j] : 0.0;
 #pragma unroll
-      for (int it = 0; it < kMaxTilesPerWave; ++it) {
-        const int t = wave + 4 * it;   // uniform within the wavefront
-        if (t < ntiles) {
-          const int i = 16 * (t / ct_n) + (lane & 15);
-          double av = 0.0;
-          if (k < m) {
-            if (i < m) av = forward ? (i > k ? Dg[i + k * m] : (i == k ? 1.0 : 0.0)) : (i <= k ? Dg[i + k * m] : 0.0);
-            else if (i < rows) av = As[k * 128 + (i - m)];
+        for (int it = 0; it < kRecTilesPerWave; ++it) {
+          const int t = wave + 4 * it;   // uniform within the wavefront
+          if (t < ntiles) {
+            const int i = 16 * (t / ct_n) + (lane & 15);
+            const double av = (k < m && i < rec_rows) ? As[k * 128 + i] : 0.0;
+            dacc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, dacc[it], 0, 0, 0);
           }
-          dacc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, dacc[it], 0, 0, 0);
         }
       }
+      // rows [0, Dn.m): the next leaf's record; the rest: the second
+      // neighbour's record
+      double* P = a.pbuf + (int64_t)lf.next_rec * a.pstride;
+      double* P2 = lf.next_rec2 >= 0 ? a.pbuf + (int64_t)lf.next_rec2 * a.pstride : nullptr;
+      const int dm2 = rec_rows - Dn.m;
+#pragma unroll
+      for (int it = 0; it < kRecTilesPerWave; ++it) {
+        const int t = wave + 4 * it;
+        if (t < ntiles) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int row = 16 * (t / ct_n) + (lane >> 4) + 4 * rr;
+            if (col < nrhs && row < Dn.m) cstore(P + row + col * Dn.m, dacc[it][rr]);
+            else if (col < nrhs && row < rec_rows) cstore(P2 + (row - Dn.m) + col * dm2, dacc[it][rr]);
+          }
+        }
+      }
+      // every wave's record stores complete, then the records' flags
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __hip_atomic_store(a.pflag + lf.next_rec, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lf.next_rec2 >= 0)
+          __hip_atomic_store(a.pflag + lf.next_rec2, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
-    __syncthreads();
-    double* P = a.pbuf + (int64_t)lf.next_rec * a.pstride;
+    stamp(a, 10);
+    {
+      const int ntiles = ((m + 15) >> 4) * ct_n;
+      double4_t dacc[kSolTilesPerWave];
 #pragma unroll
-    for (int it = 0; it < kMaxTilesPerWave; ++it) {
-      const int t = wave + 4 * it;
-      if (t < ntiles) {
-        const int rt = t / ct_n;
-        const int col = 16 * ct + (lane & 15);
+      for (int it = 0; it < kSolTilesPerWave; ++it) dacc[it] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+      for (int ks = 0; ks < ks_n; ++ks) {
+        const int k = 4 * ks + kl;
+        const double bv = (k < m && j < nrhs) ? acc[k * ldacc + j] : 0.0;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int row = 16 * rt + (lane >> 4) + 4 * rr;
-          const double v = dacc[it][rr];
-          if (col < nrhs && row < m) {
-            acc[row * ldacc + col] = v;
-            cstore(a.y + lf.row0 + row + (int64_t)col * a.N, v);
-          } else if (col < nrhs && row < rows) {
-            cstore(P + (row - m) + col * Dn.m, v);
+        for (int it = 0; it < kSolTilesPerWave; ++it) {
+          const int t = wave + 4 * it;
+          if (t < ntiles) {
+            const int i = 16 * (t / ct_n) + (lane & 15);
+            double av = 0.0;
+            if (k < m && i < m)
+              av = forward ? (i > k ? Dg[i + k * m] : (i == k ? 1.0 : 0.0)) : (i <= k ? Dg[i + k * m] : 0.0);
+            dacc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, dacc[it], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();   // every wave has read r_j from acc
+#pragma unroll
+      for (int it = 0; it < kSolTilesPerWave; ++it) {
+        const int t = wave + 4 * it;
+        if (t < ntiles) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int row = 16 * (t / ct_n) + (lane >> 4) + 4 * rr;
+            const double v = dacc[it][rr];
+            if (col < nrhs && row < m) {
+              acc[row * ldacc + col] = v;
+              cstore(a.y + lf.row0 + row + (int64_t)col * a.N, v);
+            }
           }
         }
       }
@@ -573,7 +620,7 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, const
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_s_waitcnt(0);
-    if (lf.next_rec >= 0)
+    if (lf.next_rec >= 0 && !fused)
       __hip_atomic_store(a.pflag + lf.next_rec, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int q = 0; q < lf.ntq; ++q)
       __hip_atomic_store(a.tp_flag + a.leaf_tq[lf.tq0 + q], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -752,10 +799,11 @@ __global__ void __launch_bounds__(256) diag_inverse_kernel(const T* arena, const
   }
 }
 
-// For every leaf task with a neighbour record (lf.nm >= 0): the record's
-// block D (rows of the next leaf x this leaf) times this leaf's triangle
-// inverse (forward: unit lower L^{-1}; backward: U^{-1}), in FP64, stored in
-// the factor's type.  One workgroup per leaf task; D and the inverse in LDS.
+// For every leaf task with a neighbour record (lf.nm >= 0): the records'
+// blocks D (rows of the next leaf, then of the second neighbour's record if
+// any, x this leaf) times this leaf's triangle inverse (forward: unit lower
+// L^{-1}; backward: U^{-1}), in FP64, stored in the factor's type.  One
+// workgroup per leaf task; D and the inverse in LDS.
 template <class T>
 __global__ void __launch_bounds__(256) next_inverse_kernel(const T* arena, const SLeaf* leaves,
                                                            const SDense* dense, const T* inv, T* nm, int L) {
@@ -765,12 +813,17 @@ __global__ void __launch_bounds__(256) next_inverse_kernel(const T* arena, const
   if (lf.nm < 0) return;
   const bool forward = s < L;
   const SDense d = dense[lf.next_rec];
-  const int m = lf.m, dm = d.m;
+  const int m = lf.m, dm = lf.nm_rows, dm1 = d.m;
   double* Ds = sm;              // dm x m, leading dimension dm (<= 128 x 64)
   double* Is = sm + 128 * 64;   // m x m (<= 64 x 64)
   for (int e = threadIdx.x; e < dm * m; e += blockDim.x) {
     const int i = e % dm, k = e / dm;
-    Ds[e] = double(arena[d.off + i + (int64_t)k * d.ld]);
+    if (i < dm1) {
+      Ds[e] = double(arena[d.off + i + (int64_t)k * d.ld]);
+    } else {
+      const SDense& d2 = dense[lf.next_rec2];
+      Ds[e] = double(arena[d2.off + (i - dm1) + (int64_t)k * d2.ld]);
+    }
   }
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int q = e % m, k = e / m;

@@ -161,16 +161,39 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
   // the sweep (forward: ascending rows, backward: descending), and the
   // records are split into tasks of kPushChunk so that several workgroups
   // form them together.
-  // neighbour block times the inverse, for leaves up to 64 rows whose
-  // neighbour record has at most 128 rows
+  // neighbour blocks times the inverse, for leaves up to 64 rows: the
+  // neighbour record and, when the rows fit 128 in all, the second
+  // neighbour's record of a block whose columns are this leaf alone (taken
+  // from the push tasks: on the sweep's critical path, a push after this
+  // task's end would delay the leaf after next)
   for (int32_t s = 0; s < 2 * L; ++s) {
     SLeaf& lf = sc.leaves[s];
     lf.nm = -1;
+    lf.next_rec2 = -1;
+    lf.nm_rows = 0;
     if (lf.next_rec < 0) continue;
     const SDense& d = sc.dense[lf.next_rec];
     if (lf.m > 64 || d.m > 128 || d.ncols != lf.m) continue;
+    int32_t rows = d.m;
+    const bool fwd = s < L;
+    const int32_t j = s % L;
+    const int32_t c2 = fwd ? j + 2 : j - 2;   // leaf after next in sweep order
+    if (c2 >= 0 && c2 < L) {
+      const int32_t row2 = S.clusters[S.leaf_clusters[c2]].begin;
+      std::vector<int32_t>& pr = push[s];
+      for (size_t q = 0; q < pr.size(); ++q) {
+        const SDense& d2 = sc.dense[pr[q]];
+        if (d2.row0 == row2 && d2.lf1 - d2.lf0 == 1 && d2.ncols == lf.m && rows + d2.m <= 128) {
+          lf.next_rec2 = pr[q];
+          rows += d2.m;
+          pr.erase(pr.begin() + q);
+          break;
+        }
+      }
+    }
     lf.nm = sc.nm_elems;
-    sc.nm_elems += (int64_t)d.m * lf.m;
+    lf.nm_rows = rows;
+    sc.nm_elems += (int64_t)rows * lf.m;
   }
   auto emit = [&](int32_t s, int32_t push_kind, int32_t tp_kind) {
     const bool fwd = s < L;

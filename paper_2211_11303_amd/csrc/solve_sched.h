@@ -6,8 +6,9 @@
 // Low-rank blocks contribute X_b (Y_b^T y[sigma]), the small product being
 // formed once per block by a T-product task.  Every dense block L_b y[sigma]
 // is formed into its own partial-sum record: by the task of leaf j-1 for the
-// block coupling j to j-1 (on the critical path), otherwise by the push task
-// of the leaf that completes sigma.  The task of leaf j then adds its
+// block coupling j to j-1 (on the critical path) and, with it, for the block
+// coupling j+1 to j-1, otherwise by the push task of the leaf that completes
+// sigma.  The task of leaf j then adds its
 // records in a fixed order.  The backward sweep mirrors this with U.  This
 // is the left-looking form of the recursive H-forward/backward
 // substitution: the same arithmetic, summed per row.
@@ -33,9 +34,14 @@ struct SLeaf {
   int32_t tq0, ntq;    // T-product chunks this leaf task computes after solving
                        // (leaf_tq[tq0 .. tq0 + ntq)): chunks of exactly this leaf's
                        // rows whose block is needed within kNearLeaves leaves
-  int64_t nm;          // next_rec's block times this leaf's triangle inverse in the
-                       // NM buffer (rows of the record x m, leading dimension = rows;
-                       // -1: formed from the solution instead)
+  int64_t nm;          // the neighbour records' blocks times this leaf's triangle
+                       // inverse in the NM buffer (rows of next_rec, then of
+                       // next_rec2, x m, leading dimension = those rows; -1: the
+                       // record is formed from the solution instead)
+  int32_t next_rec2;   // with nm: the record of the leaf after next (second
+                       // neighbour) coupled to this leaf alone, formed in the same
+                       // product (-1: none; otherwise a push task forms it)
+  int32_t nm_rows;     // rows of the NM block (0 without nm)
 };
 struct SDense {        // block rows of leaf j: off + i + k*ld, k < ncols
   int64_t off;
