@@ -111,6 +111,8 @@ SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs
   v.push0 = d.push0;
   v.push_recs = d.push_recs;
   v.leaf_tq = d.leaf_tq;
+  v.tg0 = d.tg0;
+  v.tg_list = d.tg_list;
   v.inv = b.inv;
   v.nm = b.nm;
   v.pivots = b.pivots;

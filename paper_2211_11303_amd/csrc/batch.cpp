@@ -170,7 +170,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
                   const std::vector<int32_t>& d, const std::vector<int32_t>& o, SolveSched* out) {
   SolveSched& M = *out;
   const size_t np = S.size();
-  std::vector<int32_t> LB(np), DB(np), LWB(np), TPB(np), PB(np), PRB(np), TQB(np);
+  std::vector<int32_t> LB(np), DB(np), LWB(np), TPB(np), PB(np), PRB(np), TQB(np), TGB(np), TGLB(np);
   std::vector<int64_t> TOFF(np), INVB(np), NMB(np);
   int32_t Ltot = 0;
   for (size_t p = 0; p < np; ++p) {
@@ -181,6 +181,8 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
     TPB[p] = (int32_t)M.tprod.size();
     PB[p] = p ? PB[p - 1] + (int32_t)S[p - 1]->push0.size() - 1 : 0;
     PRB[p] = (int32_t)M.push_recs.size();
+    TGB[p] = p ? TGB[p - 1] + (int32_t)S[p - 1]->tg0.size() - 1 : 0;
+    TGLB[p] = (int32_t)M.tg_list.size();
     TOFF[p] = M.tbuf_per_rhs;
     INVB[p] = M.inv_elems;
     NMB[p] = M.nm_elems;
@@ -209,6 +211,8 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
     }
     for (size_t i = 0; i + 1 < s.push0.size(); ++i) M.push0.push_back(s.push0[i] + PRB[p]);
     for (int32_t r : s.push_recs) M.push_recs.push_back(r + DB[p]);
+    for (size_t i = 0; i + 1 < s.tg0.size(); ++i) M.tg0.push_back(s.tg0[i] + TGLB[p]);
+    for (int32_t q : s.tg_list) M.tg_list.push_back(q + TPB[p]);
     TQB[p] = (int32_t)M.leaf_tq.size();
     for (int32_t q : s.leaf_tq) M.leaf_tq.push_back(q + TPB[p]);
     M.tbuf_per_rhs += s.tbuf_per_rhs;
@@ -217,6 +221,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
     M.max_m = std::max(M.max_m, s.max_m);
   }
   M.push0.push_back((int32_t)M.push_recs.size());
+  M.tg0.push_back((int32_t)M.tg_list.size());
   M.L = Ltot;
   M.leaves.resize(2 * (size_t)Ltot);
   for (size_t p = 0; p < np; ++p) {
@@ -243,7 +248,7 @@ void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int
       case kFwdLeaf: t.idx += LB[p]; break;
       case kBwdLeaf: t.idx = Ltot + LB[p] + (t.idx - s.L); break;
       case kFwdTprod:
-      case kBwdTprod: t.idx += TPB[p]; break;
+      case kBwdTprod: t.idx += TGB[p]; break;
       default: t.idx += PB[p]; break;   // push tasks
     }
     return t;

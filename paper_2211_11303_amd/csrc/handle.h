@@ -98,6 +98,8 @@ struct DevSched {
   const int32_t* push0 = nullptr;
   const int32_t* push_recs = nullptr;
   const int32_t* leaf_tq = nullptr;
+  const int32_t* tg0 = nullptr;
+  const int32_t* tg_list = nullptr;
   void load(const SolveSched& sc) {
     tasks = mem.keep(upload(sc.tasks));
     leaves = mem.keep(upload(sc.leaves));
@@ -107,6 +109,8 @@ struct DevSched {
     push0 = mem.keep(upload(sc.push0));
     push_recs = mem.keep(upload(sc.push_recs));
     leaf_tq = mem.keep(upload(sc.leaf_tq));
+    tg0 = mem.keep(upload(sc.tg0));
+    tg_list = mem.keep(upload(sc.tg_list));
   }
 };
 

@@ -45,6 +45,8 @@ struct SolveArgs {
   const int32_t* push0; // push task -> first record in push_recs
   const int32_t* push_recs;
   const int32_t* leaf_tq; // T-product chunks computed by leaf tasks
+  const int32_t* tg0;     // T-product task -> first T-product in tg_list
+  const int32_t* tg_list;
   double* pbuf;         // partial-sum records, pstride doubles each (m x nrhs, ld m)
   int32_t* pflag;       // one per record
   int64_t pstride;
@@ -730,9 +732,13 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
     }
     switch (task.kind) {
       case kFwdLeaf: run_leaf<T>(a, arena, inv, nm, task.idx, true, acc, As, Bs, Dg); break;
-      case kFwdTprod: run_tprod<T>(a, arena, task.idx, true, As, Bs); break;
+      case kFwdTprod:
+        for (int q = a.tg0[task.idx]; q < a.tg0[task.idx + 1]; ++q) run_tprod<T>(a, arena, a.tg_list[q], true, As, Bs);
+        break;
       case kBwdLeaf: run_leaf<T>(a, arena, inv, nm, task.idx, false, acc, As, Bs, Dg); break;
-      case kBwdTprod: run_tprod<T>(a, arena, task.idx, false, As, Bs); break;
+      case kBwdTprod:
+        for (int q = a.tg0[task.idx]; q < a.tg0[task.idx + 1]; ++q) run_tprod<T>(a, arena, a.tg_list[q], false, As, Bs);
+        break;
       case kFwdPush: run_push<T>(a, arena, task.idx, true, As, Bs); break;
       case kBwdPush: run_push<T>(a, arena, task.idx, false, As, Bs); break;
     }
@@ -850,7 +856,7 @@ hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const So
                                    int32_t nrhs, int32_t epoch, int32_t grid, hipStream_t s) {
   dev::solve_reset_kernel<<<1, 64, 0, s>>>(d.ctr);
   dev::SolveArgs a{d.tasks, d.leaves, d.dense, d.low, d.tprod, dims, d.y, d.tbuf, d.leaf_flag, d.tp_flag,
-                   d.ctr, d.push0, d.push_recs, d.leaf_tq, d.pbuf, d.pflag, d.pstride, d.trace,
+                   d.ctr, d.push0, d.push_recs, d.leaf_tq, d.tg0, d.tg_list, d.pbuf, d.pflag, d.pstride, d.trace,
                    d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch, 0};
   // acc 128 x 32, A staging 128 x kKC, B staging 32 x kKC, inverses 64 x 64
   const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC + 64 * 64) * sizeof(double);

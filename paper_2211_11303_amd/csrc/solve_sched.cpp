@@ -210,7 +210,26 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
       sc.push_recs.insert(sc.push_recs.end(), pr.begin() + c, pr.begin() + e);
       sc.tasks.push_back({push_kind, id});
     }
-    for (int32_t tp : tl) sc.tasks.push_back({tp_kind, tp});
+    // the T-products of blocks with the same column rows (several row
+    // clusters against one sigma) share a task, at most kTprodGroup of
+    // them, in the order of their first consumers: fewer workgroups wait
+    // on the same leaf, and each product still sets its own flag
+    std::vector<char> used(tl.size(), 0);
+    for (size_t i = 0; i < tl.size(); ++i) {
+      if (used[i]) continue;
+      const int32_t id = (int32_t)sc.tg0.size();
+      sc.tg0.push_back((int32_t)sc.tg_list.size());
+      const STprod& t0 = sc.tprod[tl[i]];
+      int32_t cnt = 0;
+      for (size_t q = i; q < tl.size() && cnt < kTprodGroup; ++q) {
+        const STprod& t = sc.tprod[tl[q]];
+        if (used[q] || t.col0 != t0.col0 || t.ncols != t0.ncols) continue;
+        sc.tg_list.push_back(tl[q]);
+        used[q] = 1;
+        ++cnt;
+      }
+      sc.tasks.push_back({tp_kind, id});
+    }
   };
   for (int32_t f = 0; f < L; ++f) {
     sc.tasks.push_back({kFwdLeaf, f});
@@ -222,6 +241,13 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
     emit(L + f, kBwdPush, kBwdTprod);
   }
   sc.push0.push_back((int32_t)sc.push_recs.size());
+  sc.tg0.push_back((int32_t)sc.tg_list.size());
+  // every T-product is formed exactly once: by a T-product task or by the
+  // leaf task that completes its rows
+  std::vector<int32_t> seen(sc.tprod.size(), 0);
+  for (int32_t q : sc.tg_list) ++seen[q];
+  for (int32_t q : sc.leaf_tq) ++seen[q];
+  for (int32_t c : seen) HLU_REQUIRE(c == 1, HLU_ERR_INVALID_ARG, "solve schedule: T-product not formed once");
 }
 
 }  // namespace hlu

@@ -67,6 +67,7 @@ struct STprod {
 constexpr int32_t kTprodChunkRows = 1 << 30; // rows of sigma per T-product chunk (no row split)
 constexpr int32_t kNearLeaves = 4;          // consumers this close get the chunk from the leaf task
 constexpr int32_t kPushChunk = 2;   // partial-sum records per push task
+constexpr int32_t kTprodGroup = 8;  // T-products of blocks sharing sigma's rows per task
 enum STaskKind : int32_t { kFwdLeaf = 0, kFwdTprod = 1, kBwdLeaf = 2, kBwdTprod = 3, kFwdPush = 4, kBwdPush = 5 };
 struct STask {
   int32_t kind, idx;
@@ -82,6 +83,8 @@ struct SolveSched {
   std::vector<int32_t> push0;     // per push task: first record in push_recs (size #push + 1)
   std::vector<int32_t> push_recs; // dense records computed by push tasks
   std::vector<int32_t> leaf_tq;   // T-product chunks computed by leaf tasks
+  std::vector<int32_t> tg0;       // per T-product task: first entry in tg_list (size #tasks + 1)
+  std::vector<int32_t> tg_list;   // T-products of each T-product task, in order
   int32_t n_fwd_tasks = 0;
   int64_t tbuf_per_rhs = 0;       // doubles of the T buffer per right-hand side
   int64_t inv_elems = 0;          // elements of the inverse buffer (sum of m^2 over leaves)
@@ -112,6 +115,8 @@ struct SolveDev {
   const int32_t* push0;
   const int32_t* push_recs;
   const int32_t* leaf_tq;
+  const int32_t* tg0;
+  const int32_t* tg_list;
   double* pbuf;
   int32_t* pflag;
   int64_t pstride;
