@@ -72,6 +72,25 @@ def parse():
     return p.parse_args()
 
 
+# HBM traffic of one persistent solve launch (24 columns, 32^3, FP32 factors)
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, each scaled by the reading
+# of a plain copy kernel of known size; valid only for the sources it was
+# measured on (profiles/solve_persistent_32cube_fp32_hbm_traffic.md).
+SOLVE_TRAFFIC = {"sha256": "2fcd428a4e3f68dd1558e5a978aea20f235a3e048a81dc0ed083c0d7179d8426", "columns": 24,
+                 "bytes_per_launch": 7354988139}
+SOLVE_SOURCES = ("paper_2211_11303_amd/csrc/kernels_solve.hip", "paper_2211_11303_amd/csrc/solve_sched.cpp",
+                 "paper_2211_11303_amd/csrc/solve_sched.h")
+
+
+def solve_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOLVE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -475,6 +494,10 @@ def main():
     alg_bytes = alg_bytes_total / max(1, launches)
     launch_s = r32["solve_kernel_s"] / max(1, launches)
     achieved = alg_bytes / launch_s / 1e9
+    cols = r32["solve_columns"] / max(1, launches)
+    traffic = (SOLVE_TRAFFIC["bytes_per_launch"]
+               if (SOLVE_TRAFFIC["sha256"] == solve_sources_sha256() and cols == SOLVE_TRAFFIC["columns"]
+                   and args.n == 32 and args.leaf == 64) else None)
     line = {
         "metric": "H-LU factor s + precond. GMRES solves/sec to 1e-8; FP32-HLU vs FP64-HLU",
         "value": r32["solves_per_s"],
@@ -507,7 +530,7 @@ def main():
                                                "per launch, fp32 factors, fp64 vectors; launches of the "
                                                "timed region",
                      "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes, "launch_s": launch_s,
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes, "launch_s": launch_s,
                      "launches": launches, "columns_per_launch": r32["solve_columns"] / max(1, launches)},
     }
     if "fp64" in result:
