@@ -56,6 +56,8 @@ def parse():
                    help="batched workload instead: 64 problems (8^3..24^3, kappa in [1, 10]) factored and "
                         "solved as one batch, against the same problems run one by one")
     p.add_argument("--batch-count", type=int, default=64)
+    p.add_argument("--batch-leaves", type=str, default="32,48,64",
+                   help="leaf sizes the autotuner measures per mesh size (one value: fixed leaf)")
     p.add_argument("--serve", action="store_true",
                    help="serving workload instead: Poisson arrivals of solve requests answered by hlu_server")
     p.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
@@ -163,13 +165,27 @@ def batch_main(args):
     torch.cuda.set_device(0)
     eps, mr, prec = 1e-3, args.batch_max_rank, "fp32"
     probs = inputs.batch_problems(args.batch_count, seed=7)
+    # leaf size per mesh size, measured (factor + one GMRES solve at the
+    # middle of the kappa range) before either timed region
+    cands = tuple(int(v) for v in args.batch_leaves.split(","))
+    leaf_by_n, tune_times = {}, {}
+    t = time.perf_counter()
+    for n in sorted({n for n, _ in probs}):
+        if len(cands) == 1:
+            leaf_by_n[n] = cands[0]
+            continue
+        best, secs = hlu.hlu_autotune_leaf(n, 5.5, leaves=cands, eps=eps, max_rank=mr, prec=prec,
+                                           restart=args.restart, tol=args.tol)
+        leaf_by_n[n], tune_times[n] = best, secs
+        log(f"autotune {n}^3: leaf {best} (" + ", ".join(f"{l}: {s:.3f}s" for l, s in zip(cands, secs)) + ")")
+    autotune_s = time.perf_counter() - t
     t = time.perf_counter()
     data = [(n, kappa) + tuple(hlu.hlu_kuhn_assemble(n, kappa)) for n, kappa in probs]
     protos = {}
     for n, kappa, rp, ci, va, mid in data:
         if n not in protos:
             log(f"planning {n}^3")
-            protos[n] = hlu.HLU(rp, ci, va, mid, 2.0, args.leaf)
+            protos[n] = hlu.HLU(rp, ci, va, mid, 2.0, leaf_by_n[n])
             protos[n].hlu_workspace_bytes(eps, mr, prec)
     mats = [hlu.SpMat(rp, ci, va) for _, _, rp, ci, va, _ in data]
     xs = [torch.tensor(inputs.exact_solution_cols(A.n, 1, seed=p), device="cuda") for p, A in enumerate(mats)]
@@ -227,9 +243,12 @@ def batch_main(args):
         "dtype": "f32-hlu+f64-gmres",
         "data": "synthetic",
         "config": {"workload": f"{args.batch_count} Kuhn-cube problems, n in {{8,12,16,20,24}} and kappa in "
-                               f"[1,10] from default_rng(7); eta=2, leaf={args.leaf}, eps={eps:g}, "
-                               f"rank capacity {mr}; GMRES({args.restart}) to {args.tol:g}, 1 rhs each",
-                   "count": args.batch_count, "N_total": B.n_total, "leaf": args.leaf},
+                               f"[1,10] from default_rng(7); eta=2, leaf autotuned per mesh size from "
+                               f"{{{args.batch_leaves}}}, eps={eps:g}, rank capacity {mr}; GMRES({args.restart}) "
+                               f"to {args.tol:g}, 1 rhs each",
+                   "count": args.batch_count, "N_total": B.n_total, "leaf_by_n": leaf_by_n},
+        "autotune_s": autotune_s,
+        "autotune_device_s": {n: dict(zip(cands, v)) for n, v in tune_times.items()},
         "one_by_one_problems_per_s": args.batch_count / T_seq,
         "speedup_vs_one_by_one": T_seq / T_bat,
         "batched_s": T_bat,

@@ -341,6 +341,21 @@ hlu_status hlu_server_get_stats(hlu_server s, hlu_server_stats* out);
 /* Answers every queued request, stops the workers, frees the cache. */
 void hlu_server_destroy(hlu_server s);
 
+/* ------------------------------------------------------------ autotuning
+ * Leaf size of the cluster trees for the Kuhn-cube mesh n at wavenumber
+ * kappa, chosen by measurement (for batches of problems of several sizes).
+ * For each of the `count` (1..16) candidates in leaves[] (each 1..128):
+ * builds and plans the structure (host, not timed), factors A = K -
+ * kappa^2 M with fo twice (the first uploads the plans) and solves nrhs
+ * (1..32) right-hand sides b = A 1 with GMRES (go); seconds[c] (host out)
+ * is the device time of the second factorisation plus the solve, measured
+ * with HIP events on `stream`, or HUGE_VAL if a column did not converge.
+ * *best (host out) = the candidate with the smallest time (the first on
+ * ties).  Allocates and frees its own device memory; synchronous. */
+hlu_status hlu_autotune_leaf(int32_t n, double kappa, double eta, const int32_t* leaves, int32_t count,
+                             const hlu_factor_opts* fo, const hlu_gmres_opts* go, int32_t nrhs,
+                             double* seconds, int32_t* best, void* stream);
+
 /* ------------------------------------------------------------ inspection */
 /* Sizes of the structure arrays, then a copy of them into caller-allocated
  * host arrays (any pointer may be NULL to skip it):

@@ -117,6 +117,8 @@ SIGNATURES = {
     "hlu_server_wait": (c_int32, [c_void_p, c_int64, c_double, ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     "hlu_server_get_stats": (c_int32, [c_void_p, ctypes.POINTER(ServerStats)]),
     "hlu_server_destroy": (None, [c_void_p]),
+    "hlu_autotune_leaf": (c_int32, [c_int32, c_double, c_double, P_i32, c_int32, ctypes.POINTER(FactorOpts),
+                                    ctypes.POINTER(GmresOpts), c_int32, ctypes.POINTER(c_double), P_i32, c_void_p]),
 }
 
 _lib = None

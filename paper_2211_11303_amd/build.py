@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libhlu.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["mesh.cpp", "structure.cpp", "plan.cpp", "solve_sched.cpp", "api.cpp", "gmres.cpp", "batch.cpp",
-           "server.cpp",
+           "server.cpp", "autotune.cpp",
            "kernels_hlu.hip",
            "kernels_vec.hip", "kernels_solve.hip"]
 

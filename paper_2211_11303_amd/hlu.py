@@ -65,6 +65,22 @@ def hlu_kuhn_assemble(n, kappa):
     return rp, ci, va, mid
 
 
+def hlu_autotune_leaf(n, kappa, leaves=(32, 48, 64), eta=2.0, eps=1e-3, max_rank=0, prec="fp32", restart=50,
+                      max_iters=1000, tol=1e-8, nrhs=1, stream=None):
+    """hlu_autotune_leaf: (best leaf, [device seconds of factor + GMRES per
+    candidate]) for the Kuhn-cube mesh n at wavenumber kappa."""
+    cand = np.ascontiguousarray(leaves, np.int32)
+    secs = np.empty(len(cand), np.float64)
+    best = np.empty(1, np.int32)
+    fo = L.FactorOpts(float(eps), int(max_rank), PREC[prec])
+    go = L.GmresOpts(int(restart), int(max_iters), float(tol))
+    L.check(L.lib().hlu_autotune_leaf(int(n), float(kappa), float(eta), _ptr(cand, ctypes.c_int32), len(cand),
+                                      ctypes.byref(fo), ctypes.byref(go), int(nrhs),
+                                      secs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _ptr(best, ctypes.c_int32), _stream(stream)))
+    return int(best[0]), secs.tolist()
+
+
 # ------------------------------------------------------------ sparse matrix
 class SpMat:
     """Device CSR of A (hlu_spmat)."""

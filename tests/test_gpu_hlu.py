@@ -173,3 +173,13 @@ def test_solve_timing_counts_launches(gpu):
     H.hlu_solve(torch.tensor(inputs.exact_solution_cols(A.n, 2, seed=1), device="cuda"))
     st = H.hlu_get_stats()
     assert st["solve_launches"] == 0 and st["solve_columns"] == 0
+
+
+def test_autotune_leaf(gpu):
+    """The autotuner times every candidate (factor + GMRES on the device) and
+    returns the fastest one."""
+    hlu, _ = _lib()
+    leaves = (8, 16, 32)
+    best, secs = hlu.hlu_autotune_leaf(4, 2.0, leaves=leaves, eps=1e-6, prec="fp64", restart=30, tol=1e-10)
+    assert all(np.isfinite(s) and s > 0 for s in secs), secs
+    assert best == leaves[int(np.argmin(secs))]

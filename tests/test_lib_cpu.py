@@ -145,3 +145,17 @@ def test_server_rejects_bad_refinement_options():
         with pytest.raises(L.HluError) as e:
             hlu.Server(**kw)
         assert e.value.status == L.STATUS_CODES["HLU_ERR_INVALID_ARG"], kw
+
+
+def test_autotune_rejects_bad_arguments():
+    """hlu_autotune_leaf checks its arguments before any device work."""
+    from paper_2211_11303_amd import _lib as L
+    fo = L.FactorOpts(1e-3, 0, L.HLU_FP32)
+    go = L.GmresOpts(50, 100, 1e-8)
+    secs = (ctypes.c_double * 4)()
+    best = ctypes.c_int32()
+    for cand, count, nrhs in (([0], 1, 1), ([129], 1, 1), ([32], 0, 1), ([32], 1, 0), ([32], 1, 33)):
+        arr = (ctypes.c_int32 * max(1, len(cand)))(*cand)
+        st = L.lib().hlu_autotune_leaf(4, 2.0, 2.0, arr, count, ctypes.byref(fo), ctypes.byref(go), nrhs, secs,
+                                       ctypes.byref(best), None)
+        assert st == L.STATUS_CODES["HLU_ERR_INVALID_ARG"], (cand, count, nrhs, st)
