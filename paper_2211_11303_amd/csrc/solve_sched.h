@@ -65,7 +65,7 @@ struct STprod {
   int32_t ldy, col0, ncols, slot, lf0, lf1, cap, pad;
 };
 constexpr int32_t kTprodChunkRows = 1 << 30; // rows of sigma per T-product chunk (no row split)
-constexpr int32_t kNearLeaves = 4;          // consumers this close get the chunk from the leaf task
+constexpr int32_t kNearLeaves = 2;          // consumers this close get the chunk from the leaf task
 constexpr int32_t kPushChunk = 2;   // partial-sum records per push task
 constexpr int32_t kTprodGroup = 8;  // T-products of blocks sharing sigma's rows per task
 enum STaskKind : int32_t { kFwdLeaf = 0, kFwdTprod = 1, kBwdLeaf = 2, kBwdTprod = 3, kFwdPush = 4, kBwdPush = 5 };
