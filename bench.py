@@ -55,6 +55,12 @@ def parse():
     p.add_argument("--batch", action="store_true",
                    help="batched workload instead: 64 problems (8^3..24^3, kappa in [1, 10]) factored and "
                         "solved as one batch, against the same problems run one by one")
+    p.add_argument("--table1", action="store_true",
+                   help="Example 1 protocol of the paper instead (Table 1): GMRES iteration counts per refinement "
+                        "level and kappa, beside the paper's")
+    p.add_argument("--table1-levels", type=str, default="2,3,4,5",
+                   help="refinement levels k (n = 2^(k-1) cubes per side)")
+    p.add_argument("--table1-max-iters", type=int, default=500)
     p.add_argument("--batch-count", type=int, default=64)
     p.add_argument("--batch-leaves", type=str, default="32,48,64",
                    help="leaf sizes the autotuner measures per mesh size (one value: fixed leaf)")
@@ -376,6 +382,59 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+# Table 1 of the paper: GMRES iterations for Example 1 per refinement level k
+# (rows) and kappa in {25, 100, 225, 400, 625, 900} (columns); None: ">3000"
+PAPER_TABLE1 = {2: [1, 1, 1, 1, 1, 1], 3: [2, 2, 2, 2, 2, 2], 4: [2, 4, 5, 5, 4, 3], 5: [3, 4, 8, 9, 11, None],
+                6: [3, 6, 20, 4, 48, 25], 7: [4, 5, 7, 19, 46, 93]}
+PAPER_KAPPAS = [25.0, 100.0, 225.0, 400.0, 625.0, 900.0]
+
+
+def table1_main(args):
+    """Example 1 of the paper (Sec. 4, Table 1) with its protocol: the unit
+    cube refined k times (here the Kuhn cube with n = 2^(k-1) cubes per side),
+    J_S = (0, 0, 1), b_j = <J_S, Phi_j>, the paper's kappa multiplying the
+    mass term (A = K - kappa M, so our wavenumber is sqrt(kappa)), GMRES
+    restarted after 100 iterations, stopped at relative residual 1e-5.  The
+    preconditioner is our FP64 H-LU at --eps and --leaf; the paper's rank r is
+    not stated, so the counts are compared in trend, not value."""
+    import math
+    import torch
+    from paper_2211_11303_amd import hlu
+
+    torch.cuda.set_device(0)
+    levels = [int(v) for v in args.table1_levels.split(",")]
+    rows = []
+    for k in levels:
+        n = 2 ** (k - 1)
+        rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, 1.0)
+        proto = hlu.HLU(rp, ci, va, mid, 2.0, args.leaf)
+        b = torch.tensor(hlu.hlu_kuhn_load(n, (0.0, 0.0, 1.0)), device="cuda").reshape(1, -1)
+        its = []
+        for kp in PAPER_KAPPAS:
+            kappa = math.sqrt(kp)
+            rp, ci, va, _ = hlu.hlu_kuhn_assemble(n, kappa)
+            A = hlu.SpMat(rp, ci, va)
+            H = hlu.HLU(rp, ci, va, share=proto)
+            H.hlu_factor(args.eps, prec="fp64", allow_overflow=True)
+            x, info = hlu.gmres_solve(A, b, H, restart=100, tol=1e-5, max_iters=args.table1_max_iters,
+                                      raise_on_fail=False)
+            its.append(info[0]["iters"] if info[0]["converged"] else None)
+            log(f"k={k} (n={n}, N={A.n}) kappa={kp:g}: iters {info[0]['iters']} converged {info[0]['converged']} "
+                f"relres {info[0]['relres']:.2e}")
+            del H
+        rows.append({"k": k, "n": n, "N": int(len(rp) - 1), "iters": its, "paper": PAPER_TABLE1.get(k)})
+    line = {
+        "metric": "Example 1 (Table 1 protocol): preconditioned GMRES iterations to 1e-5",
+        "unit": "iterations", "n_gpus": 1, "dtype": "f64-hlu+f64-gmres", "data": "synthetic",
+        "config": {"workload": f"Kuhn unit cube, n = 2^(k-1), J_S = (0,0,1), paper kappa in {PAPER_KAPPAS} "
+                               f"(A = K - kappa M), GMRES(100) to 1e-5, FP64 H-LU eps {args.eps:g}, leaf "
+                               f"{args.leaf}, eta 2; None = not converged within {args.table1_max_iters}",
+                   "kappas": PAPER_KAPPAS},
+        "rows": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def second_kappa(args, H1, Xs, stream):
     """The same mesh, structure and x* columns at kappa = args.kappa2 (near
     the cavity eigenvalue 26 pi^2 at kappa = 16): one factorisation (timed
@@ -424,6 +483,8 @@ def main():
         sys.exit(2)
     if args.batch:
         return batch_main(args)
+    if args.table1:
+        return table1_main(args)
     if args.serve:
         return serve_main(args)
     import numpy as np

@@ -136,6 +136,11 @@ hlu_status hlu_kuhn_sizes(int32_t n, int32_t* N, int64_t* nnz);
 hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col,
                              double* val, int32_t* mid2);
 
+/* Right-hand side of the weak form (Sec. 2.1) for a constant source field
+ * J[3] (Example 1: J_S = (0, 0, 1)): b[j] = <J, Phi_j> over the interior
+ * edges, exact, into the caller's host array b[N]. */
+hlu_status hlu_kuhn_load(int32_t n, const double* J, double* b);
+
 /* ----------------------------------------------------------- sparse matrix
  * Wraps a device CSR (borrowed: the caller keeps d_row_ptr[n+1], d_col[nnz],
  * d_val[nnz] alive until hlu_spmat_destroy). */

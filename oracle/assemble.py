@@ -106,6 +106,20 @@ class Discretisation:
         self.A.sort_indices()
         self.N = len(inner)
 
+    def load(self, J):
+        """b_j = <J, Phi_j> over the interior edges for a constant field J:
+        the right-hand side of the weak form and of the Galerkin system
+        (Sec. 2.1; Example 1 takes J_S = (0, 0, 1)).  The integral of a
+        barycentric coordinate over T is |T|/4, so tetrahedron T adds
+        |T|/4 J.(grad lambda_b - grad lambda_a) to its local edge (a, b)."""
+        J = np.asarray(J, dtype=np.float64)
+        vol, g = element_geometry(self.mesh)
+        l2g = local_to_global_edges(self.mesh)
+        full = np.zeros(len(self.mesh.edges))
+        for e, (a, b) in enumerate(LOCAL_EDGES):
+            np.add.at(full, l2g[:, e], vol / 4.0 * ((g[:, b] - g[:, a]) @ J))
+        return full[self.mesh.interior]
+
     def discrete_gradient(self):
         """G: interior edges x interior vertices, +1 at the head, -1 at the tail."""
         mesh = self.mesh

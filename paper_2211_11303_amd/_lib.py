@@ -75,6 +75,7 @@ class ServerStats(ctypes.Structure):
 SIGNATURES = {
     "hlu_last_error": (ctypes.c_char_p, []),
     "hlu_kuhn_sizes": (c_int32, [c_int32, P_i32, ctypes.POINTER(c_int64)]),
+    "hlu_kuhn_load": (c_int32, [c_int32, P_f64, P_f64]),
     "hlu_kuhn_assemble": (c_int32, [c_int32, c_double, P_i32, P_i32, P_f64, P_i32]),
     "hlu_spmat_create": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "hlu_spmat_destroy": (None, [c_void_p]),

@@ -21,6 +21,7 @@ thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 const char* get_error() { return g_last_error.c_str(); }
 
+void kuhn_load(int n, const double J[3], std::vector<double>* b);
 void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
                    std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N);
 
@@ -466,6 +467,17 @@ hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t*
     std::memcpy(col, ci.data(), ci.size() * sizeof(int32_t));
     std::memcpy(val, v.data(), v.size() * sizeof(double));
     std::memcpy(mid2, mid.data(), mid.size() * sizeof(int32_t));
+  });
+}
+
+hlu_status hlu_kuhn_load(int32_t n, const double* J, double* b) {
+  return guard([&] {
+    HLU_REQUIRE(n >= 1 && n <= 128 && J && b, HLU_ERR_INVALID_ARG, "hlu_kuhn_load: bad arguments");
+    HLU_REQUIRE(std::isfinite(J[0]) && std::isfinite(J[1]) && std::isfinite(J[2]), HLU_ERR_INVALID_ARG,
+                "hlu_kuhn_load: J must be finite");
+    std::vector<double> v;
+    kuhn_load(n, J, &v);
+    std::memcpy(b, v.data(), v.size() * sizeof(double));
   });
 }
 

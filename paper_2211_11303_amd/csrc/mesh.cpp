@@ -63,8 +63,9 @@ double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1]
 
 const int kLocalEdge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 
-// Local K and M of one tetrahedron with vertex coordinates x[4][3].
-void element(const double x[4][3], double Kl[6][6], double Ml[6][6]) {
+// Barycentric gradients g[4][3] of one tetrahedron with vertex coordinates
+// x[4][3]; returns its volume.
+double gradients(const double x[4][3], double g[4][3]) {
   double J[3][3];  // columns x1-x0, x2-x0, x3-x0
   for (int c = 0; c < 3; ++c)
     for (int r = 0; r < 3; ++r) J[r][c] = x[c + 1][r] - x[0][r];
@@ -83,13 +84,19 @@ void element(const double x[4][3], double Kl[6][6], double Ml[6][6]) {
   inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
   inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
   inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-  double g[4][3];
   for (int a = 0; a < 3; ++a) {
     g[a + 1][0] = inv[a][0];
     g[a + 1][1] = inv[a][1];
     g[a + 1][2] = inv[a][2];
   }
   for (int c = 0; c < 3; ++c) g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
+  return vol;
+}
+
+// Local K and M of one tetrahedron with vertex coordinates x[4][3].
+void element(const double x[4][3], double Kl[6][6], double Ml[6][6]) {
+  double g[4][3];
+  const double vol = gradients(x, g);
   auto I = [&](int p, int q) { return vol * (p == q ? 2.0 : 1.0) / 20.0; };
   for (int e = 0; e < 6; ++e) {
     int a = kLocalEdge[e][0], b = kLocalEdge[e][1];
@@ -111,6 +118,29 @@ struct Triplet {
   double v;
 };
 
+// Lattice vertices v[4][3] of tetrahedron p (axis permutation) of cube
+// (i, j, k): the monotone path c, c + e_p0, c + e_p0 + e_p1, c + (1,1,1).
+void tet_vertices(int i, int j, int k, int p, int v[4][3]) {
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  v[0][0] = i;
+  v[0][1] = j;
+  v[0][2] = k;
+  for (int s = 0; s < 3; ++s) {
+    for (int a = 0; a < 3; ++a) v[s + 1][a] = v[s][a];
+    v[s + 1][perms[p][s]] += 1;
+  }
+}
+
+// Interior dof of the local edges of a tetrahedron (-1: boundary edge).
+void local_dofs(const KuhnDofs& D, const int v[4][3], int32_t ld[6]) {
+  for (int e = 0; e < 6; ++e) {
+    const int* va = v[kLocalEdge[e][0]];
+    const int* vb = v[kLocalEdge[e][1]];
+    const int d = dir_index(vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]);
+    ld[e] = D.dof[D.vid(va[0], va[1], va[2]) * 7 + d];
+  }
+}
+
 void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
               std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* Nout) {
   KuhnDofs D(n);
@@ -118,29 +148,19 @@ void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<in
   const double k2 = kappa * kappa;
   std::vector<Triplet> trip;
   trip.reserve((size_t)6 * n * n * n * 36);
-  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i)
         for (int p = 0; p < 6; ++p) {
           int v[4][3];
-          v[0][0] = i; v[0][1] = j; v[0][2] = k;
-          for (int s = 0; s < 3; ++s) {
-            for (int a = 0; a < 3; ++a) v[s + 1][a] = v[s][a];
-            v[s + 1][perms[p][s]] += 1;
-          }
+          tet_vertices(i, j, k, p, v);
           double x[4][3];
           for (int s = 0; s < 4; ++s)
             for (int a = 0; a < 3; ++a) x[s][a] = double(v[s][a]) / n;
           double Kl[6][6], Ml[6][6];
           element(x, Kl, Ml);
           int32_t ld[6];
-          for (int e = 0; e < 6; ++e) {
-            const int* va = v[kLocalEdge[e][0]];
-            const int* vb = v[kLocalEdge[e][1]];
-            int d = dir_index(vb[0] - va[0], vb[1] - va[1], vb[2] - va[2]);
-            ld[e] = D.dof[D.vid(va[0], va[1], va[2]) * 7 + d];
-          }
+          local_dofs(D, v, ld);
           for (int e = 0; e < 6; ++e) {
             if (ld[e] < 0) continue;
             for (int f = 0; f < 6; ++f) {
@@ -184,6 +204,33 @@ void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<in
 void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
                    std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N) {
   assemble(n, kappa, row_ptr, col, val, mid2, N);
+}
+
+// b_j = <J, Phi_j> for a constant field J (the right-hand side of the weak
+// form, Sec. 2.1): the integral of a barycentric coordinate over T is |T|/4,
+// so T adds |T|/4 J.(grad lambda_b - grad lambda_a) to its local edge (a, b).
+void kuhn_load(int n, const double J[3], std::vector<double>* b) {
+  KuhnDofs D(n);
+  b->assign(D.N, 0.0);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        for (int p = 0; p < 6; ++p) {
+          int v[4][3];
+          tet_vertices(i, j, k, p, v);
+          double x[4][3], g[4][3];
+          for (int s = 0; s < 4; ++s)
+            for (int a = 0; a < 3; ++a) x[s][a] = double(v[s][a]) / n;
+          const double vol = gradients(x, g);
+          int32_t ld[6];
+          local_dofs(D, v, ld);
+          for (int e = 0; e < 6; ++e) {
+            if (ld[e] < 0) continue;
+            const int a = kLocalEdge[e][0], c = kLocalEdge[e][1];
+            double d[3] = {g[c][0] - g[a][0], g[c][1] - g[a][1], g[c][2] - g[a][2]};
+            (*b)[ld[e]] += vol / 4.0 * dot3(J, d);
+          }
+        }
 }
 
 }  // namespace hlu

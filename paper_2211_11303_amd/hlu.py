@@ -81,6 +81,15 @@ def hlu_autotune_leaf(n, kappa, leaves=(32, 48, 64), eta=2.0, eps=1e-3, max_rank
     return int(best[0]), secs.tolist()
 
 
+def hlu_kuhn_load(n, J=(0.0, 0.0, 1.0)):
+    """b_j = <J, Phi_j> over the interior edges (host numpy array)."""
+    N, _ = hlu_kuhn_sizes(n)
+    Jv = np.ascontiguousarray(J, np.float64)
+    b = np.empty(N, np.float64)
+    L.check(L.lib().hlu_kuhn_load(int(n), _ptr(Jv, ctypes.c_double), _ptr(b, ctypes.c_double)))
+    return b
+
+
 # ------------------------------------------------------------ sparse matrix
 class SpMat:
     """Device CSR of A (hlu_spmat)."""

@@ -42,6 +42,19 @@ def test_assembly_matches_oracle(n, kappa):
     assert hlu.hlu_kuhn_sizes(n) == (7 * n ** 3 - 9 * n ** 2 + 3 * n, len(ci))
 
 
+@pytest.mark.parametrize("n", [1, 2, 4, 8])
+def test_load_matches_oracle(n):
+    """hlu_kuhn_load against the oracle's load (itself pinned by the exact
+    reproduction of constant fields and G^T b = 0)."""
+    from paper_2211_11303_amd import hlu
+    d = Discretisation(n, 1.0)
+    for J in ((0.0, 0.0, 1.0), (0.3, -1.2, 0.7)):
+        b = hlu.hlu_kuhn_load(n, J)
+        ref = d.load(J)
+        assert b.shape == ref.shape
+        assert np.abs(b - ref).max() <= 1e-14 * max(1e-300, np.abs(ref).max())
+
+
 @pytest.mark.parametrize("n,leaf", [(4, 32), (4, 8), (5, 20), (8, 64), (8, 17)])
 def test_structure_bit_exact(n, leaf):
     from paper_2211_11303_amd import hlu

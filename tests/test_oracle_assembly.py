@@ -80,3 +80,23 @@ def test_cavity_eigenvalue_convergence():
         errs.append(np.max(np.abs(pos - 2 * np.pi ** 2)) / (2 * np.pi ** 2))
     assert errs[1] < 0.05
     assert errs[0] / errs[1] > 3.0
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_load_of_constant_field(n):
+    """<J, Phi_j> for a constant J, two ways.  Whitney forms reproduce a
+    constant field exactly, J = sum over all edges of (J . (p_head - p_tail))
+    Phi_e, so the load equals (M_full d)[interior] with d_e = J . (p_head -
+    p_tail), the mass matrix pinned above.  And since div J = 0, the load
+    is orthogonal to the gradients of interior hat functions: G^T b = 0."""
+    d = Discretisation(n, 1.0)
+    m = d.mesh
+    p = m.coords.astype(np.float64) / n
+    for J in (np.array([0.0, 0.0, 1.0]), np.array([0.3, -1.2, 0.7])):
+        b = d.load(J)
+        de = (p[m.edges[:, 1]] - p[m.edges[:, 0]]) @ J
+        ref = (d.M_full @ de)[m.interior]
+        assert np.abs(b - ref).max() <= 1e-14 * np.abs(ref).max()
+        G = d.discrete_gradient()
+        assert np.abs(G.T @ b).max() <= 1e-14 * np.abs(b).max()
+        assert np.abs(b).max() > 0
