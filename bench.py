@@ -84,8 +84,8 @@ def parse():
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, each scaled by the reading
 # of a plain copy kernel of known size; valid only for the sources it was
 # measured on (profiles/solve_persistent_32cube_fp32_hbm_traffic.md).
-SOLVE_TRAFFIC = {"sha256": "2fcd428a4e3f68dd1558e5a978aea20f235a3e048a81dc0ed083c0d7179d8426", "columns": 24,
-                 "bytes_per_launch": 7354988139}
+SOLVE_TRAFFIC = {"sha256": "534f9e253cfc708889edf8ab40b28b350909119adbc7c093d37f2531115b440b", "columns": 24,
+                 "bytes_per_launch": 7351435015}
 SOLVE_SOURCES = ("paper_2211_11303_amd/csrc/kernels_solve.hip", "paper_2211_11303_amd/csrc/solve_sched.cpp",
                  "paper_2211_11303_amd/csrc/solve_sched.h")
 
