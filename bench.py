@@ -313,8 +313,10 @@ def serve_main(args):
         keys = sorted(mats)
         log(f"warming the factor cache: {len(keys)} (n, kappa) pairs")
         warm = [srv.hlu_server_submit(n, k, np.zeros((1, mats[(n, k)].shape[0]))) for n, k in keys]
-        for tk in warm:
+        for i, tk in enumerate(warm):
             srv.hlu_server_wait(tk, raise_on_fail=False)
+            if i % 10 == 9:
+                log(f"warmed {i + 1}")
     st0 = srv.hlu_server_get_stats()
     setup_s = time.perf_counter() - t
     log(f"serving {len(reqs)} requests at {args.serve_rate}/s")
