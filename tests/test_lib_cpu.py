@@ -172,3 +172,18 @@ def test_autotune_rejects_bad_arguments():
         st = L.lib().hlu_autotune_leaf(4, 2.0, 2.0, arr, count, ctypes.byref(fo), ctypes.byref(go), nrhs, secs,
                                        ctypes.byref(best), None)
         assert st == L.STATUS_CODES["HLU_ERR_INVALID_ARG"], (cand, count, nrhs, st)
+
+
+@pytest.mark.parametrize("n,leaf", [(12, 64), (12, 32)])
+def test_planning_mid_size(n, leaf):
+    """Host planning of a mid-size mesh: the factor plan and the persistent
+    solve schedule are built (the schedule builder checks that every
+    T-product is formed exactly once, by a leaf task or by one T-product
+    task) and the sizes are consistent."""
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, 8.0)
+    h = hlu.HLU(rp, ci, va, mid, 2.0, leaf)
+    b32 = h.hlu_workspace_bytes(1e-3, prec="fp32")
+    st = h.hlu_get_stats()
+    assert b32 > 0 and st["factor_waves"] > 0 and st["factor_tasks"] > st["factor_waves"]
+    assert st["num_leaf_clusters"] * 2 - 1 == st["num_clusters"]
