@@ -16,7 +16,7 @@ factorisations are timed separately (HIP events) and reported beside it,
 with the same steps for the FP64 H-LU and for FP32 factors computed with
 FP64 task arithmetic, and one solve of the same columns at kappa = 16.
 
-Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  --gpus above 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -480,8 +480,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
-              f"supported by this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported",
+              file=sys.stderr)
         sys.exit(2)
     if args.batch:
         return batch_main(args)

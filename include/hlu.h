@@ -49,7 +49,7 @@ typedef enum {
   HLU_ERR_STATE = -6,          /* call out of order (e.g. solve before factor)*/
   HLU_ERR_RANK_OVERFLOW = -7,  /* a truncated rank exceeded the block's
                                   storage capacity (result kept at capacity)  */
-  HLU_ERR_UNSUPPORTED = -8     /* input outside what this build handles       */
+  HLU_ERR_UNSUPPORTED = -8     /* input outside what the library handles     */
 } hlu_status;
 
 /* Precision of an H-LU.  HLU_FP64: factors stored and computed in FP64.
