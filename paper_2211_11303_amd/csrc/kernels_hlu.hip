@@ -501,7 +501,7 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
 }
 
 constexpr int kCompressMin = 8;         // S larger than this is compressed before the eigensolver
-constexpr double kCompressTol = 0.003;  // relative pivot tolerance of that compression, in units of eps
+constexpr double kCompressTol = 0.01;   // relative pivot tolerance of that compression, in units of eps
 
 template <class T>
 __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops, const TruncPart* parts,
@@ -523,9 +523,9 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   const TruncOp op = ops[blockIdx.x];
   const double tol2 = floor_rel * floor_rel;
   // Jacobi stops when the remaining off-diagonal part of the core is far
-  // below the truncation threshold: (0.01 eps)^4 relative in squared
+  // below the truncation threshold: (0.03 eps)^4 relative in squared
   // Frobenius norm (eigenvalues of the core are squared singular values)
-  const double te = 0.01 * fmax(eps, floor_rel);
+  const double te = 0.03 * fmax(eps, floor_rel);
   const double off_rel = fmax(1e-26, te * te * te * te);
   const int64_t t_start = trace ? (int64_t)wall_clock64() : 0;
   int rounds = 0, k_first = -1, r1_first = -1, sweeps = 0;
