@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--table1-levels", type=str, default="2,3,4,5",
                    help="refinement levels k (n = 2^(k-1) cubes per side)")
     p.add_argument("--table1-max-iters", type=int, default=500)
+    p.add_argument("--table1-all", action="store_true",
+                   help="also run the cells skipped by default (k = 5, kappa = 900)")
     p.add_argument("--batch-count", type=int, default=64)
     p.add_argument("--batch-leaves", type=str, default="32,48,64",
                    help="leaf sizes the autotuner measures per mesh size (one value: fixed leaf)")
@@ -389,6 +391,9 @@ def serve_main(args):
 PAPER_TABLE1 = {2: [1, 1, 1, 1, 1, 1], 3: [2, 2, 2, 2, 2, 2], 4: [2, 4, 5, 5, 4, 3], 5: [3, 4, 8, 9, 11, None],
                 6: [3, 6, 20, 4, 48, 25], 7: [4, 5, 7, 19, 46, 93]}
 PAPER_KAPPAS = [25.0, 100.0, 225.0, 400.0, 625.0, 900.0]
+# k = 5 at kappa = 900 (kappa h ~ 1.9): factor ranks above the 64-column block
+# capacity, and the run did not finish within minutes; skipped unless asked
+TABLE1_SKIP = {(5, 900.0)}
 
 
 def table1_main(args):
@@ -413,6 +418,9 @@ def table1_main(args):
         b = torch.tensor(hlu.hlu_kuhn_load(n, (0.0, 0.0, 1.0)), device="cuda").reshape(1, -1)
         its = []
         for kp in PAPER_KAPPAS:
+            if (k, kp) in TABLE1_SKIP and not args.table1_all:
+                its.append("skipped")
+                continue
             kappa = math.sqrt(kp)
             rp, ci, va, _ = hlu.hlu_kuhn_assemble(n, kappa)
             A = hlu.SpMat(rp, ci, va)
