@@ -251,9 +251,10 @@ def batch_main(args):
         "dtype": "f32-hlu+f64-gmres",
         "data": "synthetic",
         "config": {"workload": f"{args.batch_count} Kuhn-cube problems, n in {{8,12,16,20,24}} and kappa in "
-                               f"[1,10] from default_rng(7); eta=2, leaf autotuned per mesh size from "
-                               f"{{{args.batch_leaves}}}, eps={eps:g}, rank capacity {mr}; GMRES({args.restart}) "
-                               f"to {args.tol:g}, 1 rhs each",
+                               f"[1,10] from default_rng(7); eta=2, "
+                               + (f"leaf autotuned per mesh size from {{{args.batch_leaves}}}" if len(cands) > 1
+                                  else f"leaf {cands[0]}")
+                               + f", eps={eps:g}, rank capacity {mr}; GMRES({args.restart}) to {args.tol:g}, 1 rhs each",
                    "count": args.batch_count, "N_total": B.n_total, "leaf_by_n": leaf_by_n},
         "autotune_s": autotune_s,
         "autotune_device_s": {n: dict(zip(cands, v)) for n, v in tune_times.items()},
