@@ -28,6 +28,8 @@
 #include <climits>
 #include <map>
 #include <queue>
+#include <set>
+#include <tuple>
 
 #include "common.h"
 
@@ -624,30 +626,35 @@ class Planner {
     std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
       return temps_[a].first != temps_[b].first ? temps_[a].first < temps_[b].first : a < b;
     });
-    std::map<int64_t, int64_t> by_off;                 // free ranges: offset -> size
-    std::multimap<int64_t, int64_t> by_size;           // size -> offset
-    auto erase_size = [&](int64_t off, int64_t size) {
-      auto r = by_size.equal_range(size);
-      for (auto it = r.first; it != r.second; ++it)
-        if (it->second == off) {
-          by_size.erase(it);
-          return;
-        }
+    // free ranges, by offset (-> size, insertion order) and by (size,
+    // insertion order, offset): best fit takes the smallest size that fits,
+    // the oldest free range among equal sizes
+    using Key = std::tuple<int64_t, int64_t, int64_t>;
+    std::map<int64_t, std::pair<int64_t, int64_t>> by_off;
+    std::set<Key> by_size;
+    int64_t seq = 0;
+    auto add_free = [&](int64_t off, int64_t size) {
+      by_off[off] = {size, seq};
+      by_size.insert(Key{size, seq, off});
+      ++seq;
+    };
+    auto erase_size = [&](std::map<int64_t, std::pair<int64_t, int64_t>>::iterator it) {
+      by_size.erase(Key{it->second.first, it->second.second, it->first});
     };
     int64_t peak = 0;
     auto release = [&](int64_t off, int64_t size) {
       auto next = by_off.lower_bound(off);
       if (next != by_off.end() && next->first == off + size) {
-        size += next->second;
-        erase_size(next->first, next->second);
+        size += next->second.first;
+        erase_size(next);
         next = by_off.erase(next);
       }
       if (next != by_off.begin()) {
         auto prev = std::prev(next);
-        if (prev->first + prev->second == off) {
-          erase_size(prev->first, prev->second);
+        if (prev->first + prev->second.first == off) {
+          erase_size(prev);
           off = prev->first;
-          size += prev->second;
+          size += prev->second.first;
           by_off.erase(prev);
         }
       }
@@ -655,8 +662,7 @@ class Planner {
         peak = off;
         return;
       }
-      by_off[off] = size;
-      by_size.insert({size, off});
+      add_free(off, size);
     };
     using Ev = std::pair<int32_t, int32_t>;   // (last wave, temp)
     std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> live;
@@ -667,16 +673,13 @@ class Planner {
         release(L.phys, L.size);
         live.pop();
       }
-      auto it = by_size.lower_bound(T.size);
+      auto it = by_size.lower_bound(Key{T.size, INT64_MIN, INT64_MIN});
       if (it != by_size.end()) {
-        const int64_t off = it->second, size = it->first;
+        const int64_t size = std::get<0>(*it), off = std::get<2>(*it);
         by_size.erase(it);
         by_off.erase(off);
         T.phys = off;
-        if (size > T.size) {
-          by_off[off + T.size] = size - T.size;
-          by_size.insert({size - T.size, off + T.size});
-        }
+        if (size > T.size) add_free(off + T.size, size - T.size);
       } else {
         T.phys = peak;
         peak += T.size;
