@@ -690,18 +690,19 @@ class Planner {
     return max_peak_;
   }
 
+  // Physical offset of a virtual temporary offset: the temporary is found
+  // by binary search over the (increasing) virtual begins, kept in their own
+  // dense array while the plan is remapped.
   int64_t remap(int64_t off) const {
     if (off < temp_base_ || off >= temp_top_ || temps_.empty()) return off;
-    size_t lo = 0, hi = temps_.size();
-    while (hi - lo > 1) {
-      size_t mid = (lo + hi) / 2;
-      if (temps_[mid].vbegin <= off) lo = mid;
-      else hi = mid;
-    }
-    return temp_base_ + temps_[lo].phys + (off - temps_[lo].vbegin);
+    const size_t u = (size_t)(std::upper_bound(vbegin_.begin(), vbegin_.end(), off) - vbegin_.begin());
+    const size_t t = u > 0 ? u - 1 : 0;
+    return temp_base_ + temps_[t].phys + (off - vbegin_[t]);
   }
 
-  void remap_plan(Plan& P) const {
+  void remap_plan(Plan& P) {
+    vbegin_.resize(temps_.size());
+    for (size_t i = 0; i < temps_.size(); ++i) vbegin_[i] = temps_[i].vbegin;
     auto R = [&](MatRef& m) { m.off = remap(m.off); };
     for (auto& g : P.gemm) R(g.C);
     for (auto& t : P.terms) {
@@ -721,6 +722,7 @@ class Planner {
       R(p.Y);
     }
     for (auto& f : P.fill) R(f.M);
+    std::vector<int64_t>().swap(vbegin_);
   }
 
   HB temp_lowrank(int32_t r0, int32_t r1, int32_t c0, int32_t c1) {
@@ -937,6 +939,7 @@ class Planner {
   std::vector<int32_t> leaf_of_pos_;
   std::vector<int32_t> leaf_buf_, leaf_ybuf_, init_buf_;
   std::vector<Temp> temps_;
+  std::vector<int64_t> vbegin_;   // virtual begins of temps_, filled while the plan is remapped
   std::map<int32_t, std::vector<PartSpec>> pending_;
   std::map<int32_t, HB> temp_hb_;
   std::vector<int32_t> temp_of_buf_;
