@@ -198,6 +198,15 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream);
 hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
                      void* stream);
 
+/* Synchronises the stream and reports what the stream-ordered solves of h
+ * left on the device: HLU_ERR_DEVICE if a persistent solve launched on h
+ * since the previous report gave up waiting for one of its inputs (each
+ * wait is bounded by 20 s of device wall clock; the launch then drains and
+ * its result is invalid).  Clears the report.  gmres_solve checks the same
+ * word at every synchronisation of its iteration and fails with
+ * HLU_ERR_DEVICE. */
+hlu_status hlu_sync_status(hlu_handle h, void* stream);
+
 /* y = P^T L U P v (the product of the computed factors), for checking the
  * factor error; same layout rules as hlu_solve (no aliasing). */
 hlu_status hlu_apply_lu(hlu_handle h, const double* d_v, double* d_y, int32_t nrhs, int64_t ld,
@@ -236,6 +245,10 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
 hlu_status hlu_batch_create(const hlu_handle* hs, int32_t count, const hlu_factor_opts* o,
                             int32_t max_rhs, hlu_batch* out);
 void hlu_batch_destroy(hlu_batch b);
+
+/* hlu_sync_status for the batch's own persistent solves (hlu_solve_batch;
+ * gmres_solve_batch checks at every synchronisation). */
+hlu_status hlu_batch_sync_status(hlu_batch b, void* stream);
 
 /* count, n_total, row_base[count] (host, may be NULL) and the size of the
  * merged factor schedule (waves, tasks). */
@@ -379,6 +392,17 @@ hlu_status hlu_export_structure(hlu_handle h, int32_t* perm, int32_t* begin, int
  * dense blocks) after hlu_factor. Synchronous. */
 hlu_status hlu_get_ranks(hlu_handle h, int32_t* ranks);
 hlu_status hlu_get_stats(hlu_handle h, hlu_stats* out);
+
+/* Host replay of the round structure of every truncation of the factor
+ * plan for options o (Sec. 4: truncated SVD after each low-rank addition),
+ * with every rank the plan reads forced to forced_rank (>= 0): the rounds
+ * the device kernel would run if every truncation kept that rank (at most
+ * the block's capacity, the columns of the round and the round's limit).
+ * No device work.  out (host, 5 entries): truncation ops, total rounds,
+ * largest rounds of one op, rounds that absorbed no part column while parts
+ * remained (a block already at the round's 64 columns), ops that did not
+ * finish within their bound (0 for a plan the kernel completes). */
+hlu_status hlu_check_trunc_rounds(hlu_handle h, const hlu_factor_opts* o, int32_t forced_rank, int64_t* out);
 
 /* enable != 0: from now on bracket every persistent solve launch of hlu_solve
  * (and of gmres_solve's preconditioner) with HIP events on its stream;

@@ -97,6 +97,10 @@ SIGNATURES = {
     "hlu_get_ranks": (c_int32, [c_void_p, P_i32]),
     "hlu_get_stats": (c_int32, [c_void_p, ctypes.POINTER(Stats)]),
     "hlu_set_timing": (c_int32, [c_void_p, c_int32]),
+    "hlu_sync_status": (c_int32, [c_void_p, c_void_p]),
+    "hlu_batch_sync_status": (c_int32, [c_void_p, c_void_p]),
+    "hlu_check_trunc_rounds": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), c_int32,
+                                         ctypes.POINTER(c_int64)]),
     "hlu_build_shared": (c_int32, [c_void_p, ctypes.POINTER(HluCsr), ctypes.POINTER(c_void_p)]),
     "hlu_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(FactorOpts), c_int32,
                                    ctypes.POINTER(c_void_p)]),

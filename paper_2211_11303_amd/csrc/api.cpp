@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "trunc_rounds.h"
 
 namespace hlu {
 
@@ -85,8 +86,8 @@ void SolveBufs::alloc(const SolveSched& sc, int32_t N, int32_t rhs) {
   HIP_OK(hipMemset(flags, 0, nflags * sizeof(int32_t)));
   pstride = (int64_t)sc.max_m * rhs;
   pbuf = mem.keep(dmalloc<double>(std::max<size_t>(1, sc.dense.size()) * (size_t)pstride));
-  ctr = mem.keep(dmalloc<int32_t>(4));
-  HIP_OK(hipMemset(ctr, 0, 4 * sizeof(int32_t)));
+  ctr = mem.keep(dmalloc<int32_t>(kSolveCtrWords));
+  HIP_OK(hipMemset(ctr, 0, kSolveCtrWords * sizeof(int32_t)));
   if (getenv("HLU_DEBUG_SOLVE_TRACE")) trace = mem.keep(dmalloc<int64_t>(12 * std::max<size_t>(1, sc.tasks.size())));
   epoch = 0;
 }
@@ -99,7 +100,31 @@ size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t rhs) {
   b += (size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs * sizeof(double);
   b += (2 * (size_t)sc.L + sc.tprod.size() + sc.dense.size() + 1) * sizeof(int32_t);
   b += std::max<size_t>(1, sc.dense.size()) * (size_t)sc.max_m * rhs * sizeof(double);
-  return b + 4 * sizeof(int32_t);
+  return b + kSolveCtrWords * sizeof(int32_t);
+}
+
+int64_t solve_wait_ticks() {
+  static std::once_flag once;
+  static int64_t khz = 100000;   // 100 MHz unless the device says otherwise
+  std::call_once(once, [] {
+    int dev = 0, r = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&r, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+        r > 0)
+      khz = r;
+  });
+  double us = 20e6;
+  if (const char* e = getenv("HLU_DEBUG_SOLVE_WAIT_US")) us = std::max(0.0, atof(e));
+  return (int64_t)(us * (double)khz / 1000.0);
+}
+
+bool take_solve_error(int32_t* ctr, hipStream_t s) {
+  int32_t e = 0;
+  HIP_OK(hipMemcpyAsync(&e, ctr + 3, sizeof(e), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (e == 0) return false;
+  HIP_OK(zero_int_launch(ctr + 3, 1, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return true;
 }
 
 SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs& b) {
@@ -126,6 +151,7 @@ SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs
   v.pbuf = b.pbuf;
   v.pstride = b.pstride;
   v.trace = b.trace;
+  v.wait_ticks = solve_wait_ticks();
   v.ntasks = (int32_t)sc.tasks.size();
   v.n_fwd = sc.n_fwd_tasks;
   v.L = sc.L;
@@ -613,9 +639,10 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     if (fp32_storage(o->prec)) factor_impl<float>(h, s);
     else factor_impl<double>(h, s);
     HIP_OK(hipStreamSynchronize(s));
-    int32_t status[2];
+    int32_t status[3];
     HIP_OK(hipMemcpy(status, h->status, sizeof(status), hipMemcpyDeviceToHost));
     HLU_REQUIRE(status[0] == 0, HLU_ERR_ZERO_PIVOT, "hlu_factor: zero pivot in a diagonal leaf");
+    HLU_REQUIRE(status[2] == 0, HLU_ERR_DEVICE, "hlu_factor: a truncation exceeded its round bound");
     h->factored = true;
     gather_stats(h, h->sbuf->pivots);
     h->stats.capped_blocks = status[1];
@@ -644,6 +671,16 @@ hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs,
     } else {
       solve_persistent_impl<double>(h, d_b, d_x, nrhs, ld, s);
     }
+  });
+}
+
+hlu_status hlu_sync_status(hlu_handle h, void* stream) {
+  return guard([&] {
+    HLU_REQUIRE(h, HLU_ERR_INVALID_ARG, "hlu_sync_status: NULL handle");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(hipStreamSynchronize(s));
+    if (h->sbuf && take_solve_error(h->sbuf->ctr, s))
+      fail(HLU_ERR_DEVICE, "hlu_sync_status: a persistent solve gave up waiting for its inputs; its results are invalid");
   });
 }
 
@@ -702,6 +739,48 @@ hlu_status hlu_get_ranks(hlu_handle h, int32_t* ranks) {
     HIP_OK(hipMemcpy(dims.data(), h->dims, dims.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     const Structure& S = h->sh->S;
     for (size_t l = 0; l < S.leaves.size(); ++l) ranks[l] = st.slot[l] >= 0 ? dims[st.slot[l]] : -1;
+  });
+}
+
+hlu_status hlu_check_trunc_rounds(hlu_handle h, const hlu_factor_opts* o, int32_t forced_rank, int64_t* out) {
+  return guard([&] {
+    HLU_REQUIRE(h && out && forced_rank >= 0, HLU_ERR_INVALID_ARG, "hlu_check_trunc_rounds: bad arguments");
+    check_opts(o);
+    use_bundle(h, kcap_for(o));
+    const Plan& pl = h->pb->ps.factor;
+    // every rank of the plan (blocks and temporaries) forced to forced_rank
+    const std::vector<int32_t> dims((size_t)std::max(1, h->pb->ps.store.num_slots), forced_rank);
+    int64_t rounds = 0, max_rounds = 0, stalled = 0, unfinished = 0;
+    for (const TruncOp& op : pl.trunc) {
+      const int bound = trunc_max_rounds(op, pl.parts.data(), dims.data());
+      int r = std::min(forced_rank, op.cap);
+      TruncCursor cur{0, 0};
+      int n = 0;
+      while (true) {
+        bool done = false;
+        int absorbed = 0;
+        const int K = trunc_round_columns(op, pl.parts.data(), dims.data(), r, &cur, &done,
+                                          [&](int, int p, int) { absorbed += p >= 0; });
+        if (K == 0) break;
+        ++n;
+        stalled += absorbed == 0 && !done;
+        // the truncation keeps at most K columns, its eps-rank forced_rank
+        // and the round's limit
+        r = std::min(std::min(forced_rank, K), trunc_rank_limit(op, done));
+        if (done) break;
+        if (n >= bound) {
+          ++unfinished;
+          break;
+        }
+      }
+      rounds += n;
+      max_rounds = std::max<int64_t>(max_rounds, n);
+    }
+    out[0] = (int64_t)pl.trunc.size();
+    out[1] = rounds;
+    out[2] = max_rounds;
+    out[3] = stalled;
+    out[4] = unfinished;
   });
 }
 

@@ -456,9 +456,10 @@ hlu_status hlu_factor_batch(hlu_batch b, void* stream) {
     if (fp32_storage(b->opts.prec)) factor_batch_impl<float>(b, s);
     else factor_batch_impl<double>(b, s);
     HIP_OK(hipStreamSynchronize(s));
-    int32_t status[2];
+    int32_t status[3];
     HIP_OK(hipMemcpy(status, static_cast<char*>(b->work) + b->status_off, sizeof(status), hipMemcpyDeviceToHost));
     HLU_REQUIRE(status[0] == 0, HLU_ERR_ZERO_PIVOT, "hlu_factor_batch: zero pivot in a diagonal leaf");
+    HLU_REQUIRE(status[2] == 0, HLU_ERR_DEVICE, "hlu_factor_batch: a truncation exceeded its round bound");
     for (size_t p = 0; p < b->hs.size(); ++p) {
       hlu_s* h = b->hs[p];
       h->factored = true;
@@ -497,6 +498,17 @@ hlu_status hlu_solve_batch(hlu_batch b, const double* d_b, double* d_x, int32_t 
   });
 }
 
+hlu_status hlu_batch_sync_status(hlu_batch b, void* stream) {
+  return guard([&] {
+    checked(b, false);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(hipStreamSynchronize(s));
+    if (b->bufs.ctr && take_solve_error(b->bufs.ctr, s))
+      fail(HLU_ERR_DEVICE,
+           "hlu_batch_sync_status: a persistent solve gave up waiting for its inputs; its results are invalid");
+  });
+}
+
 size_t gmres_batch_workspace_bytes(hlu_batch b, int32_t nrhs, int32_t restart) {
   if (!b || nrhs <= 0 || restart <= 0) return 0;
   return gmres_core_bytes((int64_t)b->N_tot * nrhs, (int32_t)b->hs.size() * nrhs, restart);
@@ -527,6 +539,7 @@ hlu_status gmres_solve_batch(hlu_batch b, const double* d_b, double* d_x, int32_
       HIP_OK(spmv_launch(N, b->d_rp, b->d_ci, b->d_val, in, out, nrhs, N, 1.0, 0.0, s));
     };
     sys.precond = [&](const double* in, double* out) { solve_batch(b, in, out, nrhs, s); };
+    sys.d_err = b->bufs.ctr + 3;
     gmres_core(sys, d_b, d_x, o, d_work, info, s);
     for (int32_t c = 0; c < sys.nseg; ++c)
       if (!info[c].converged) all_conv = false;

@@ -61,8 +61,15 @@ void gmres_core(const GmresSystem& sys, const double* b, double* x, const hlu_gm
   auto norms = [&](const double* vec, std::vector<double>* out) {
     HIP_OK(seg_dot_launch(nseg, doff, dlen, 1, vec, vstride, vec, part, dh, s));
     std::vector<double> t(nseg);
+    int32_t err = 0;
     HIP_OK(hipMemcpyAsync(t.data(), dh, nseg * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (sys.d_err) HIP_OK(hipMemcpyAsync(&err, sys.d_err, sizeof(err), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    if (err != 0) {
+      HIP_OK(zero_int_launch(sys.d_err, 1, s));
+      HIP_OK(hipStreamSynchronize(s));
+      fail(HLU_ERR_DEVICE, "gmres: a preconditioner launch gave up waiting for its inputs");
+    }
     out->resize(nseg);
     for (int c = 0; c < nseg; ++c) (*out)[c] = std::sqrt(std::max(0.0, t[c]));
   };
@@ -232,6 +239,10 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
         HIP_OK(hipMemcpyAsync(out, in, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
     };
+    if (precond) {
+      ensure_solve_bufs(precond);   // made by the first solve otherwise
+      sys.d_err = precond->sbuf->ctr + 3;
+    }
     gmres_core(sys, bb, xx, o, wp, info, s);
     HIP_OK(copy_cols_launch(N, nrhs, xx, N, d_x, ld, s));
     HIP_OK(hipStreamSynchronize(s));

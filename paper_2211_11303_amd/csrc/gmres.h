@@ -14,6 +14,9 @@ struct GmresSystem {
   int64_t total = 0;                 // elements of one vector block
   // whole-block operator and preconditioner: out = A in, out = M^{-1} in
   std::function<void(const double*, double*)> matvec, precond;
+  // error word of the preconditioner's persistent launches (ctr[3]), read
+  // at every synchronisation of the iteration; may be null
+  int32_t* d_err = nullptr;
 };
 
 // Device bytes gmres_core needs for blocks of `total` elements.

@@ -133,6 +133,18 @@ struct SolveBufs {
   void alloc(const SolveSched& sc, int32_t N, int32_t max_rhs);
 };
 
+// Words of a persistent solve's counter block (kernels_solve.hip: claim
+// counter, finished forward tasks, error of the launch, error since the host
+// last read it, workgroups that have left).
+constexpr int kSolveCtrWords = 8;
+// Longest wait of a persistent-solve task before its launch gives up, in
+// device wall-clock ticks: 20 s, or HLU_DEBUG_SOLVE_WAIT_US microseconds
+// (the tests force the error path with a tiny limit).
+int64_t solve_wait_ticks();
+// Reads and clears the error word a persistent launch leaves in ctr[3]
+// (synchronises the stream); true if some launch gave up a wait.
+bool take_solve_error(int32_t* ctr, hipStream_t s);
+
 // Device bytes SolveBufs::alloc takes for this schedule.
 size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t max_rhs);
 

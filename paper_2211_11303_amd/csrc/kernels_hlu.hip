@@ -8,15 +8,15 @@
 #include <cstdlib>
 
 #include <cstdint>
+#include <mutex>
 
 #include "plan.h"
+#include "trunc_rounds.h"
 
 namespace hlu {
 namespace dev {
 
-__device__ __forceinline__ int dimv(int32_t code, const int32_t* dims) {
-  return code >= 0 ? code : dims[-code - 1];
-}
+__device__ __forceinline__ int dimv(int32_t code, const int32_t* dims) { return dim_of(code, dims); }
 
 template <class T>
 __device__ __forceinline__ T& at(T* base, const MatRef& m, int i, int j) {
@@ -252,8 +252,9 @@ __global__ void fill_kernel(T* arena, const FillOp* ops, const int32_t* dims) {
 // (r <= capacity) gives the best rank-r approximation Q W_r W_r^T R Ya^T:
 //   X_C = Xa T_x,  T_x = P_1..r1 R11^{-1} W_r   (orthonormal columns)
 //   Y_C = Ya T_y,  T_y = R^T W_r                (norms sigma_i)
-// More than kKMax columns are absorbed in chunks, truncating after each.
-constexpr int kKMax = 64;
+// More than kKMax columns are absorbed in rounds, truncating after each; the
+// round structure and its termination bound are in trunc_rounds.h.
+constexpr int kKMax = kTruncCols;
 constexpr int kLd = kKMax + 1;
 
 struct ColSrc {
@@ -518,7 +519,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   __shared__ double red[8];
   __shared__ int piv[kKMax], chosen[kKMax], sel[kKMax], pk[kKMax], pfirst[kKMax];
   __shared__ int s_int[4];
-  __shared__ int s_K, s_r, s_r1, s_part, s_pcol, s_done;
+  __shared__ int s_K, s_r, s_r1, s_part, s_pcol, s_done, s_maxr;
 
   const TruncOp op = ops[blockIdx.x];
   const double tol2 = floor_rel * floor_rel;
@@ -543,40 +544,28 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
     s_r = dims[op.slot];
     s_part = 0;
     s_pcol = 0;
+    s_maxr = trunc_max_rounds(op, parts, dims);
   }
   __syncthreads();
   while (true) {
-    // column list: current C columns, then up to kKMax - r part columns
+    // column list: current C columns, then part columns (trunc_rounds.h)
     if (threadIdx.x == 0) {
-      int K = 0;
-      const int r = s_r;
-      for (int a = 0; a < r; ++a) {
-        xs[K] = ColSrc{op.xoff + (int64_t)a * op.ldx, 1, 0, op.m, 1.0};
-        ys[K] = ColSrc{op.yoff + (int64_t)a * op.ldy, 1, 0, op.n, 1.0};
-        ++K;
-      }
-      int p = s_part, c = s_pcol;
-      while (p < op.np && K < kKMax) {
-        const TruncPart P = parts[op.p0 + p];
-        const int kp = dimv(P.X.cols, dims);
-        if (c >= kp) {
-          ++p;
-          c = 0;
-          continue;
+      TruncCursor cur{s_part, s_pcol};
+      bool done = false;
+      const int K = trunc_round_columns(op, parts, dims, s_r, &cur, &done, [&](int k, int p, int c) {
+        if (p < 0) {
+          xs[k] = ColSrc{op.xoff + (int64_t)c * op.ldx, 1, 0, op.m, 1.0};
+          ys[k] = ColSrc{op.yoff + (int64_t)c * op.ldy, 1, 0, op.n, 1.0};
+        } else {
+          const TruncPart P = parts[op.p0 + p];
+          xs[k] = ColSrc{P.X.off + (int64_t)c * P.X.cs, P.X.rs, P.row_off, dimv(P.X.rows, dims), P.alpha};
+          ys[k] = ColSrc{P.Y.off + (int64_t)c * P.Y.cs, P.Y.rs, P.col_off, dimv(P.Y.rows, dims), 1.0};
         }
-        xs[K] = ColSrc{P.X.off + (int64_t)c * P.X.cs, P.X.rs, P.row_off, dimv(P.X.rows, dims), P.alpha};
-        ys[K] = ColSrc{P.Y.off + (int64_t)c * P.Y.cs, P.Y.rs, P.col_off, dimv(P.Y.rows, dims), 1.0};
-        ++K;
-        ++c;
-      }
-      while (p < op.np && c >= dimv(parts[op.p0 + p].X.cols, dims)) {
-        ++p;
-        c = 0;
-      }
-      s_part = p;
-      s_pcol = c;
+      });
+      s_part = cur.part;
+      s_pcol = cur.col;
       s_K = K;
-      s_done = (p >= op.np);
+      s_done = done;
     }
     __syncthreads();
     const int K = s_K;
@@ -706,8 +695,9 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         for (int k = 0; k < r1; ++k)
           if (sqrt(mu[sel[k]]) > thr) ++cnt;
         if (s1 == 0.0) cnt = 0;
-        const int r = cnt < op.cap ? cnt : op.cap;
-        if (cnt > op.cap) atomicAdd(&status[1], 1);
+        const int lim = trunc_rank_limit(op, s_done != 0);
+        const int r = cnt < lim ? cnt : lim;
+        if (cnt > lim) atomicAdd(&status[1], 1);
         s_r = r;
       }
       __syncthreads();
@@ -761,6 +751,10 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
     __syncthreads();
     ++rounds;
     if (s_done) break;
+    if (rounds >= s_maxr) {   // unreachable by the round structure; reported, never spun on
+      if (threadIdx.x == 0) atomicAdd(&status[2], 1);
+      break;
+    }
   }
   if (threadIdx.x == 0) dims[op.slot] = s_r;
   if (trace && threadIdx.x == 0) {   // debug: per-op size and clocks
@@ -784,13 +778,12 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
 constexpr int64_t kTruncTraceOps = 12 << 20;
 int64_t* trunc_trace_buffer(size_t* ops) {
   static int64_t* buf = nullptr;
-  static bool tried = false;
-  if (!tried) {
-    tried = true;
+  static std::once_flag tried;
+  std::call_once(tried, [] {
     if (getenv("HLU_DEBUG_TRUNC_TRACE") &&
         hipMalloc(&buf, (size_t)kTruncTraceOps * kTruncTraceFields * sizeof(int64_t)) != hipSuccess)
       buf = nullptr;
-  }
+  });
   if (ops) *ops = (size_t)kTruncTraceOps;
   return buf;
 }
@@ -799,15 +792,14 @@ template <class T, class C>
 hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
                          double eps, double floor_rel, int32_t max_leaf, int32_t tile_base,
                          hipStream_t s) {
-  static bool attrs_set = false;
-  if (!attrs_set) {
+  static std::once_flag attrs_set;   // launchers run on several server threads
+  std::call_once(attrs_set, [] {
     // allow dynamic LDS up to the 160 KB of a gfx950 CU
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::getrf_kernel<T, C>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dev::kLdsBytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::tri_kernel<T, C>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dev::kLdsBytes);
-    attrs_set = true;
-  }
+  });
   if (w.count[kFill] > 0) {
     dim3 g(64, w.count[kFill]);
     dev::fill_kernel<T><<<g, 256, 0, s>>>(arena, P.fill + w.begin[kFill], dims);

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "solve_sched.h"
 
@@ -24,7 +25,6 @@ constexpr int kSolTilesPerWave = 2;   // solution rows: (64 / 16) row tiles x 2 
 
 constexpr int kSolveThreads = 256;
 constexpr int kMaxRhsTile = 8;          // columns per register tile of the triangular solve
-constexpr int kSpinLimit = 1 << 25;     // bounded waits; on overflow the error flag is set
 // debug trace per task: claim, solve start, end, workgroup, low-rank done,
 // triangle done, product done, flags stored, batched low-rank started,
 // batched low-rank done, neighbour record published (fused form), (unused)
@@ -41,7 +41,9 @@ struct SolveArgs {
   double* tbuf;         // T products
   int32_t* leaf_flag;   // 2L flags
   int32_t* tp_flag;     // one per T-product
-  int32_t* ctr;         // [0] claim counter, [1] finished forward tasks, [2] error
+  int32_t* ctr;         // [0] claim counter, [1] finished forward tasks, [2] error of this
+                        // launch, [3] error of any launch since the host last read it,
+                        // [4] workgroups that have left the task loop
   const int32_t* push0; // push task -> first record in push_recs
   const int32_t* push_recs;
   const int32_t* leaf_tq; // T-product chunks computed by leaf tasks
@@ -51,6 +53,7 @@ struct SolveArgs {
   int32_t* pflag;       // one per record
   int64_t pstride;
   int64_t* trace;       // optional (debug): kTraceFields clocks per task
+  int64_t wait_ticks;   // longest wait, in wall-clock ticks, before the launch gives up
   int32_t ntasks, n_fwd, N, nrhs, max_rhs, L, epoch;
   int32_t cur_task;     // set per task (trace only)
 };
@@ -73,14 +76,17 @@ __device__ __forceinline__ int32_t load_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Spin (relaxed loads, no cache maintenance) until *f == want, bounded;
-// returns false on timeout or if another task already reported one.
-__device__ bool spin_eq(const int32_t* f, int32_t want, int32_t* err) {
-  int spins = 0;
+// Spin (relaxed loads, no cache maintenance) until *f == want, for at most
+// `ticks` of the constant-rate wall clock; returns false on timeout (and
+// sets the launch's error word) or if another task already reported one.
+// After an error every wait returns at once, so the launch drains.
+__device__ bool spin_eq(const int32_t* f, int32_t want, int32_t* err, int64_t ticks) {
+  if (load_relaxed(f) == want) return true;
+  const int64_t t0 = (int64_t)wall_clock64();
   while (load_relaxed(f) != want) {
     if (load_relaxed(err) != 0) return false;
     __builtin_amdgcn_s_sleep(2);
-    if (++spins > kSpinLimit) {
+    if ((int64_t)wall_clock64() - t0 > ticks) {
       __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -98,12 +104,12 @@ __device__ void acquire_all() {
 // All threads: wait for flags[lf0..lf1) == epoch, then acquire.
 __device__ void wait_leaves(const SolveArgs& a, int base, int lf0, int lf1) {
   for (int f = lf0 + (int)threadIdx.x; f < lf1; f += blockDim.x)
-    spin_eq(a.leaf_flag + base + f, a.epoch, a.ctr + 2);
+    spin_eq(a.leaf_flag + base + f, a.epoch, a.ctr + 2, a.wait_ticks);
   acquire_all();
 }
 
 __device__ void wait_one(const SolveArgs& a, const int32_t* f, int32_t want) {
-  if (threadIdx.x == 0) spin_eq(f, want, a.ctr + 2);
+  if (threadIdx.x == 0) spin_eq(f, want, a.ctr + 2, a.wait_ticks);
   acquire_all();
 }
 
@@ -291,7 +297,7 @@ __device__ bool low_batched(const SolveArgs& a, const T* arena, const SLeaf& lf,
       const int vc = min(kKC, wn - v0);
       // the T products of the contributions overlapping these columns
       if (kt > 0 && my0 < w0 + v0 + vc && my1 > w0 + v0)
-        for (int q = 0; q < Lw.ntp; ++q) spin_eq(a.tp_flag + Lw.tp + q, a.epoch, a.ctr + 2);
+        for (int q = 0; q < Lw.ntp; ++q) spin_eq(a.tp_flag + Lw.tp + q, a.epoch, a.ctr + 2, a.wait_ticks);
       acquire_all();
       // T rows and the first X pass are loaded together, then written
       double tr[8];
@@ -409,7 +415,7 @@ __device__ void run_leaf(const SolveArgs& a, const T* arena, const T* inv, const
   // dense contributions: the partial-sum records of this row in record
   // order, except the one the preceding leaf task forms, which comes last
   for (int t = threadIdx.x; t < lf.nd; t += blockDim.x)
-    if (lf.d0 + t != lf.prev_rec) spin_eq(a.pflag + lf.d0 + t, a.epoch, a.ctr + 2);
+    if (lf.d0 + t != lf.prev_rec) spin_eq(a.pflag + lf.d0 + t, a.epoch, a.ctr + 2, a.wait_ticks);
   acquire_all();
   for (int t0 = 0; t0 < lf.nd; t0 += 4) {
     // four records' loads in flight together
@@ -748,6 +754,13 @@ __global__ void __launch_bounds__(kSolveThreads) solve_persistent_kernel(const T
     }
     __syncthreads();
   }
+  // the last workgroup to leave folds this launch's error word into the
+  // word the host reads (hlu_sync_status, GMRES)
+  if (threadIdx.x == 0) {
+    const int32_t left = __hip_atomic_fetch_add(a.ctr + 4, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (left == (int32_t)gridDim.x - 1 && load_relaxed(a.ctr + 2) != 0)
+      __hip_atomic_store(a.ctr + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Inverses of the two triangles of each diagonal leaf, one workgroup per
@@ -846,7 +859,7 @@ __global__ void __launch_bounds__(256) next_inverse_kernel(const T* arena, const
 }
 
 __global__ void solve_reset_kernel(int32_t* ctr) {
-  if (threadIdx.x < 2) ctr[threadIdx.x] = 0;
+  if (threadIdx.x < 3 || threadIdx.x == 4) ctr[threadIdx.x] = 0;
 }
 
 }  // namespace dev
@@ -857,15 +870,14 @@ hipError_t solve_persistent_launch(const T* arena, const int32_t* dims, const So
   dev::solve_reset_kernel<<<1, 64, 0, s>>>(d.ctr);
   dev::SolveArgs a{d.tasks, d.leaves, d.dense, d.low, d.tprod, dims, d.y, d.tbuf, d.leaf_flag, d.tp_flag,
                    d.ctr, d.push0, d.push_recs, d.leaf_tq, d.tg0, d.tg_list, d.pbuf, d.pflag, d.pstride, d.trace,
-                   d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch, 0};
+                   d.wait_ticks, d.ntasks, d.n_fwd, N, nrhs, d.max_rhs, d.L, epoch, 0};
   // acc 128 x 32, A staging 128 x kKC, B staging 32 x kKC, inverses 64 x 64
   const size_t sh = ((size_t)128 * 32 + 128 * dev::kKC + 32 * dev::kKC + 64 * 64) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
+  static std::once_flag attr;
+  std::call_once(attr, [sh] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::solve_persistent_kernel<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    attr = true;
-  }
+  });
   dev::solve_persistent_kernel<T><<<grid, dev::kSolveThreads, sh, s>>>(arena, static_cast<const T*>(d.inv),
                                                                        static_cast<const T*>(d.nm), a);
   return hipGetLastError();
@@ -878,22 +890,20 @@ hipError_t diag_inverse_launch(const T* arena, const SolveDev& d, hipStream_t s)
   const size_t tri = m * m * sizeof(double);
   int cols = (int)std::min<size_t>(m, (kLds - tri) / (m * sizeof(double)));
   const size_t sh = tri + m * (size_t)cols * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::diag_inverse_kernel<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
-    attr = true;
-  }
+  });
   dim3 g(d.L, 2);
   dev::diag_inverse_kernel<T><<<g, 256, sh, s>>>(arena, d.leaves, static_cast<T*>(d.inv), d.pivots, cols);
   // neighbour blocks times the inverses (96 KB of LDS)
   constexpr size_t kNmLds = (128 * 64 + 64 * 64) * sizeof(double);
-  static bool attr2 = false;
-  if (!attr2) {
+  static std::once_flag attr2;
+  std::call_once(attr2, [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::next_inverse_kernel<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmLds);
-    attr2 = true;
-  }
+  });
   dev::next_inverse_kernel<T><<<2 * d.L, 256, kNmLds, s>>>(arena, d.leaves, d.dense, static_cast<const T*>(d.inv),
                                                           static_cast<T*>(d.nm), d.L);
   return hipGetLastError();

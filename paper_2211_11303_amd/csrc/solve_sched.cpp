@@ -248,6 +248,64 @@ void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* ou
   for (int32_t q : sc.tg_list) ++seen[q];
   for (int32_t q : sc.leaf_tq) ++seen[q];
   for (int32_t c : seen) HLU_REQUIRE(c == 1, HLU_ERR_INVALID_ARG, "solve schedule: T-product not formed once");
+  check_solve_waits(sc);
+}
+
+// Every flag a task of the persistent solve waits on is set by exactly one
+// task that comes earlier in claim order.  Workgroups claim tasks in that
+// order, so the earliest unfinished task waits on finished tasks only and
+// every claimed task completes, whatever the number of resident workgroups.
+void check_solve_waits(const SolveSched& sc) {
+  const int32_t L = sc.L;
+  const int32_t nt = (int32_t)sc.tasks.size();
+  std::vector<int32_t> leaf_at(2 * L, -1), rec_at(sc.dense.size(), -1), tp_at(sc.tprod.size(), -1);
+  auto set = [&](std::vector<int32_t>& at, int32_t i, int32_t t) {
+    HLU_REQUIRE(i >= 0 && i < (int32_t)at.size() && at[i] < 0, HLU_ERR_INVALID_ARG,
+                "solve schedule: a flag is set by two tasks or out of range");
+    at[i] = t;
+  };
+  for (int32_t t = 0; t < nt; ++t) {
+    const STask& k = sc.tasks[t];
+    if (k.kind == kFwdLeaf || k.kind == kBwdLeaf) {
+      const SLeaf& lf = sc.leaves[k.idx];
+      set(leaf_at, k.idx, t);
+      if (lf.next_rec >= 0) set(rec_at, lf.next_rec, t);
+      if (lf.next_rec2 >= 0) set(rec_at, lf.next_rec2, t);
+      for (int32_t q = 0; q < lf.ntq; ++q) set(tp_at, sc.leaf_tq[lf.tq0 + q], t);
+    } else if (k.kind == kFwdPush || k.kind == kBwdPush) {
+      for (int32_t q = sc.push0[k.idx]; q < sc.push0[k.idx + 1]; ++q) set(rec_at, sc.push_recs[q], t);
+    } else {
+      for (int32_t q = sc.tg0[k.idx]; q < sc.tg0[k.idx + 1]; ++q) set(tp_at, sc.tg_list[q], t);
+    }
+  }
+  auto before = [&](const std::vector<int32_t>& at, int32_t i, int32_t t) {
+    HLU_REQUIRE(i >= 0 && i < (int32_t)at.size() && at[i] >= 0 && at[i] < t, HLU_ERR_INVALID_ARG,
+                "solve schedule: a task waits on a flag no earlier task sets");
+  };
+  for (int32_t t = 0; t < nt; ++t) {
+    const STask& k = sc.tasks[t];
+    const bool fwd = k.kind == kFwdLeaf || k.kind == kFwdPush || k.kind == kFwdTprod;
+    HLU_REQUIRE(fwd == (t < sc.n_fwd_tasks), HLU_ERR_INVALID_ARG, "solve schedule: sweeps interleaved");
+    const int32_t base = fwd ? 0 : L;
+    if (k.kind == kFwdLeaf || k.kind == kBwdLeaf) {
+      const SLeaf& lf = sc.leaves[k.idx];
+      for (int32_t d = lf.d0; d < lf.d0 + lf.nd; ++d) before(rec_at, d, t);
+      for (int32_t l = lf.l0; l < lf.l0 + lf.nl; ++l)
+        for (int32_t q = 0; q < sc.low[l].ntp; ++q) before(tp_at, sc.low[l].tp + q, t);
+    } else if (k.kind == kFwdPush || k.kind == kBwdPush) {
+      for (int32_t q = sc.push0[k.idx]; q < sc.push0[k.idx + 1]; ++q) {
+        const SDense& d = sc.dense[sc.push_recs[q]];
+        for (int32_t f = d.lf0; f < d.lf1; ++f) before(leaf_at, base + f, t);
+      }
+    } else {
+      for (int32_t q = sc.tg0[k.idx]; q < sc.tg0[k.idx + 1]; ++q) {
+        const STprod& p = sc.tprod[sc.tg_list[q]];
+        for (int32_t f = p.lf0; f < p.lf1; ++f) before(leaf_at, base + f, t);
+      }
+    }
+  }
+  // the backward leaf tasks also wait for the count of finished forward
+  // tasks, all of which come first (checked above)
 }
 
 }  // namespace hlu

@@ -96,6 +96,8 @@ struct SolveSched {
 };
 
 void build_solve_sched(const Structure& S, const StoragePlan& st, SolveSched* out);
+// Throws unless every flag a task waits on is set by one earlier task.
+void check_solve_waits(const SolveSched& sc);
 
 // Device copy of a schedule and the buffers of the persistent solve.
 struct SolveDev {
@@ -121,6 +123,7 @@ struct SolveDev {
   int32_t* pflag;
   int64_t pstride;
   int64_t* trace;
+  int64_t wait_ticks;   // longest wait of a task, in device wall-clock ticks
   int32_t ntasks, n_fwd, L, max_m, max_rhs;
 };
 

@@ -194,6 +194,11 @@ class HLU:
         L.check(L.lib().hlu_solve(self.handle, _dev_ptr(b2), _dev_ptr(x2), nrhs, self.n, _stream(stream)))
         return x
 
+    def hlu_sync_status(self, stream=None):
+        """Synchronise and raise HLU_ERR_DEVICE if a persistent solve of this
+        handle gave up waiting since the last call."""
+        L.check(L.lib().hlu_sync_status(self.handle, _stream(stream)))
+
     def hlu_apply_lu(self, v, stream=None):
         torch = _torch()
         v2, nrhs = _as_block(v, self.n)
@@ -212,6 +217,14 @@ class HLU:
         totals that hlu_get_stats reports as solve_launches / solve_kernel_ms)."""
         L.check(L.lib().hlu_set_timing(self.handle, 1 if enable else 0))
         return self
+
+    def hlu_check_trunc_rounds(self, eps, forced_rank, max_rank=0, prec="fp64"):
+        """Host replay of the truncation rounds of the factor plan with every
+        rank forced to forced_rank (no device work)."""
+        o = self._opts(eps, max_rank, prec)
+        out = (ctypes.c_int64 * 5)()
+        L.check(L.lib().hlu_check_trunc_rounds(self.handle, ctypes.byref(o), int(forced_rank), out))
+        return dict(zip(("ops", "rounds", "max_rounds", "stalled_rounds", "unfinished"), list(out)))
 
     def hlu_get_ranks(self):
         nb = self.structure_sizes()[2]
@@ -335,6 +348,9 @@ class HLUBatch:
             r0 = int(self.row_base[p])
             out.append(x[:, r0:r0 + m.n])
         return out
+
+    def hlu_batch_sync_status(self, stream=None):
+        L.check(L.lib().hlu_batch_sync_status(self.handle, _stream(stream)))
 
     def hlu_solve_batch(self, b, stream=None):
         torch = _torch()

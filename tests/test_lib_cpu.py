@@ -187,3 +187,28 @@ def test_planning_mid_size(n, leaf):
     st = h.hlu_get_stats()
     assert b32 > 0 and st["factor_waves"] > 0 and st["factor_tasks"] > st["factor_waves"]
     assert st["num_leaf_clusters"] * 2 - 1 == st["num_clusters"]
+
+
+@pytest.mark.parametrize("n,leaf", [(8, 32), (16, 64)])
+def test_truncation_rounds_terminate(n, leaf):
+    """Host replay of the truncation rounds of the factor plan (the same
+    round code as the device kernel) with every rank forced: at rank 64 a
+    block already holds a whole round's columns while parts remain (the
+    case that once looped), and every op still finishes within its bound;
+    the total rounds grow with the forced rank."""
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, 8.0)
+    H = hlu.HLU(rp, ci, va, mid, eta=2.0, leaf=leaf)
+    prev = 0
+    for forced in (0, 4, 48, 64, 200):
+        r = H.hlu_check_trunc_rounds(1e-3, forced)
+        assert r["ops"] > 0 and r["unfinished"] == 0, (forced, r)
+        assert r["rounds"] >= prev
+        prev = r["rounds"]
+        if forced >= 64:
+            assert r["stalled_rounds"] > 0, r
+        if forced <= 48:
+            assert r["stalled_rounds"] == 0, r
+    # a capacity cap below the round limit never stalls
+    r = H.hlu_check_trunc_rounds(1e-3, 200, max_rank=32)
+    assert r["unfinished"] == 0 and r["stalled_rounds"] == 0, r
