@@ -759,14 +759,14 @@ hlu_status hlu_check_trunc_rounds(hlu_handle h, const hlu_factor_opts* o, int32_
       while (true) {
         bool done = false;
         int absorbed = 0;
-        const int K = trunc_round_columns(op, pl.parts.data(), dims.data(), r, &cur, &done,
+        const int K = trunc_round_columns(op, pl.parts.data(), dims.data(), r, kTruncCols, &cur, &done,
                                           [&](int, int p, int) { absorbed += p >= 0; });
         if (K == 0) break;
         ++n;
         stalled += absorbed == 0 && !done;
         // the truncation keeps at most K columns, its eps-rank forced_rank
         // and the round's limit
-        r = std::min(std::min(forced_rank, K), trunc_rank_limit(op, done));
+        r = std::min(std::min(forced_rank, K), trunc_rank_limit(op, done, kTruncCols));
         if (done) break;
         if (n >= bound) {
           ++unfinished;

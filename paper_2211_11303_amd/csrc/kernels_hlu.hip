@@ -507,7 +507,8 @@ constexpr double kCompressTol = 0.01;   // relative pivot tolerance of that comp
 template <class T>
 __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops, const TruncPart* parts,
                                                     int32_t* dims, double eps, double floor_rel,
-                                                    int32_t* status, int64_t* trace, int32_t op_base) {
+                                                    int32_t* status, int64_t* trace, int32_t op_base,
+                                                    int round_cols) {
   __shared__ double bufG[kKMax * kLd];
   __shared__ double bufR[kKMax * kLd];
   __shared__ double bufS[kKMax * kLd];
@@ -552,7 +553,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
     if (threadIdx.x == 0) {
       TruncCursor cur{s_part, s_pcol};
       bool done = false;
-      const int K = trunc_round_columns(op, parts, dims, s_r, &cur, &done, [&](int k, int p, int c) {
+      const int K = trunc_round_columns(op, parts, dims, s_r, round_cols, &cur, &done, [&](int k, int p, int c) {
         if (p < 0) {
           xs[k] = ColSrc{op.xoff + (int64_t)c * op.ldx, 1, 0, op.m, 1.0};
           ys[k] = ColSrc{op.yoff + (int64_t)c * op.ldy, 1, 0, op.n, 1.0};
@@ -695,7 +696,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         for (int k = 0; k < r1; ++k)
           if (sqrt(mu[sel[k]]) > thr) ++cnt;
         if (s1 == 0.0) cnt = 0;
-        const int lim = trunc_rank_limit(op, s_done != 0);
+        const int lim = trunc_rank_limit(op, s_done != 0, round_cols);
         const int r = cnt < lim ? cnt : lim;
         if (cnt > lim) atomicAdd(&status[1], 1);
         s_r = r;
@@ -788,6 +789,16 @@ int64_t* trunc_trace_buffer(size_t* ops) {
   return buf;
 }
 
+// Columns of one truncation round: kTruncCols, or fewer with
+// HLU_DEBUG_TRUNC_COLS (2..64), which the tests use to force blocks to the
+// round's width while parts remain (the rank-overflow path).
+int trunc_round_cols() {
+  const char* e = getenv("HLU_DEBUG_TRUNC_COLS");
+  if (!e) return kTruncCols;
+  const int c = atoi(e);
+  return c < 2 ? 2 : (c > kTruncCols ? kTruncCols : c);
+}
+
 template <class T, class C>
 hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
                          double eps, double floor_rel, int32_t max_leaf, int32_t tile_base,
@@ -823,7 +834,8 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
     int64_t* tr = trunc_trace_buffer(nullptr);
     if (tr && w.begin[kTrunc] + w.count[kTrunc] > kTruncTraceOps) tr = nullptr;
     dev::trunc_kernel<T><<<w.count[kTrunc], 256, 0, s>>>(arena, P.trunc + w.begin[kTrunc], P.parts, dims,
-                                                          eps, floor_rel, status, tr, w.begin[kTrunc]);
+                                                          eps, floor_rel, status, tr, w.begin[kTrunc],
+                                                          trunc_round_cols());
   }
   return hipGetLastError();
 }

@@ -22,7 +22,7 @@
 namespace hlu {
 
 constexpr int kTruncCols = 64;        // columns of one round (LDS capacity)
-constexpr int kTruncMinAbsorb = 16;   // part columns a round absorbs while parts remain
+constexpr int kTruncMinAbsorb = 1;    // part columns a round absorbs while parts remain
 
 __host__ __device__ inline int dim_of(int32_t code, const int32_t* dims) {
   return code >= 0 ? code : dims[-code - 1];
@@ -34,19 +34,20 @@ struct TruncCursor {
 };
 
 // Column list of the next round: the r current columns of C, then part
-// columns from the cursor until kTruncCols columns or the parts run out.
+// columns from the cursor until `cols` (<= kTruncCols, normally equal)
+// columns or the parts run out.
 // emit(k, p, c) receives stack position k and its source: p = -1 for column
 // c of C, else column c of part p.  Advances the cursor past the absorbed
 // columns (and past parts of rank 0), sets *done when no part column is
 // left, returns the number of columns K.
 template <class Emit>
 __host__ __device__ inline int trunc_round_columns(const TruncOp& op, const TruncPart* parts,
-                                                   const int32_t* dims, int r, TruncCursor* cur,
+                                                   const int32_t* dims, int r, int cols, TruncCursor* cur,
                                                    bool* done, Emit&& emit) {
   int K = 0;
   for (int a = 0; a < r; ++a) emit(K++, -1, a);
   int p = cur->part, c = cur->col;
-  while (p < op.np && K < kTruncCols) {
+  while (p < op.np && K < cols) {
     if (c >= dim_of(parts[op.p0 + p].X.cols, dims)) {
       ++p;
       c = 0;
@@ -65,16 +66,16 @@ __host__ __device__ inline int trunc_round_columns(const TruncOp& op, const Trun
   return K;
 }
 
-// Largest rank a round may keep: the block's capacity in the last round,
-// otherwise at most kTruncCols - kTruncMinAbsorb.
-__host__ __device__ inline int trunc_rank_limit(const TruncOp& op, bool done) {
-  const int lim = kTruncCols - kTruncMinAbsorb;
+// Largest rank a round of `cols` columns may keep: the block's capacity in
+// the last round, otherwise at most cols - kTruncMinAbsorb.
+__host__ __device__ inline int trunc_rank_limit(const TruncOp& op, bool done, int cols) {
+  const int lim = cols - kTruncMinAbsorb;
   return done ? op.cap : (op.cap < lim ? op.cap : lim);
 }
 
 // Bound on the rounds of an op: the first round may absorb nothing (C
-// already at kTruncCols columns), every later round but the last absorbs at
-// least kTruncMinAbsorb part columns.
+// already at the round's columns), every later round but the last absorbs
+// at least kTruncMinAbsorb part columns.
 __host__ __device__ inline int trunc_max_rounds(const TruncOp& op, const TruncPart* parts, const int32_t* dims) {
   int64_t cols = 0;
   for (int p = 0; p < op.np; ++p) cols += dim_of(parts[op.p0 + p].X.cols, dims);

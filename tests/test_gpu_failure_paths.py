@@ -1,9 +1,9 @@
 """GPU tests of the device-side failure paths, each forced from the host so
 that every kernel still exits normally.
 
-* A truncation whose eps-rank reaches the block's 64-column capacity while
-  parts remain (16^3, leaf 64, kappa 30 = the paper's kappa 900, eps 1e-3:
-  the oracle's ranks reach 73) ends with HLU_ERR_RANK_OVERFLOW.
+* A truncation whose kept rank fills a whole round while parts remain
+  (forced by narrowing the rounds with HLU_DEBUG_TRUNC_COLS) ends with
+  HLU_ERR_RANK_OVERFLOW; the paper's k = 5, kappa 900 factor finishes.
 * A persistent solve whose waits are given a zero time limit (the
   HLU_DEBUG_SOLVE_WAIT_US switch) reports HLU_ERR_DEVICE through
   hlu_sync_status and gmres_solve, and the next solve with the normal limit
@@ -26,23 +26,46 @@ def _lib():
 
 
 def test_rank_overflow_is_reported(gpu):
+    """Rounds narrowed to 16 columns (HLU_DEBUG_TRUNC_COLS): blocks of
+    eps-rank above 15 fill a round while parts remain, the situation in which
+    a round once absorbed nothing and the kernel looped.  The factor must
+    return HLU_ERR_RANK_OVERFLOW at once; with full rounds it succeeds."""
+    L, hlu, _ = _lib()
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(8, 8.0)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, 32)
+    print("case: 8^3 leaf 32 kappa 8 eps 1e-4 fp64, 16-column truncation rounds", flush=True)
+    os.environ["HLU_DEBUG_TRUNC_COLS"] = "16"
+    try:
+        t = time.time()
+        with pytest.raises(L.HluError) as e:
+            H.hlu_factor(1e-4, prec="fp64")
+        assert e.value.status == L.STATUS_CODES["HLU_ERR_RANK_OVERFLOW"]
+        assert time.time() - t < 60.0
+        st = H.hlu_get_stats()
+        assert st["capped_blocks"] > 0 and st["max_rank"] <= 16, st
+    finally:
+        del os.environ["HLU_DEBUG_TRUNC_COLS"]
+    H.hlu_factor(1e-4, prec="fp64")
+    st = H.hlu_get_stats()
+    assert st["capped_blocks"] == 0 and st["max_rank"] > 16, st
+
+
+def test_paper_k5_kappa900_factor_finishes(gpu):
+    """Table 1, k = 5, kappa_paper = 900 (16^3, kappa 30, eps 1e-3, leaf 64):
+    the factor whose truncation once looped finishes promptly, either within
+    capacity or with HLU_ERR_RANK_OVERFLOW (the oracle's ranks reach 73)."""
+    import torch
     L, hlu, _ = _lib()
     print("case: 16^3 leaf 64 kappa 30 eps 1e-3 fp64", flush=True)
     rp, ci, va, mid = hlu.hlu_kuhn_assemble(16, 30.0)
     H = hlu.HLU(rp, ci, va, mid, 2.0, 64)
     t = time.time()
-    with pytest.raises(L.HluError) as e:
-        H.hlu_factor(1e-3, prec="fp64")
-    assert e.value.status == L.STATUS_CODES["HLU_ERR_RANK_OVERFLOW"]
+    H.hlu_factor(1e-3, prec="fp64", allow_overflow=True)
     assert time.time() - t < 60.0
     st = H.hlu_get_stats()
-    assert st["capped_blocks"] > 0 and st["max_rank"] <= 64, st
-    # the factor is kept at capacity and usable
-    H2 = H.hlu_factor(1e-3, prec="fp64", allow_overflow=True)
-    import torch
-    b = torch.ones((1, H.n), dtype=torch.float64, device="cuda")
-    x = H2.hlu_solve(b)
-    torch.cuda.synchronize()
+    assert st["max_rank"] <= 64, st
+    x = H.hlu_solve(torch.ones((1, H.n), dtype=torch.float64, device="cuda"))
+    H.hlu_sync_status()
     assert torch.isfinite(x).all()
 
 
@@ -85,7 +108,10 @@ def test_factor_and_solve_are_deterministic(gpu):
     for prec in ("fp64", "fp32"):
         out = []
         for _ in range(2):
-            H = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(1e-4, prec=prec)
+            H = hlu.HLU(rp, ci, va, mid, 2.0, leaf)
+            H.hlu_bind_workspace(H.hlu_workspace_bytes(1e-4, prec=prec))
+            H.work.zero_()   # temporaries never written keep these zeros
+            H.hlu_factor(1e-4, prec=prec)
             arena = H.work.clone()
             x1 = H.hlu_solve(X).clone()
             x2 = H.hlu_solve(X).clone()
