@@ -225,6 +225,23 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
                        hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info,
                        void* d_work, size_t work_bytes, void* stream);
 
+/* gmres_solve without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, semantics and results
+ * as gmres_solve; the Krylov workspace is a static device array of
+ * gmres_static_max_bytes() bytes (64 MiB), one per GPU, held from the first
+ * call on that GPU until the process ends.  Calls no hipMalloc / hipFree:
+ * HLU_ERR_OUT_OF_MEMORY if gmres_workspace_bytes(n, nrhs, restart) exceeds
+ * that size; HLU_ERR_STATE if precond's solve buffers have not been made
+ * yet (one hlu_solve or gmres_solve on it makes them) or its solve timing
+ * is on.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (several streams or threads) race and must be serialised by
+ * the caller. */
+size_t gmres_static_max_bytes(void);
+hlu_status gmres_solve_static(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                              hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info,
+                              void* stream);
+
 /* ------------------------------------------------------------------ batch
  * Independent problems (each an hlu_handle, of any size) factored and solved
  * together: every launch of the batch factorisation runs the ready tasks of

@@ -91,6 +91,9 @@ SIGNATURES = {
     "gmres_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
                               ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), c_void_p, c_size_t,
                               c_void_p]),
+    "gmres_static_max_bytes": (c_size_t, []),
+    "gmres_solve_static": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
+                                     ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), c_void_p]),
     "hlu_structure_sizes": (c_int32, [c_void_p, P_i32, P_i32, P_i32]),
     "hlu_export_structure": (c_int32, [c_void_p, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32,
                                        P_i32]),

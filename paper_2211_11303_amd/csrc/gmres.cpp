@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -188,18 +190,14 @@ void check_gmres_opts(const hlu_gmres_opts* o) {
 
 using namespace hlu;
 
-extern "C" {
+namespace hlu {
+namespace {
 
-size_t gmres_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart) {
-  if (n <= 0 || nrhs <= 0 || restart <= 0) return 0;
-  const int64_t total = (int64_t)n * nrhs;
-  // + the right-hand side and the iterate, contiguous
-  return gmres_core_bytes(total, nrhs, restart) + 2 * align256((size_t)total * sizeof(double));
-}
-
-hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, hlu_handle precond,
-                       const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work, size_t work_bytes,
-                       void* stream) {
+// gmres_solve on a given workspace.  may_allocate = false: fail instead of
+// making the preconditioner's solve buffers (the allocation-free entry).
+hlu_status gmres_solve_on(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, hlu_handle precond,
+                          const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work, size_t work_bytes,
+                          hipStream_t s, bool may_allocate) {
   bool all_conv = true;
   hlu_status st = guard([&] {
     HLU_REQUIRE(A && d_b && d_x && o && info && d_work && nrhs >= 1 && ld >= A->n, HLU_ERR_INVALID_ARG,
@@ -209,12 +207,17 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
     if (precond) {
       HLU_REQUIRE(precond->factored, HLU_ERR_STATE, "gmres_solve: preconditioner not factored");
       HLU_REQUIRE(precond->sh->S.N == A->n, HLU_ERR_INVALID_ARG, "gmres_solve: size mismatch");
+      if (!may_allocate) {
+        HLU_REQUIRE(precond->sbuf != nullptr, HLU_ERR_STATE,
+                    "gmres_solve_static: the preconditioner's solve buffers are not made yet (one hlu_solve makes "
+                    "them)");
+        HLU_REQUIRE(!precond->timing, HLU_ERR_STATE, "gmres_solve_static: solve timing creates events; disable it");
+      }
     }
     const int32_t N = A->n;
     const int64_t total = (int64_t)N * nrhs;
     HLU_REQUIRE(work_bytes >= gmres_workspace_bytes(N, nrhs, o->restart), HLU_ERR_OUT_OF_MEMORY,
                 "gmres_solve: workspace too small");
-    hipStream_t s = (hipStream_t)stream;
     char* wp = static_cast<char*>(d_work);
     double* bb = reinterpret_cast<double*>(wp);
     wp += align256((size_t)total * sizeof(double));
@@ -240,7 +243,7 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
       }
     };
     if (precond) {
-      ensure_solve_bufs(precond);   // made by the first solve otherwise
+      ensure_solve_bufs(precond);   // made by the first solve otherwise (checked above when not allowed)
       sys.d_err = precond->sbuf->ctr + 3;
     }
     gmres_core(sys, bb, xx, o, wp, info, s);
@@ -255,6 +258,64 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
     return HLU_ERR_NOT_CONVERGED;
   }
   return HLU_OK;
+}
+
+// Workspace of gmres_solve_static: a file-scope device array, one copy per
+// GPU, located once per device with hipGetSymbolAddress.  In host code the
+// array's name is not a device address; only the located pointers are used.
+constexpr size_t kStaticGmresBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticGmresBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device ordinal -> address of its copy of `scratch`
+
+void* static_scratch() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  HIP_OK(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+  HLU_REQUIRE(ptr != nullptr, HLU_ERR_DEVICE, "gmres_solve_static: no address for the static workspace");
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+
+}  // namespace
+}  // namespace hlu
+
+extern "C" {
+
+size_t gmres_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart) {
+  if (n <= 0 || nrhs <= 0 || restart <= 0) return 0;
+  const int64_t total = (int64_t)n * nrhs;
+  // + the right-hand side and the iterate, contiguous
+  return gmres_core_bytes(total, nrhs, restart) + 2 * align256((size_t)total * sizeof(double));
+}
+
+hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, hlu_handle precond,
+                       const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work, size_t work_bytes,
+                       void* stream) {
+  return gmres_solve_on(A, d_b, d_x, nrhs, ld, precond, o, info, d_work, work_bytes, (hipStream_t)stream, true);
+}
+
+size_t gmres_static_max_bytes(void) { return kStaticGmresBytes; }
+
+hlu_status gmres_solve_static(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                              hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info, void* stream) {
+  void* work = nullptr;
+  hlu_status st = guard([&] {
+    HLU_REQUIRE(A && o && nrhs >= 1 && o->restart >= 1, HLU_ERR_INVALID_ARG, "gmres_solve_static: bad arguments");
+    const size_t need = gmres_workspace_bytes(A->n, nrhs, o->restart);
+    HLU_REQUIRE(need <= kStaticGmresBytes, HLU_ERR_OUT_OF_MEMORY,
+                "gmres_solve_static: the Krylov workspace (" + std::to_string(need) +
+                    " bytes) exceeds the static workspace (" + std::to_string(kStaticGmresBytes) + " bytes)");
+    work = static_scratch();
+  });
+  if (st != HLU_OK) return st;
+  return gmres_solve_on(A, d_b, d_x, nrhs, ld, precond, o, info, work, kStaticGmresBytes, (hipStream_t)stream,
+                        false);
 }
 
 }  // extern "C"

@@ -274,6 +274,27 @@ def gmres_solve(A, b, precond=None, restart=50, tol=1e-8, max_iters=1000, stream
     return x.reshape(b.shape), infos
 
 
+def gmres_solve_static(A, b, precond=None, restart=50, tol=1e-8, max_iters=1000, stream=None,
+                       raise_on_fail=True):
+    """gmres_solve on the library's static device workspace (no device
+    allocation inside the call; x is the caller's output tensor)."""
+    torch = _torch()
+    b2, nrhs = _as_block(b, A.n)
+    x = torch.zeros_like(b2)
+    o = L.GmresOpts(int(restart), int(max_iters), float(tol))
+    info = (L.GmresInfo * nrhs)()
+    st = L.lib().gmres_solve_static(A.handle, _dev_ptr(b2), _dev_ptr(x), nrhs, A.n,
+                                    precond.handle if precond is not None else None, ctypes.byref(o), info,
+                                    _stream(stream))
+    infos = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, abs_res=i.abs_res) for i in info]
+    _check_gmres(st, raise_on_fail)
+    return x.reshape(b.shape), infos
+
+
+def gmres_static_max_bytes():
+    return L.lib().gmres_static_max_bytes()
+
+
 def _check_gmres(st, raise_on_fail):
     if st != L.HLU_OK and (raise_on_fail or st != -5):
         L.check(st)
