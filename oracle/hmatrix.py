@@ -421,10 +421,27 @@ class HLU:
         """L U V in cluster order."""
         return apply_L(self.H.root, apply_U(self.H.root, V))
 
-    def factor_error(self, nprobe=8, seed=12345):
+    def factor_error(self, nprobe=8, seed=12345, storage=np.float64):
         """|| (L U - P A P^T) Omega ||_F / || P A P^T Omega ||_F, Omega standard
-        normal N x nprobe from numpy's default_rng(seed)."""
+        normal N x nprobe from numpy's default_rng(seed).
+
+        storage: every stored entry of the factors (dense leaves, low-rank
+        factors) is first rounded to this type; np.float32 gives the error of
+        the computed factors once stored in FP32 (the FP32 precision pattern
+        stores the H-LU in FP32; the paper has no FP32 mode).  The factors
+        themselves are left unchanged."""
         Om = np.random.default_rng(seed).standard_normal((self.H.N, nprobe))
         Ap = self.A[self.perm][:, self.perm]
         ref = Ap @ Om
-        return float(np.linalg.norm(self.apply_LU(Om) - ref) / np.linalg.norm(ref))
+        saved = []
+        if storage is not np.float64:
+            for b in self.H.root.leaves():
+                saved.append((b, b.D, b.X, b.Y))
+                b.D = None if b.D is None else b.D.astype(storage).astype(np.float64)
+                b.X = None if b.X is None else b.X.astype(storage).astype(np.float64)
+                b.Y = None if b.Y is None else b.Y.astype(storage).astype(np.float64)
+        try:
+            return float(np.linalg.norm(self.apply_LU(Om) - ref) / np.linalg.norm(ref))
+        finally:
+            for b, D, X, Y in saved:
+                b.D, b.X, b.Y = D, X, Y

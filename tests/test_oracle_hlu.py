@@ -117,3 +117,27 @@ def test_zero_pivot_detected():
     D = np.array([[0.0, 1.0], [1.0, 0.0]])
     with pytest.raises(hmatrix.ZeroPivot):
         hmatrix.getrf_nopiv(D)
+
+
+@pytest.mark.parametrize("n,leaf,rtol", [(4, 32, 1e-3), (4, 8, 0.5)])
+def test_fp32_storage_error_matches_dense(n, leaf, rtol):
+    """factor_error(storage=float32) of the untruncated H-LU against the same
+    probe error of the textbook dense LU of P A P^T with L and U rounded to
+    FP32 (the exact factors are the dense LU, so only the rounding differs):
+    equal where the factors are stored densely (leaf 32 at 4^3); where many
+    blocks are stored as X Y^T (leaf 8), X and Y are rounded instead of
+    their product, the same order of error.  storage=float64 leaves the
+    error unchanged."""
+    d, s = _problem(n, leaf, 2.0)
+    h = HLU(s, d.A, 0.0).factor()
+    Ap = d.A.toarray()[np.ix_(s.perm, s.perm)]
+    L, U = _dense_lu_nopiv(Ap)
+    Om = np.random.default_rng(12345).standard_normal((len(Ap), 8))
+    L32 = L.astype(np.float32).astype(float)
+    U32 = U.astype(np.float32).astype(float)
+    ref = Ap @ Om
+    e_dense32 = np.linalg.norm(L32 @ (U32 @ Om) - ref) / np.linalg.norm(ref)
+    e32 = h.factor_error(storage=np.float32)
+    assert abs(e32 - e_dense32) <= rtol * e_dense32, (e32, e_dense32)
+    assert 1e-9 < e32 < 1e-5
+    assert h.factor_error() == h.factor_error(storage=np.float64) < 1e-12
