@@ -86,8 +86,8 @@ def parse():
 # measured on (profiles/solve_persistent_32cube_fp32_hbm_traffic.md).
 SOLVE_TRAFFIC = {"sha256": "534f9e253cfc708889edf8ab40b28b350909119adbc7c093d37f2531115b440b", "columns": 24,
                  "bytes_per_launch": 7351435015}
-SOLVE_SOURCES = ("paper_2211_11303_amd/csrc/kernels_solve.hip", "paper_2211_11303_amd/csrc/solve_sched.cpp",
-                 "paper_2211_11303_amd/csrc/solve_sched.h")
+SOLVE_SOURCES = ("paper_2211_11303_amd/csrc/kernels_chain.hip", "paper_2211_11303_amd/csrc/chain_sched.cpp",
+                 "paper_2211_11303_amd/csrc/chain_sched.h")
 
 
 def solve_sources_sha256():

@@ -12,10 +12,10 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhlu.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mesh.cpp", "structure.cpp", "plan.cpp", "solve_sched.cpp", "api.cpp", "gmres.cpp", "batch.cpp",
+SOURCES = ["mesh.cpp", "structure.cpp", "plan.cpp", "chain_sched.cpp", "api.cpp", "gmres.cpp", "batch.cpp",
            "server.cpp", "autotune.cpp",
            "kernels_hlu.hip",
-           "kernels_vec.hip", "kernels_solve.hip"]
+           "kernels_vec.hip", "kernels_chain.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

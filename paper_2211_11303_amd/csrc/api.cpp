@@ -57,7 +57,7 @@ std::shared_ptr<PlanBundle> get_bundle(Shared& sh, int32_t kcap) {
   auto pb = std::make_shared<PlanBundle>();
   pb->kcap = kcap;
   build_plans(sh.S, kcap, kMaxRhs, sh.nonzero_admissible, &pb->ps);
-  build_solve_sched(sh.S, pb->ps.store, &pb->sc);
+  build_chain_sched(sh.S, pb->ps.store, &pb->sc);
   sh.bundles[kcap] = pb;
   return pb;
 }
@@ -74,33 +74,37 @@ void ensure_device(Shared& sh, PlanBundle& pb) {
   pb.on_device = true;
 }
 
-void SolveBufs::alloc(const SolveSched& sc, int32_t N, int32_t rhs) {
+void SolveBufs::alloc(const ChainSched& sc, int32_t N, int32_t rhs) {
   max_rhs = rhs;
   inv = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.inv_elems)));   // sized for FP64
-  nm = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.nm_elems)));
+  stack = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.stack_elems)));
   pivots = mem.keep(dmalloc<double>((size_t)N));
   y = mem.keep(dmalloc<double>((size_t)N * rhs));
   tbuf = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs));
-  const size_t nflags = 2 * (size_t)sc.L + sc.tprod.size() + sc.dense.size() + 1;
+  rstride = (int64_t)sc.max_m * rhs;
+  fbuf = mem.keep(dmalloc<double>((size_t)std::max(1, sc.num_recs) * (size_t)rstride));
+  const size_t nflags = sc.tprod.size() + (size_t)sc.num_recs + 1;
   flags = mem.keep(dmalloc<int32_t>(nflags));
   HIP_OK(hipMemset(flags, 0, nflags * sizeof(int32_t)));
-  pstride = (int64_t)sc.max_m * rhs;
-  pbuf = mem.keep(dmalloc<double>(std::max<size_t>(1, sc.dense.size()) * (size_t)pstride));
+  prog = mem.keep(dmalloc<int32_t>(2 * kMaxChains));
+  HIP_OK(hipMemset(prog, 0, 2 * kMaxChains * sizeof(int32_t)));
   ctr = mem.keep(dmalloc<int32_t>(kSolveCtrWords));
   HIP_OK(hipMemset(ctr, 0, kSolveCtrWords * sizeof(int32_t)));
-  if (getenv("HLU_DEBUG_SOLVE_TRACE")) trace = mem.keep(dmalloc<int64_t>(12 * std::max<size_t>(1, sc.tasks.size())));
+  if (getenv("HLU_DEBUG_SOLVE_TRACE"))
+    trace = mem.keep(dmalloc<int64_t>(10 * (size_t)std::max(1, sc.L) + 6 * (size_t)std::max(1, sc.num_recs)));
+  kargs = mem.keep(dmalloc<unsigned char>(kChainArgBytes));
   epoch = 0;
 }
 
-size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t rhs) {
+size_t solve_buffer_bytes(const ChainSched& sc, int32_t N, int32_t rhs) {
   size_t b = 0;
   b += (size_t)std::max<int64_t>(1, sc.inv_elems) * sizeof(double);
-  b += (size_t)std::max<int64_t>(1, sc.nm_elems) * sizeof(double);
+  b += (size_t)std::max<int64_t>(1, sc.stack_elems) * sizeof(double);
   b += (size_t)N * sizeof(double) * (1 + rhs);
   b += (size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs * sizeof(double);
-  b += (2 * (size_t)sc.L + sc.tprod.size() + sc.dense.size() + 1) * sizeof(int32_t);
-  b += std::max<size_t>(1, sc.dense.size()) * (size_t)sc.max_m * rhs * sizeof(double);
-  return b + kSolveCtrWords * sizeof(int32_t);
+  b += (size_t)std::max(1, sc.num_recs) * sc.max_m * rhs * sizeof(double);
+  b += (sc.tprod.size() + (size_t)sc.num_recs + 1 + 2 * kMaxChains) * sizeof(int32_t);
+  return b + kSolveCtrWords * sizeof(int32_t) + kChainArgBytes;
 }
 
 int64_t solve_wait_ticks() {
@@ -127,34 +131,37 @@ bool take_solve_error(int32_t* ctr, hipStream_t s) {
   return true;
 }
 
-SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs& b) {
-  SolveDev v{};
-  v.tasks = d.tasks;
+ChainDev make_chain_dev(const ChainSched& sc, const DevSched& d, const SolveBufs& b) {
+  ChainDev v{};
   v.leaves = d.leaves;
-  v.dense = d.dense;
-  v.low = d.low;
+  v.tgt = d.tgt;
+  v.gdense = d.gdense;
+  v.glow = d.glow;
+  v.ginl = d.ginl;
+  v.gathers = d.gathers;
   v.tprod = d.tprod;
-  v.push0 = d.push0;
-  v.push_recs = d.push_recs;
-  v.leaf_tq = d.leaf_tq;
   v.tg0 = d.tg0;
   v.tg_list = d.tg_list;
+  v.tasks = d.tasks;
+  v.member_L = d.member_L;
+  v.member_pos0 = d.member_pos0;
+  v.stack = b.stack;
   v.inv = b.inv;
-  v.nm = b.nm;
   v.pivots = b.pivots;
   v.y = b.y;
   v.tbuf = b.tbuf;
-  v.leaf_flag = b.flags;
-  v.tp_flag = b.flags + 2 * sc.L;
-  v.pflag = b.flags + 2 * sc.L + sc.tprod.size();
+  v.fbuf = b.fbuf;
+  v.tp_flag = b.flags;
+  v.g_flag = b.flags + sc.tprod.size();
+  v.prog = b.prog;
   v.ctr = b.ctr;
-  v.pbuf = b.pbuf;
-  v.pstride = b.pstride;
+  v.rstride = b.rstride;
   v.trace = b.trace;
+  v.kargs = b.kargs;
   v.wait_ticks = solve_wait_ticks();
   v.ntasks = (int32_t)sc.tasks.size();
-  v.n_fwd = sc.n_fwd_tasks;
   v.L = sc.L;
+  v.members = sc.members;
   v.max_m = sc.max_m;
   v.max_rhs = b.max_rhs;
   return v;
@@ -316,8 +323,8 @@ template <class T>
 void ensure_inverses(hlu_s* h, hipStream_t s) {
   ensure_solve_bufs(h);
   if (h->inv_ready) return;
-  const SolveDev d = make_solve_dev(h->pb->sc, h->pb->dsc, *h->sbuf);
-  HIP_OK(diag_inverse_launch<T>(static_cast<const T*>(h->arena), d, s));
+  const ChainDev d = make_chain_dev(h->pb->sc, h->pb->dsc, *h->sbuf);
+  HIP_OK(chain_prepare_launch<T>(static_cast<const T*>(h->arena), h->dims, d, d.L, s));
   h->inv_ready = true;
 }
 
@@ -353,11 +360,10 @@ template <class T>
 void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, int64_t ld, hipStream_t s) {
   ensure_inverses<T>(h, s);
   SolveBufs& sb = *h->sbuf;
-  const SolveSched& sc = h->pb->sc;
-  const SolveDev d = make_solve_dev(sc, h->pb->dsc, sb);
+  const ChainSched& sc = h->pb->sc;
+  const ChainDev d = make_chain_dev(sc, h->pb->dsc, sb);
   const T* arena = static_cast<const T*>(h->arena);
   const int32_t N = h->sh->S.N;
-  const int grid = std::max(1, std::min<int>(d.ntasks, 256));   // one 144 KB-LDS workgroup per CU
   for (int32_t c0 = 0; c0 < nrhs; c0 += kMaxRhs) {
     const int32_t nc = std::min(kMaxRhs, nrhs - c0);
     HIP_OK(gather_launch<double>(N, nc, h->sh->d_perm, b + (int64_t)c0 * ld, ld, sb.y, N, s));
@@ -371,22 +377,20 @@ void solve_persistent_impl(hlu_s* h, const double* b, double* x, int32_t nrhs, i
       }
       HIP_OK(hipEventRecord(h->tev[h->tev_used], s));
     }
-    HIP_OK(solve_persistent_launch<T>(arena, h->dims, d, N, nc, sb.epoch, grid, s));
+    if (sb.trace) HIP_OK(hipMemsetAsync(sb.trace, 0, 10 * (size_t)sc.L * sizeof(int64_t), s));   // debug
+    HIP_OK(chain_solve_launch<T>(arena, h->dims, d, N, nc, sb.epoch, s));
     if (h->timing) {
       HIP_OK(hipEventRecord(h->tev[h->tev_used + 1], s));
       h->tev_used += 2;
       h->stats.solve_columns += nc;
     }
     HIP_OK(scatter_perm_launch<double>(N, nc, h->sh->d_perm, sb.y, N, x + (int64_t)c0 * ld, ld, s));
-    if (sb.trace) {   // debug: dump task clocks and kinds
+    if (sb.trace) {   // debug: the chain's clocks of this launch
       HIP_OK(hipStreamSynchronize(s));
-      std::vector<int64_t> tr(12 * (size_t)d.ntasks);
+      std::vector<int64_t> tr(10 * (size_t)sc.L + 6 * (size_t)sc.num_recs);
       HIP_OK(hipMemcpy(tr.data(), sb.trace, tr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
       if (FILE* f = fopen(getenv("HLU_DEBUG_SOLVE_TRACE"), "wb")) {
-        for (int32_t t = 0; t < d.ntasks; ++t) {
-          fwrite(&sc.tasks[t], sizeof(STask), 1, f);   // kind, idx (int32 each)
-          fwrite(tr.data() + 12 * t, 12 * sizeof(int64_t), 1, f);
-        }
+        fwrite(tr.data(), sizeof(int64_t), tr.size(), f);
         fclose(f);
       }
     }

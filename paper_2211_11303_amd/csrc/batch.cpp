@@ -9,10 +9,10 @@
 // recompression tasks of all problems that are ready at that depth.  The
 // batch needs as many waves as its deepest problem, not their sum.
 //
-// The persistent solve is merged the same way: the problems' task lists are
-// interleaved (each problem's own order is kept, so every wait still points
-// to an earlier task), vectors of all problems are stacked into one block,
-// and a single launch runs all forward sweeps, then all backward sweeps.
+// The persistent solve is merged the same way: every problem keeps its own
+// chains, the problems' helper tasks are interleaved (each problem's own
+// order is kept, so every wait still points backwards), vectors of all
+// problems are stacked into one block, and a single launch runs all sweeps.
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -35,7 +35,7 @@ struct hlu_batch_s {
   // merged factor plan and solve schedule
   hlu::Plan plan;
   hlu::DevArrays dplan;
-  hlu::SolveSched sc;
+  hlu::ChainSched sc;
   hlu::DevSched dsc;
   hlu::SolveBufs bufs;
   hlu::Owned mem;
@@ -165,115 +165,6 @@ void merge_plans(const std::vector<const Plan*>& P, const std::vector<int64_t>& 
   }
 }
 
-// Union of the problems' solve schedules (see the file comment).
-void merge_scheds(const std::vector<const SolveSched*>& S, const std::vector<int64_t>& a,
-                  const std::vector<int32_t>& d, const std::vector<int32_t>& o, SolveSched* out) {
-  SolveSched& M = *out;
-  const size_t np = S.size();
-  std::vector<int32_t> LB(np), DB(np), LWB(np), TPB(np), PB(np), PRB(np), TQB(np), TGB(np), TGLB(np);
-  std::vector<int64_t> TOFF(np), INVB(np), NMB(np);
-  int32_t Ltot = 0;
-  for (size_t p = 0; p < np; ++p) {
-    const SolveSched& s = *S[p];
-    LB[p] = Ltot;
-    DB[p] = (int32_t)M.dense.size();
-    LWB[p] = (int32_t)M.low.size();
-    TPB[p] = (int32_t)M.tprod.size();
-    PB[p] = p ? PB[p - 1] + (int32_t)S[p - 1]->push0.size() - 1 : 0;
-    PRB[p] = (int32_t)M.push_recs.size();
-    TGB[p] = p ? TGB[p - 1] + (int32_t)S[p - 1]->tg0.size() - 1 : 0;
-    TGLB[p] = (int32_t)M.tg_list.size();
-    TOFF[p] = M.tbuf_per_rhs;
-    INVB[p] = M.inv_elems;
-    NMB[p] = M.nm_elems;
-    Ltot += s.L;
-    for (SDense r : s.dense) {
-      r.off += a[p];
-      r.col0 += o[p];
-      r.row0 += o[p];
-      r.lf0 += LB[p];
-      r.lf1 += LB[p];
-      M.dense.push_back(r);
-    }
-    for (SLow r : s.low) {
-      r.xoff += a[p];
-      r.tp += TPB[p];
-      M.low.push_back(r);
-    }
-    for (STprod r : s.tprod) {
-      r.yoff += a[p];
-      r.toff += TOFF[p];
-      r.col0 += o[p];
-      r.slot += d[p];
-      r.lf0 += LB[p];
-      r.lf1 += LB[p];
-      M.tprod.push_back(r);
-    }
-    for (size_t i = 0; i + 1 < s.push0.size(); ++i) M.push0.push_back(s.push0[i] + PRB[p]);
-    for (int32_t r : s.push_recs) M.push_recs.push_back(r + DB[p]);
-    for (size_t i = 0; i + 1 < s.tg0.size(); ++i) M.tg0.push_back(s.tg0[i] + TGLB[p]);
-    for (int32_t q : s.tg_list) M.tg_list.push_back(q + TPB[p]);
-    TQB[p] = (int32_t)M.leaf_tq.size();
-    for (int32_t q : s.leaf_tq) M.leaf_tq.push_back(q + TPB[p]);
-    M.tbuf_per_rhs += s.tbuf_per_rhs;
-    M.inv_elems += s.inv_elems;
-    M.nm_elems += s.nm_elems;
-    M.max_m = std::max(M.max_m, s.max_m);
-  }
-  M.push0.push_back((int32_t)M.push_recs.size());
-  M.tg0.push_back((int32_t)M.tg_list.size());
-  M.L = Ltot;
-  M.leaves.resize(2 * (size_t)Ltot);
-  for (size_t p = 0; p < np; ++p) {
-    const SolveSched& s = *S[p];
-    for (int32_t q = 0; q < 2 * s.L; ++q) {
-      SLeaf lf = s.leaves[q];
-      lf.row0 += o[p];
-      lf.diag += a[p];
-      lf.inv += INVB[p];
-      lf.d0 += DB[p];
-      lf.l0 += LWB[p];
-      if (lf.next_rec >= 0) lf.next_rec += DB[p];
-      if (lf.next_rec2 >= 0) lf.next_rec2 += DB[p];
-      if (lf.prev_rec >= 0) lf.prev_rec += DB[p];
-      lf.tq0 += TQB[p];
-      if (lf.nm >= 0) lf.nm += NMB[p];
-      const int32_t dst = q < s.L ? LB[p] + q : Ltot + LB[p] + (q - s.L);
-      M.leaves[dst] = lf;
-    }
-  }
-  auto remap = [&](size_t p, STask t) {
-    const SolveSched& s = *S[p];
-    switch (t.kind) {
-      case kFwdLeaf: t.idx += LB[p]; break;
-      case kBwdLeaf: t.idx = Ltot + LB[p] + (t.idx - s.L); break;
-      case kFwdTprod:
-      case kBwdTprod: t.idx += TGB[p]; break;
-      default: t.idx += PB[p]; break;   // push tasks
-    }
-    return t;
-  };
-  // interleave: every problem advances in proportion to its own length
-  for (int sweep = 0; sweep < 2; ++sweep) {
-    struct Key {
-      double pos;
-      int32_t p, i;
-    };
-    std::vector<Key> keys;
-    for (size_t p = 0; p < np; ++p) {
-      const SolveSched& s = *S[p];
-      const int32_t b = sweep ? s.n_fwd_tasks : 0;
-      const int32_t e = sweep ? (int32_t)s.tasks.size() : s.n_fwd_tasks;
-      for (int32_t i = b; i < e; ++i) keys.push_back({(i - b + 0.5) / (double)(e - b), (int32_t)p, i});
-    }
-    std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
-      return x.pos < y.pos || (x.pos == y.pos && x.p < y.p);
-    });
-    for (const Key& k : keys) M.tasks.push_back(remap(k.p, S[k.p]->tasks[k.i]));
-    if (sweep == 0) M.n_fwd_tasks = (int32_t)M.tasks.size();
-  }
-}
-
 hlu_batch_s* checked(hlu_batch_s* b, bool need_bound) {
   HLU_REQUIRE(b, HLU_ERR_INVALID_ARG, "NULL batch");
   for (hlu_s* h : b->hs) HLU_REQUIRE(h, HLU_ERR_STATE, "a member handle of the batch was destroyed");
@@ -296,8 +187,8 @@ void factor_batch_impl(hlu_batch_s* b, hipStream_t s) {
                           b->max_leaf, tile_base, compute64, s));
     tile_base += w.gemm_tiles;
   }
-  const SolveDev d = make_solve_dev(b->sc, b->dsc, b->bufs);
-  HIP_OK(diag_inverse_launch<T>(reinterpret_cast<const T*>(base), d, s));
+  const ChainDev d = make_chain_dev(b->sc, b->dsc, b->bufs);
+  HIP_OK(chain_prepare_launch<T>(reinterpret_cast<const T*>(base), dims, d, d.L, s));
 }
 
 template <class T>
@@ -305,12 +196,11 @@ void solve_batch_impl(hlu_batch_s* b, const double* x_in, double* x_out, int32_t
   char* base = static_cast<char*>(b->work);
   const int32_t* dims = reinterpret_cast<const int32_t*>(base + b->dims_off);
   SolveBufs& sb = b->bufs;
-  const SolveDev d = make_solve_dev(b->sc, b->dsc, sb);
+  const ChainDev d = make_chain_dev(b->sc, b->dsc, sb);
   const int32_t N = b->N_tot;
   HIP_OK(gather_launch<double>(N, nrhs, b->d_perm, x_in, N, sb.y, N, s));
   sb.epoch = sb.epoch % 1000000000 + 1;
-  const int grid = std::max(1, std::min<int>(d.ntasks, 256));
-  HIP_OK(solve_persistent_launch<T>(reinterpret_cast<const T*>(base), dims, d, N, nrhs, sb.epoch, grid, s));
+  HIP_OK(chain_solve_launch<T>(reinterpret_cast<const T*>(base), dims, d, N, nrhs, sb.epoch, s));
   HIP_OK(scatter_perm_launch<double>(N, nrhs, b->d_perm, sb.y, N, x_out, N, s));
 }
 
@@ -338,6 +228,8 @@ hlu_status hlu_batch_create(const hlu_handle* hs, int32_t count, const hlu_facto
   return guard([&] {
     HLU_REQUIRE(hs && out && count >= 1, HLU_ERR_INVALID_ARG, "hlu_batch_create: bad arguments");
     HLU_REQUIRE(max_rhs >= 1 && max_rhs <= kMaxRhs, HLU_ERR_INVALID_ARG, "hlu_batch_create: need 1 <= max_rhs <= 32");
+    HLU_REQUIRE(count <= kMaxChains, HLU_ERR_UNSUPPORTED,
+                "hlu_batch_create: at most 64 problems (each needs a chain workgroup of the solve)");
     check_opts(o);
     for (int32_t i = 0; i < count; ++i) {
       HLU_REQUIRE(hs[i], HLU_ERR_INVALID_ARG, "hlu_batch_create: NULL handle");
@@ -377,13 +269,13 @@ hlu_status hlu_batch_create(const hlu_handle* hs, int32_t count, const hlu_facto
     std::vector<int64_t> a;
     for (size_t x : b->arena_off) a.push_back((int64_t)(x / es));
     std::vector<const Plan*> plans;
-    std::vector<const SolveSched*> scheds;
+    std::vector<const ChainSched*> scheds;
     for (auto& pb : pbs) {
       plans.push_back(&pb->ps.factor);
       scheds.push_back(&pb->sc);
     }
     merge_plans(plans, a, b->slot_base, &b->plan);
-    merge_scheds(scheds, a, b->slot_base, b->row_base, &b->sc);
+    merge_chain_scheds(scheds, a, b->slot_base, b->row_base, &b->sc);
     b->dplan.load(b->plan);
     b->dsc.load(b->sc);
     b->bufs.alloc(b->sc, b->N_tot, max_rhs);

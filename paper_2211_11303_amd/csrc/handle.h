@@ -20,7 +20,7 @@
 
 #include "common.h"
 #include "plan.h"
-#include "solve_sched.h"
+#include "chain_sched.h"
 #include "structure.h"
 
 namespace hlu {
@@ -90,52 +90,63 @@ struct DevArrays {
 // Read-only device copy of a persistent-solve schedule.
 struct DevSched {
   Owned mem;
-  const STask* tasks = nullptr;
-  const SLeaf* leaves = nullptr;
-  const SDense* dense = nullptr;
-  const SLow* low = nullptr;
-  const STprod* tprod = nullptr;
-  const int32_t* push0 = nullptr;
-  const int32_t* push_recs = nullptr;
-  const int32_t* leaf_tq = nullptr;
+  const CLeaf* leaves = nullptr;
+  const CTarget* tgt = nullptr;
+  const GDense* gdense = nullptr;
+  const GLow* glow = nullptr;
+  const GInline* ginl = nullptr;
+  const CGather* gathers = nullptr;
+  const CTprod* tprod = nullptr;
   const int32_t* tg0 = nullptr;
   const int32_t* tg_list = nullptr;
-  void load(const SolveSched& sc) {
-    tasks = mem.keep(upload(sc.tasks));
+  const CTask* tasks = nullptr;
+  const int32_t* member_L = nullptr;
+  const int32_t* member_pos0 = nullptr;
+  void load(const ChainSched& sc) {
     leaves = mem.keep(upload(sc.leaves));
-    dense = mem.keep(upload(sc.dense));
-    low = mem.keep(upload(sc.low));
+    tgt = mem.keep(upload(sc.tgt));
+    gdense = mem.keep(upload(sc.gdense));
+    glow = mem.keep(upload(sc.glow));
+    ginl = mem.keep(upload(sc.ginl));
+    gathers = mem.keep(upload(sc.gathers));
     tprod = mem.keep(upload(sc.tprod));
-    push0 = mem.keep(upload(sc.push0));
-    push_recs = mem.keep(upload(sc.push_recs));
-    leaf_tq = mem.keep(upload(sc.leaf_tq));
     tg0 = mem.keep(upload(sc.tg0));
     tg_list = mem.keep(upload(sc.tg_list));
+    tasks = mem.keep(upload(sc.tasks));
+    member_L = mem.keep(upload(sc.member_L));
+    member_pos0 = mem.keep(upload(sc.member_pos0));
   }
 };
+
+// Chains of one persistent solve launch at most (a quarter of the grid:
+// the rest of the workgroups run the helper tasks, and several persistent
+// solves on concurrent streams still find helpers).
+constexpr int kMaxChains = 64;
 
 // Mutable buffers of persistent solves with a given schedule (columns per
 // launch <= max_rhs).
 struct SolveBufs {
   Owned mem;
   void* inv = nullptr;        // triangle inverses (sized for FP64)
-  void* nm = nullptr;         // neighbour blocks times inverses (sized for FP64)
+  void* stack = nullptr;      // stacked operators of the chains (sized for FP64)
   double* pivots = nullptr;   // U_ii, cluster order
   double* y = nullptr;        // N x max_rhs
-  double* tbuf = nullptr;
-  int32_t* flags = nullptr;   // 2L leaf flags, T-product flags, record flags
-  double* pbuf = nullptr;
+  double* tbuf = nullptr;     // T products
+  double* fbuf = nullptr;     // gather records
+  int32_t* flags = nullptr;   // T-product flags, then record flags
+  int32_t* prog = nullptr;    // chain progress words
   int32_t* ctr = nullptr;
-  int64_t* trace = nullptr;   // debug clocks (HLU_DEBUG_SOLVE_TRACE)
-  int64_t pstride = 0;
+  int64_t* trace = nullptr;   // debug clocks of the chain (HLU_DEBUG_SOLVE_TRACE)
+  void* kargs = nullptr;      // launch arguments of the persistent solve
+  int64_t rstride = 0;
   int32_t max_rhs = 0;
   int32_t epoch = 0;
-  void alloc(const SolveSched& sc, int32_t N, int32_t max_rhs);
+  void alloc(const ChainSched& sc, int32_t N, int32_t max_rhs);
 };
 
-// Words of a persistent solve's counter block (kernels_solve.hip: claim
-// counter, finished forward tasks, error of the launch, error since the host
-// last read it, workgroups that have left).
+// Words of a persistent solve's counter block (kernels_chain.hip: claim
+// counter, unused, error of the launch, error since the host last read it,
+// workgroups that have left).
 constexpr int kSolveCtrWords = 8;
 // Longest wait of a persistent-solve task before its launch gives up, in
 // device wall-clock ticks: 20 s, or HLU_DEBUG_SOLVE_WAIT_US microseconds
@@ -146,17 +157,17 @@ int64_t solve_wait_ticks();
 bool take_solve_error(int32_t* ctr, hipStream_t s);
 
 // Device bytes SolveBufs::alloc takes for this schedule.
-size_t solve_buffer_bytes(const SolveSched& sc, int32_t N, int32_t max_rhs);
+size_t solve_buffer_bytes(const ChainSched& sc, int32_t N, int32_t max_rhs);
 
 // Kernel launch view of a schedule and its buffers.
-SolveDev make_solve_dev(const SolveSched& sc, const DevSched& d, const SolveBufs& b);
+ChainDev make_chain_dev(const ChainSched& sc, const DevSched& d, const SolveBufs& b);
 
 // Plans for one rank capacity, shared by the handles of one structure.
 // Host part built by get_bundle; device copies made by ensure_device.
 struct PlanBundle {
   int32_t kcap = 0;
   PlanSet ps;
-  SolveSched sc;
+  ChainSched sc;
   bool on_device = false;
   DevArrays dfactor, dsolve, dapply;
   DevSched dsc;
