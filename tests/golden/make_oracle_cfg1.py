@@ -1,6 +1,8 @@
 """Writes tests/golden/oracle_cfg1_k{kappa}_e{eps}.json: oracle results for
 the 16^3 cube workload (leaf 64, eta 2, 8 right-hand sides per seed,
-GMRES(50) to 1e-8).  Calls only the oracle (and the seeded input draw).
+GMRES(50) to 1e-8), including the factor error of the oracle factors
+rounded to FP32 storage (the rounding floor of the FP32 mode).  Calls only
+the oracle (and the seeded input draw).
 
 Usage: python tests/golden/make_oracle_cfg1.py KAPPA EPS
 """
@@ -32,6 +34,7 @@ def main(kappa, eps, n=16, leaf=64, seeds=(0, 1, 2), nrhs=8):
     t_factor = time.time() - t
     ranks = h.H.ranks()
     out = dict(n=n, kappa=kappa, eps=eps, leaf=leaf, N=d.N, factor_error=h.factor_error(),
+               factor_error_fp32_storage=h.factor_error(storage=np.float32),
                max_rank=int(max(ranks)), mean_rank=float(np.mean(ranks)), oracle_factor_s=t_factor,
                truncations=h.trunc.count, solves=[])
     for seed in seeds:
