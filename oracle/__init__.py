@@ -20,6 +20,9 @@ Modules, in the order of the method:
                    SVD, Sec. 4), H-matrix products, H-LU factorisation
                    (Algorithm 1, step II) and H-triangular solves
                    (Algorithm 1, step III).
+* ``hinverse``  -- approximate inverse B_H of the H-matrix by the Schulz
+                   iteration in H-arithmetic (Sec. 3; truncated SVD, Sec. 4),
+                   used as a preconditioner (Example 2).
 * ``krylov``    -- preconditioned restarted GMRES (Sec. 4, Example 1) and the
                    preconditioned Richardson iteration of Algorithm 1, step III.
 
