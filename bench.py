@@ -114,6 +114,76 @@ def event_time(fn, stream):
     return out, e0.elapsed_time(e1) / 1e3
 
 
+def oracle_errors(args, x, X):
+    """Per-solve ||x - x_oracle|| / ||x_oracle|| against the oracle's
+    solutions of the same right-hand sides (stored by
+    tests/golden/make_oracle_cfg2.py, oracle only), when the workload is the
+    one they were computed for; else None."""
+    import numpy as np
+    tag = os.path.join(ROOT, "tests", "golden", f"oracle_cfg2_k{int(args.kappa)}")
+    if not (args.n == 32 and args.leaf == 64 and args.eps == 1e-3 and args.restart == 50 and args.tol == 1e-8
+            and args.nrhs == 8 and float(args.kappa) == int(args.kappa) and os.path.exists(tag + "_x.npz")):
+        return None
+    z = np.load(tag + "_x.npz")
+    with open(tag + ".json") as f:
+        g = json.load(f)
+    xs = x.cpu().numpy()
+    Xs = X.cpu().numpy()
+    out = []
+    for k in range(len(z["seeds"])):
+        row = int(z["seeds"][k]) * args.nrhs + int(z["cols"][k])   # step block: seeds 0..2 x nrhs columns
+        xo = Xs[row] + z["scale"][k] * z["q"][k].astype(np.float64)
+        out.append(float(np.linalg.norm(xs[row] - xo) / np.linalg.norm(xo)))
+    return {"per_solve": out, "max": max(out), "oracle_err_vs_xstar_max": max(r["err"] for r in g["solves"]),
+            "oracle_iters": sorted({r["iters"] for r in g["solves"]}), "oracle_factor_error": g["factor_error"]}
+
+
+def oracle_full_size(args):
+    """The oracle's own timings on the whole workload, as stored with its
+    results by tests/golden/make_oracle_cfg2.py (one core, one BLAS thread,
+    run once on the build host, not on the GPU host): factor seconds and
+    GMRES seconds per right-hand side."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_cfg2_k{int(args.kappa)}.json")
+    if not (args.n == 32 and args.leaf == 64 and args.eps == 1e-3 and os.path.exists(path)):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    per = [r["seconds"] for r in g["solves"]]
+    return {"factor_s": g["oracle_factor_s"], "solve_s_mean": sum(per) / len(per),
+            "solves_per_s": len(per) / sum(per), "threads": g["oracle_threads"], "right_hand_sides": len(per),
+            "where": "build host (not the GPU host), stored with the oracle results"}
+
+
+def per_sweep_rates(A, H, B, args):
+    """Solves/s with 1 and 8 right-hand sides per GMRES call (one call each,
+    columns 0 and 0..7 of the workload), and the persistent H-solve launch
+    time at 1, 8 and all columns (HIP events on the launch stream)."""
+    import torch
+    from paper_2211_11303_amd import hlu
+    out = {}
+    for c in (1, 8):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, infos = hlu.gmres_solve(A, B[:c].contiguous(), H, restart=args.restart, tol=args.tol, max_iters=1000,
+                                   raise_on_fail=False)
+        torch.cuda.synchronize()
+        out[f"solves_per_s_{c}rhs"] = c / (time.perf_counter() - t0)
+        out[f"iters_{c}rhs"] = max(i["iters"] for i in infos)
+    for c in (1, 8, B.shape[0]):
+        v = B[:c].contiguous()
+        H.hlu_solve(v)
+        H.hlu_set_timing(True)
+        s0 = H.hlu_get_stats()
+        for _ in range(3):
+            H.hlu_solve(v)
+        torch.cuda.synchronize()
+        s1 = H.hlu_get_stats()
+        H.hlu_set_timing(False)
+        out[f"hsolve_launch_ms_{c}rhs"] = (s1["solve_kernel_ms"] - s0["solve_kernel_ms"]) / max(
+            1, s1["solve_launches"] - s0["solve_launches"])
+    return out
+
+
 def cpu_baseline(n, kappa, leaf, eps, restart, tol, level, N_full, iters_full, nrhs=24):
     """The oracle (FP64, plain Python/NumPy, one BLAS thread) on a bounded
     sample of the same workload: the principal diagonal block of A on one
@@ -562,15 +632,16 @@ def main():
         H.hlu_set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        iters, relres, errs = [], [], []
+        iters, relres, xs = [], [], []
         for k in range(args.steps):
             x, infos = solve_batch(k)
             log(f"{prec}: step {k} iters {[i['iters'] for i in infos]}")
             iters += [i["iters"] for i in infos]
             relres += [i["relres"] for i in infos]
-            errs.append(((x - X[0]).norm(dim=1) / X[0].norm(dim=1)).max().item())
+            xs.append(x)
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
+        errs = [((x - X[0]).norm(dim=1) / X[0].norm(dim=1)).max().item() for x in xs]
         ts = H.hlu_get_stats()
         H.hlu_set_timing(False)
         result[prec] = dict(factor_s=tf, T=T, solves_per_s=args.steps * nrhs_step / T, iters=iters,
@@ -578,7 +649,12 @@ def main():
                             solve_launches=ts["solve_launches"], solve_columns=ts["solve_columns"],
                             solve_kernel_s=ts["solve_kernel_ms"] / 1e3,
                             max_rank=st["max_rank"], mean_rank=st["mean_rank"],
-                            lowrank_entries=st["lowrank_entries"], capped=st["capped_blocks"])
+                            lowrank_entries=st["lowrank_entries"], capped=st["capped_blocks"],
+                            factor_flops=st["factor_flops"],
+                            factor_flops_by_kind={k: st["factor_flops_" + k] for k in ("getrf", "tri", "gemm",
+                                                                                       "trunc")},
+                            err_vs_oracle=oracle_errors(args, x, X[0]),
+                            per_sweep=per_sweep_rates(A, H, B[0], args))
 
     r32 = result["fp32"]
     # algorithmic bytes of one H-solve launch (L then U sweep) on c columns:
@@ -624,7 +700,12 @@ def main():
                                               "num_dense", "dense_entries", "factor_waves",
                                               "factor_tasks", "solve_waves")},
         "ranks_fp32": {"max": r32["max_rank"], "mean": r32["mean_rank"], "capped": r32["capped"]},
-        "roofline": {"bound": "hbm", "kernel": "solve_persistent_kernel<float>: one H-solve (L then U sweep) "
+        "factor_flops_fp32": r32["factor_flops"],
+        "factor_gflops_per_s_fp32": r32["factor_flops"] / r32["factor_s"] / 1e9,
+        "factor_flops_by_kind_fp32": r32["factor_flops_by_kind"],
+        "err_vs_oracle_fp32": r32["err_vs_oracle"],
+        "per_sweep_fp32": r32["per_sweep"],
+        "roofline": {"bound": "hbm", "kernel": "chain_solve_kernel<float>: one H-solve (L then U sweep) "
                                                "per launch, fp32 factors, fp64 vectors; launches of the "
                                                "timed region",
                      "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
@@ -637,6 +718,8 @@ def main():
                      "iters_fp64": sorted(set(r64["iters"])), "relres_max_fp64": r64["relres_max"],
                      "err_vs_xstar_max_fp64": r64["err_xstar_max"],
                      "ranks_fp64": {"max": r64["max_rank"], "mean": r64["mean_rank"]},
+                     "factor_gflops_per_s_fp64": r64["factor_flops"] / r64["factor_s"] / 1e9,
+                     "err_vs_oracle_fp64": r64["err_vs_oracle"], "per_sweep_fp64": r64["per_sweep"],
                      "fp32_over_fp64_solves": r32["solves_per_s"] / r64["solves_per_s"]})
         ra = result["fp32-acc64"]
         line["fp32_storage_fp64_tasks"] = {
@@ -650,6 +733,9 @@ def main():
         iters_full = max(result["fp64"]["iters"]) if "fp64" in result else max(r32["iters"])
         line["cpu_baseline"] = cpu_baseline(args.n, args.kappa, args.leaf, args.eps, args.restart, args.tol,
                                             args.cpu_level, N, iters_full)
+        ref = oracle_full_size(args)
+        if ref:
+            line["cpu_baseline"]["full_size_oracle"] = ref
     print(json.dumps(line), flush=True)
 
 

@@ -117,7 +117,27 @@ typedef struct {
   int64_t solve_launches;        /* persistent solve launches timed since hlu_set_timing */
   int64_t solve_columns;         /* right-hand-side columns those launches processed */
   double solve_kernel_ms;        /* their summed durations (HIP events on the launch stream) */
+  /* Nominal flops of the last hlu_factor (not filled for batch members):
+   * leaf LU 2m^3/3, triangular solves and products m^2 n, products of
+   * blocks 2mnk per term, truncation: Gram matrices 2(m+n)K^2, pivoted
+   * Cholesky K^3/3, core 2K^2 r + 2r^2 K, Jacobi 9n^3 per sweep, rebuild
+   * 2(m r + n K) r_new (K stacked columns, r their numerical rank). */
+  double factor_flops;
+  double factor_flops_getrf, factor_flops_tri, factor_flops_gemm, factor_flops_trunc;
 } hlu_stats;
+
+/* Schulz iteration for the H-matrix inverse (hlu_inverse). */
+typedef struct {
+  int32_t max_iters;   /* Schulz steps at most, >= 0                          */
+  double tol;          /* stop when the probed residual rho <= tol            */
+} hlu_schulz_opts;
+
+typedef struct {
+  int32_t iters;       /* Schulz steps taken (and kept)                       */
+  int32_t converged;   /* 1 if rho <= tol                                     */
+  double residual;     /* rho = ||(I - A_H B_H) Omega||_F / ||Omega||_F       */
+  double residual0;    /* rho of the start X_0                                */
+} hlu_schulz_info;
 
 /* ---------------------------------------------------------------- problem
  * The Kuhn-split unit cube (Example 1, Sec. 4): n^3 cubes, each cut into six
@@ -177,9 +197,15 @@ void hlu_destroy(hlu_handle h);
 hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
 
 /* All device bytes a factored handle holds for these options: the bound
- * workspace plus the library-owned buffers of its own solves and its matrix
- * values (shared plans excluded).  For admission by device-memory budget. */
+ * workspace, the library-owned buffers of its own solves, its matrix values,
+ * and the plan arrays, solve schedule, scatter targets and permutation of
+ * its structure (hlu_plan_device_bytes; those are shared by every handle of
+ * the structure, so a caller holding several handles of one structure counts
+ * them once).  For admission by device-memory budget. */
 hlu_status hlu_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
+/* The shared part of hlu_device_bytes: device copies of the structure's
+ * task plans, solve schedule, scatter targets and permutation. */
+hlu_status hlu_plan_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
 
 /* Hands the library a caller-owned device buffer of at least the bytes
  * reported above (256-byte aligned).  It stays in use until re-bound or the
@@ -212,6 +238,32 @@ hlu_status hlu_sync_status(hlu_handle h, void* stream);
 hlu_status hlu_apply_lu(hlu_handle h, const double* d_v, double* d_y, int32_t nrhs, int64_t ld,
                         void* stream);
 
+/* Approximate inverse B_H of the H-matrix A_H by the Schulz iteration
+ * (Sec. 3: the inverse of the H-matrix approximation of the Galerkin
+ * matrix by the iterative method of Schulz; Sec. 4: truncated SVD of rank r
+ * in the admissible blocks; Example 2: B_H as the preconditioner):
+ *   X_{k+1} = X_k (2I - A_H X_k),  X_0 = A^T / (||A||_1 ||A||_inf),
+ * both products in H-arithmetic on the handle's block tree, every addition
+ * into a low-rank block truncated with the rule of o (eps, max_rank); o->prec
+ * as for hlu_factor.  The iteration stops when rho_k = ||(I - A_H X_k)
+ * Omega||_F / ||Omega||_F <= so->tol, when a step does not decrease rho
+ * (the truncation floor; the previous iterate is kept), or after
+ * so->max_iters steps.  d_probe: Omega, device, N x nprobe column-major in
+ * the natural order, 1 <= nprobe <= 32 (borrowed; the caller draws it).
+ * Requires a symmetric A (HLU_ERR_UNSUPPORTED otherwise; K - kappa^2 M is
+ * symmetric) and no admissible block holding matrix entries (leaf sizes
+ * >= 32 on the Kuhn cube; HLU_ERR_UNSUPPORTED otherwise).  Uses the bound
+ * workspace, of at least hlu_inverse_workspace_bytes(h, o) bytes (four
+ * H-matrices: A_H, two iterates, 2I - A_H X_k).  On success the handle holds
+ * B_H instead of H-LU factors: hlu_solve and gmres_solve's preconditioner
+ * apply x = B_H b (an H-matrix-vector product), hlu_apply_lu returns
+ * HLU_ERR_STATE until the next hlu_factor.  info (host) receives the steps
+ * and residuals; hlu_get_stats the ranks of B_H and the flops.  Synchronises
+ * the stream. */
+hlu_status hlu_inverse_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
+hlu_status hlu_inverse(hlu_handle h, const hlu_factor_opts* o, const hlu_schulz_opts* so,
+                       const double* d_probe, int32_t nprobe, hlu_schulz_info* info, void* stream);
+
 /* Restarted right-preconditioned flexible GMRES (Sec. 4), x0 = 0,
  * classical Gram-Schmidt applied twice, FP64 throughout; precond may be
  * NULL.  Each of the nrhs columns is solved independently (its own Arnoldi
@@ -241,6 +293,23 @@ size_t gmres_static_max_bytes(void);
 hlu_status gmres_solve_static(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
                               hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info,
                               void* stream);
+
+/* Preconditioned Richardson iteration of Algorithm 1, steps III-IV, for
+ * every column of b (device, N x nrhs, leading dimension ld): x_0 = 0 and
+ * for k = 1, 2, ...:  r = b - A x;  err = ||r||_2 / ||b||_2;
+ * x += M^{-1} r (the preconditioner of `precond`: its H-LU factors, or its
+ * Schulz inverse);  stop once err < tol -- the correction is applied before
+ * the loop is left, the order the paper gives -- or after max_iters
+ * corrections.  info[c] (host): iters = corrections applied, converged
+ * (err < tol reached), abs_res = ||A x - b||_2 at exit (step IV's "error"),
+ * relres = abs_res / ||b||_2.  x (device) must not alias b.  d_work: device
+ * workspace of at least hlu_richardson_workspace_bytes(N, nrhs) bytes.
+ * Returns HLU_OK even when a column did not reach tol (see info).
+ * Synchronises the stream. */
+size_t hlu_richardson_workspace_bytes(int32_t n, int32_t nrhs);
+hlu_status hlu_richardson(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                          hlu_handle precond, double tol, int32_t max_iters, hlu_gmres_info* info,
+                          void* d_work, size_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------------ batch
  * Independent problems (each an hlu_handle, of any size) factored and solved

@@ -49,10 +49,20 @@ class Stats(ctypes.Structure):
         ("capped_blocks", c_int32), ("mean_rank", c_double), ("lowrank_entries", c_double),
         ("min_abs_pivot", c_double), ("max_abs_pivot", c_double),
         ("solve_launches", c_int64), ("solve_columns", c_int64), ("solve_kernel_ms", c_double),
+        ("factor_flops", c_double), ("factor_flops_getrf", c_double), ("factor_flops_tri", c_double),
+        ("factor_flops_gemm", c_double), ("factor_flops_trunc", c_double),
     ]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SchulzOpts(ctypes.Structure):
+    _fields_ = [("max_iters", c_int32), ("tol", c_double)]
+
+
+class SchulzInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("converged", c_int32), ("residual", c_double), ("residual0", c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -92,8 +102,14 @@ SIGNATURES = {
                               ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), c_void_p, c_size_t,
                               c_void_p]),
     "gmres_static_max_bytes": (c_size_t, []),
+    "hlu_richardson_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "hlu_richardson": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_double, c_int32,
+                                 ctypes.POINTER(GmresInfo), c_void_p, c_size_t, c_void_p]),
     "gmres_solve_static": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
                                      ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), c_void_p]),
+    "hlu_inverse_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
+    "hlu_inverse": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(SchulzOpts), c_void_p, c_int32,
+                              ctypes.POINTER(SchulzInfo), c_void_p]),
     "hlu_structure_sizes": (c_int32, [c_void_p, P_i32, P_i32, P_i32]),
     "hlu_export_structure": (c_int32, [c_void_p, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32, P_i32,
                                        P_i32]),
@@ -118,6 +134,7 @@ SIGNATURES = {
     "gmres_solve_batch": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(GmresOpts),
                                     ctypes.POINTER(GmresInfo), c_void_p, c_size_t, c_void_p]),
     "hlu_device_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
+    "hlu_plan_device_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
     "hlu_server_create": (c_int32, [ctypes.POINTER(ServerOpts), ctypes.POINTER(c_void_p)]),
     "hlu_server_prepare": (c_int32, [c_void_p, c_int32]),
     "hlu_server_submit": (c_int32, [c_void_p, c_int32, c_double, c_int32, c_void_p, c_void_p,

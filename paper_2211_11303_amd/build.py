@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libhlu.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["mesh.cpp", "structure.cpp", "plan.cpp", "chain_sched.cpp", "api.cpp", "gmres.cpp", "batch.cpp",
-           "server.cpp", "autotune.cpp",
+           "server.cpp", "autotune.cpp", "hinverse.cpp",
            "kernels_hlu.hip",
            "kernels_vec.hip", "kernels_chain.hip"]
 

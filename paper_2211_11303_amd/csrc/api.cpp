@@ -32,7 +32,7 @@ WorkLayout work_layout(const PlanSet& ps, int32_t prec) {
   L.arena_bytes = align256((size_t)ps.store.total_elems * elem_size(prec));
   L.dims_off = L.arena_bytes;
   L.status_off = L.dims_off + align256((size_t)ps.store.num_slots * sizeof(int32_t));
-  L.total = L.status_off + 256;
+  L.total = L.status_off + kStatusWords * sizeof(int32_t);
   return L;
 }
 
@@ -72,6 +72,28 @@ void ensure_device(Shared& sh, PlanBundle& pb) {
   pb.dsc.load(pb.sc);
   ensure_targets(sh, pb);
   pb.on_device = true;
+}
+
+namespace {
+template <class V>
+size_t vbytes(const V& v) {
+  return v.size() * sizeof(typename V::value_type);
+}
+size_t plan_device_bytes(const Plan& p) {
+  return vbytes(p.getrf) + vbytes(p.tri) + vbytes(p.gemm) + vbytes(p.terms) + vbytes(p.trunc) + vbytes(p.parts) +
+         vbytes(p.fill) + vbytes(p.gemm_tile_op) + vbytes(p.gemm_tile_ij);
+}
+}  // namespace
+
+size_t bundle_device_bytes(const Shared& sh, const PlanBundle& pb) {
+  const ChainSched& sc = pb.sc;
+  size_t b = plan_device_bytes(pb.ps.factor) + plan_device_bytes(pb.ps.fwd_bwd) + plan_device_bytes(pb.ps.apply);
+  b += vbytes(sc.leaves) + vbytes(sc.tgt) + vbytes(sc.gdense) + vbytes(sc.glow) + vbytes(sc.ginl) +
+       vbytes(sc.gathers) + vbytes(sc.tprod) + vbytes(sc.tg0) + vbytes(sc.tg_list) + vbytes(sc.tasks) +
+       vbytes(sc.member_L) + vbytes(sc.member_pos0);
+  b += sh.col.size() * sizeof(int64_t);      // scatter targets
+  b += sh.S.perm.size() * sizeof(int32_t);   // permutation
+  return b;
 }
 
 void SolveBufs::alloc(const ChainSched& sc, int32_t N, int32_t rhs) {
@@ -258,6 +280,19 @@ void gather_stats(hlu_s* h, const double* d_pivots) {
   h->stats.max_abs_pivot = hi;
 }
 
+// Nominal flops of the last factorisation from the status words.
+void read_flops(const int32_t* d_status, hlu_stats* st) {
+  uint64_t f[kNumFlopKinds * kFlopSpread];
+  HIP_OK(hipMemcpy(f, d_status + kFlopWord0, sizeof(f), hipMemcpyDeviceToHost));
+  double k[kNumFlopKinds] = {0, 0, 0, 0};
+  for (int i = 0; i < kNumFlopKinds * kFlopSpread; ++i) k[i / kFlopSpread] += (double)f[i];
+  st->factor_flops_getrf = k[kFlopGetrf];
+  st->factor_flops_tri = k[kFlopTri];
+  st->factor_flops_gemm = k[kFlopGemm];
+  st->factor_flops_trunc = k[kFlopTrunc];
+  st->factor_flops = k[0] + k[1] + k[2] + k[3];
+}
+
 // Adds the durations of the recorded event pairs to the timing totals.
 void harvest_timing(hlu_s* h) {
   for (size_t i = 0; i + 1 < h->tev_used; i += 2) {
@@ -332,7 +367,7 @@ template <class T>
 void factor_impl(hlu_s* h, hipStream_t s) {
   T* arena = static_cast<T*>(h->arena);
   factor_prepare<T>(h, arena, h->dims, s);
-  HIP_OK(zero_int_launch(h->status, 64, s));
+  HIP_OK(zero_int_launch(h->status, kStatusWords, s));
   run_plan<T>(h, h->pb->ps.factor, h->pb->dfactor, h->factor_compute64, s);
   // the persistent solve applies the diagonal leaves through their inverses
   h->inv_ready = false;
@@ -450,6 +485,8 @@ void resolve_memory(hlu_s* h, const hlu_factor_opts* o) {
   h->status = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.status_off);
 }
 
+}  // namespace
+
 void use_bundle(hlu_s* h, int32_t kcap) {
   if (h->pb && h->pb->kcap == kcap) return;
   HLU_REQUIRE(!h->batch, HLU_ERR_STATE, "handle is bound through a batch with another rank capacity");
@@ -458,7 +495,6 @@ void use_bundle(hlu_s* h, int32_t kcap) {
   h->factored = false;
 }
 
-}  // namespace
 }  // namespace hlu
 
 using namespace hlu;
@@ -608,13 +644,23 @@ hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* b
   });
 }
 
+hlu_status hlu_plan_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes) {
+  return guard([&] {
+    HLU_REQUIRE(h && bytes, HLU_ERR_INVALID_ARG, "hlu_plan_device_bytes: NULL argument");
+    check_opts(o);
+    use_bundle(h, kcap_for(o));
+    *bytes = bundle_device_bytes(*h->sh, *h->pb);
+  });
+}
+
 hlu_status hlu_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes) {
   return guard([&] {
     HLU_REQUIRE(h && bytes, HLU_ERR_INVALID_ARG, "hlu_device_bytes: NULL argument");
     check_opts(o);
     use_bundle(h, kcap_for(o));
     const size_t ws = work_layout(h->pb->ps, o->prec).total;
-    *bytes = ws + solve_buffer_bytes(h->pb->sc, h->sh->S.N, kMaxRhs) + h->val.size() * sizeof(double);
+    *bytes = ws + solve_buffer_bytes(h->pb->sc, h->sh->S.N, kMaxRhs) + h->val.size() * sizeof(double) +
+             bundle_device_bytes(*h->sh, *h->pb);
   });
 }
 
@@ -639,6 +685,7 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     ensure_device(*h->sh, *h->pb);
     hipStream_t s = (hipStream_t)stream;
     h->factored = false;
+    h->mode = 0;
     record_factor(h, o);
     if (fp32_storage(o->prec)) factor_impl<float>(h, s);
     else factor_impl<double>(h, s);
@@ -649,6 +696,7 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     HLU_REQUIRE(status[2] == 0, HLU_ERR_DEVICE, "hlu_factor: a truncation exceeded its round bound");
     h->factored = true;
     gather_stats(h, h->sbuf->pivots);
+    read_flops(h->status, &h->stats);
     h->stats.capped_blocks = status[1];
     dump_trunc_trace(h->pb->ps.factor);
     if (status[1] > 0 && o->max_rank == 0) {
@@ -664,6 +712,10 @@ hlu_status hlu_solve(hlu_handle h, const double* d_b, double* d_x, int32_t nrhs,
     HLU_REQUIRE(h && d_b && d_x && nrhs >= 1 && ld >= h->sh->S.N, HLU_ERR_INVALID_ARG, "hlu_solve: bad arguments");
     HLU_REQUIRE(h->factored, HLU_ERR_STATE, "hlu_solve: handle is not factored");
     hipStream_t s = (hipStream_t)stream;
+    if (h->mode == 1) {   // the Schulz inverse: x = B_H b
+      inverse_apply(h, d_b, d_x, nrhs, ld, s);
+      return;
+    }
     const char* e = getenv("HLU_DEBUG_WAVE_SOLVE");
     if (e && e[0] == '1') {   // the planned wave form of the same solve, for cross-checks
       if (fp32_storage(h->prec))
@@ -692,7 +744,7 @@ hlu_status hlu_apply_lu(hlu_handle h, const double* d_v, double* d_y, int32_t nr
   return guard([&] {
     HLU_REQUIRE(h && d_v && d_y && nrhs >= 1 && ld >= h->sh->S.N && d_v != d_y, HLU_ERR_INVALID_ARG,
                 "hlu_apply_lu: bad arguments");
-    HLU_REQUIRE(h->factored, HLU_ERR_STATE, "hlu_apply_lu: handle is not factored");
+    HLU_REQUIRE(h->factored && h->mode == 0, HLU_ERR_STATE, "hlu_apply_lu: handle holds no H-LU factors");
     hipStream_t s = (hipStream_t)stream;
     if (fp32_storage(h->prec))
       solve_impl<float>(h, h->pb->ps.apply, h->pb->dapply, d_v, d_y, nrhs, ld, s);

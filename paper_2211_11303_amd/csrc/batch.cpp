@@ -179,7 +179,7 @@ void factor_batch_impl(hlu_batch_s* b, hipStream_t s) {
   int32_t* status = reinterpret_cast<int32_t*>(base + b->status_off);
   for (size_t p = 0; p < b->hs.size(); ++p)
     factor_prepare<T>(b->hs[p], reinterpret_cast<T*>(base + b->arena_off[p]), dims + b->slot_base[p], s);
-  HIP_OK(zero_int_launch(status, 64, s));
+  HIP_OK(zero_int_launch(status, kStatusWords, s));
   const bool compute64 = fp64_tasks(b->opts.prec);
   int32_t tile_base = 0;
   for (const Wave& w : b->plan.waves) {
@@ -263,7 +263,7 @@ hlu_status hlu_batch_create(const hlu_handle* hs, int32_t count, const hlu_facto
     b->N_tot = rows;
     b->dims_off = off;
     b->status_off = b->dims_off + align256((size_t)slots * sizeof(int32_t));
-    b->total = b->status_off + 256;
+    b->total = b->status_off + kStatusWords * sizeof(int32_t);
     // merged plan and schedule
     const size_t es = elem_size(o->prec);
     std::vector<int64_t> a;

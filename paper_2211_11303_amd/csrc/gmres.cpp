@@ -207,7 +207,7 @@ hlu_status gmres_solve_on(hlu_spmat A, const double* d_b, double* d_x, int32_t n
     if (precond) {
       HLU_REQUIRE(precond->factored, HLU_ERR_STATE, "gmres_solve: preconditioner not factored");
       HLU_REQUIRE(precond->sh->S.N == A->n, HLU_ERR_INVALID_ARG, "gmres_solve: size mismatch");
-      if (!may_allocate) {
+      if (!may_allocate && precond->mode == 0) {
         HLU_REQUIRE(precond->sbuf != nullptr, HLU_ERR_STATE,
                     "gmres_solve_static: the preconditioner's solve buffers are not made yet (one hlu_solve makes "
                     "them)");
@@ -242,7 +242,7 @@ hlu_status gmres_solve_on(hlu_spmat A, const double* d_b, double* d_x, int32_t n
         HIP_OK(hipMemcpyAsync(out, in, (size_t)total * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
     };
-    if (precond) {
+    if (precond && precond->mode == 0) {   // H-LU factors: the persistent solve's error word
       ensure_solve_bufs(precond);   // made by the first solve otherwise (checked above when not allowed)
       sys.d_err = precond->sbuf->ctr + 3;
     }
@@ -298,6 +298,110 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
                        const hlu_gmres_opts* o, hlu_gmres_info* info, void* d_work, size_t work_bytes,
                        void* stream) {
   return gmres_solve_on(A, d_b, d_x, nrhs, ld, precond, o, info, d_work, work_bytes, (hipStream_t)stream, true);
+}
+
+size_t hlu_richardson_workspace_bytes(int32_t n, int32_t nrhs) {
+  if (n <= 0 || nrhs <= 0) return 0;
+  const size_t blk = align256((size_t)n * nrhs * sizeof(double));
+  return 4 * blk + align256((size_t)kDotBlocks * nrhs * sizeof(double)) + 2 * align256((size_t)nrhs * sizeof(double)) +
+         2 * align256((size_t)nrhs * sizeof(int64_t));
+}
+
+// Algorithm 1, steps III-IV, for every column of b: x_0 = 0 and, for
+// k = 1, 2, ...: r = b - A x; err = ||r|| / ||b||; x += U^{-1}(L^{-1} r);
+// stop once err < tol (the correction is applied before leaving, the order
+// the paper gives) or after max_iters corrections; then ||A x - b||_2.
+// Columns run together; a column that has stopped gets zero corrections.
+hlu_status hlu_richardson(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, hlu_handle precond,
+                          double tol, int32_t max_iters, hlu_gmres_info* info, void* d_work, size_t work_bytes,
+                          void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  return guard([&] {
+    HLU_REQUIRE(A && d_b && d_x && precond && info && d_work && nrhs >= 1 && ld >= A->n && d_b != d_x,
+                HLU_ERR_INVALID_ARG, "hlu_richardson: bad arguments");
+    HLU_REQUIRE(tol >= 0.0 && std::isfinite(tol) && max_iters >= 1, HLU_ERR_INVALID_ARG,
+                "hlu_richardson: need a finite tol >= 0 and max_iters >= 1");
+    HLU_REQUIRE(precond->factored, HLU_ERR_STATE, "hlu_richardson: preconditioner not factored");
+    HLU_REQUIRE(precond->sh->S.N == A->n, HLU_ERR_INVALID_ARG, "hlu_richardson: size mismatch");
+    const int32_t N = A->n;
+    HLU_REQUIRE(work_bytes >= hlu_richardson_workspace_bytes(N, nrhs), HLU_ERR_OUT_OF_MEMORY,
+                "hlu_richardson: workspace too small");
+    const int64_t total = (int64_t)N * nrhs;
+    const size_t blk = align256((size_t)total * sizeof(double));
+    char* wp = static_cast<char*>(d_work);
+    double* bb = reinterpret_cast<double*>(wp);
+    wp += blk;
+    double* xx = reinterpret_cast<double*>(wp);
+    wp += blk;
+    double* r = reinterpret_cast<double*>(wp);
+    wp += blk;
+    double* z = reinterpret_cast<double*>(wp);
+    wp += blk;
+    double* part = reinterpret_cast<double*>(wp);
+    wp += align256((size_t)kDotBlocks * nrhs * sizeof(double));
+    double* dn = reinterpret_cast<double*>(wp);
+    wp += align256((size_t)nrhs * sizeof(double));
+    double* dc = reinterpret_cast<double*>(wp);
+    wp += align256((size_t)nrhs * sizeof(double));
+    int64_t* doff = reinterpret_cast<int64_t*>(wp);
+    wp += align256((size_t)nrhs * sizeof(int64_t));
+    int64_t* dlen = reinterpret_cast<int64_t*>(wp);
+    std::vector<int64_t> off(nrhs), len(nrhs, N);
+    for (int c = 0; c < nrhs; ++c) off[c] = (int64_t)c * N;
+    HIP_OK(hipMemcpyAsync(doff, off.data(), nrhs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(dlen, len.data(), nrhs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_OK(copy_cols_launch(N, nrhs, d_b, ld, bb, N, s));
+    HIP_OK(hipMemsetAsync(xx, 0, (size_t)total * sizeof(double), s));
+    auto sqnorms = [&](const double* v) {
+      HIP_OK(seg_dot_launch(nrhs, doff, dlen, 1, v, 0, v, part, dn, s));
+      std::vector<double> t(nrhs);
+      HIP_OK(hipMemcpyAsync(t.data(), dn, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      return t;
+    };
+    auto residual = [&] {   // r = b - A x
+      HIP_OK(spmv_launch(N, A->rp, A->ci, A->val, xx, r, nrhs, N, 1.0, 0.0, s));
+      HIP_OK(sub_launch(total, bb, r, s));
+    };
+    std::vector<double> bnorm = sqnorms(bb);
+    for (double& v : bnorm) v = std::sqrt(std::max(0.0, v));
+    std::vector<char> done(nrhs, 0), conv(nrhs, 0);
+    std::vector<int32_t> iters(nrhs, 0);
+    std::vector<double> coef(nrhs);
+    for (int32_t k = 1; k <= max_iters; ++k) {
+      residual();
+      const std::vector<double> rn = sqnorms(r);
+      bool any = false;
+      for (int c = 0; c < nrhs; ++c) {
+        coef[c] = done[c] ? 0.0 : 1.0;
+        any = any || !done[c];
+      }
+      if (!any) break;
+      HIP_OK(hipMemcpyAsync(dc, coef.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_OK(seg_scale_launch(nrhs, doff, dlen, N, r, dc, r, s));   // stopped columns: zero correction
+      const hlu_status ps = hlu_solve(precond, r, z, nrhs, N, s);
+      if (ps != HLU_OK) fail(ps, std::string("hlu_richardson: preconditioner: ") + get_error());
+      for (int c = 0; c < nrhs; ++c) coef[c] = -coef[c];
+      HIP_OK(hipMemcpyAsync(dc, coef.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_OK(seg_orth_launch(nrhs, doff, dlen, N, 1, z, 0, dc, xx, s));   // x += z on running columns
+      for (int c = 0; c < nrhs; ++c) {
+        if (done[c]) continue;
+        iters[c] = k;
+        const double err = bnorm[c] > 0.0 ? std::sqrt(std::max(0.0, rn[c])) / bnorm[c] : 0.0;
+        if (err < tol) done[c] = conv[c] = 1;
+      }
+    }
+    residual();
+    const std::vector<double> rn = sqnorms(r);
+    for (int c = 0; c < nrhs; ++c) {
+      info[c].iters = iters[c];
+      info[c].converged = conv[c];
+      info[c].abs_res = std::sqrt(std::max(0.0, rn[c]));
+      info[c].relres = bnorm[c] > 0.0 ? info[c].abs_res / bnorm[c] : 0.0;
+    }
+    HIP_OK(copy_cols_launch(N, nrhs, xx, N, d_x, ld, s));
+    HIP_OK(hipStreamSynchronize(s));
+  });
 }
 
 size_t gmres_static_max_bytes(void) { return kStaticGmresBytes; }

@@ -162,6 +162,12 @@ size_t solve_buffer_bytes(const ChainSched& sc, int32_t N, int32_t max_rhs);
 // Kernel launch view of a schedule and its buffers.
 ChainDev make_chain_dev(const ChainSched& sc, const DevSched& d, const SolveBufs& b);
 
+// Plans of the Schulz inverse for one rank capacity and their device copies.
+struct InverseBundle {
+  InversePlanSet ip;
+  DevArrays dstep[2], dapply[2], damul;
+};
+
 // Plans for one rank capacity, shared by the handles of one structure.
 // Host part built by get_bundle; device copies made by ensure_device.
 struct PlanBundle {
@@ -173,6 +179,7 @@ struct PlanBundle {
   DevSched dsc;
   Owned mem;
   int64_t* d_target = nullptr;   // arena element of every stored entry of A
+  std::unique_ptr<InverseBundle> inv;   // built by get_inverse_bundle on first use
 };
 
 struct Shared {
@@ -185,6 +192,11 @@ struct Shared {
   std::mutex mu;
   std::map<int32_t, std::shared_ptr<PlanBundle>> bundles;
 };
+
+// Device bytes of the plan arrays, schedule, scatter targets and
+// permutation shared by every handle of the structure (one copy per rank
+// capacity).
+size_t bundle_device_bytes(const Shared& sh, const PlanBundle& pb);
 
 // Plans for capacity kcap (host work, built on first use; thread-safe).
 std::shared_ptr<PlanBundle> get_bundle(Shared& sh, int32_t kcap);
@@ -231,6 +243,14 @@ hipError_t scatter_perm_launch(int32_t n, int32_t nrhs, const int32_t* perm, con
                                double* dst, int64_t ldd, hipStream_t s);
 template <class T>
 hipError_t scatter_values_launch(int64_t nnz, const int64_t* target, const double* val, T* arena, hipStream_t s);
+template <class T>
+hipError_t scatter_values_scaled_launch(int64_t nnz, const int64_t* target, int64_t shift, double scale,
+                                        const double* val, T* arena, hipStream_t s);
+// {||v - u||^2, ||v||^2} over n elements into the last two of
+// diff_norm_scratch_doubles() doubles of scratch (deterministic order)
+size_t diff_norm_scratch_doubles();
+template <class T>
+hipError_t diff_norm_launch(int64_t n, const T* v, const T* u, double* scratch, hipStream_t s);
 template <class T>
 hipError_t zero_launch(T* p, int64_t n, hipStream_t s);
 template <class T>
@@ -280,7 +300,13 @@ struct hlu_s {
   // own persistent solves
   std::unique_ptr<hlu::SolveBufs> sbuf;
   bool inv_ready = false;                // sbuf->inv holds this factor's inverses
-  // factor state
+  // factor state (mode 0: H-LU factors; mode 1: Schulz inverse B_H, held in
+  // H-matrix inv_mat of the inverse layout; `factored`: a preconditioner is
+  // ready)
+  int32_t mode = 0;
+  int32_t inv_mat = 1;
+  double* red = nullptr;                 // inverse mode: reduction scratch in the workspace
+  int32_t symmetric = -1;                // values checked symmetric (1), not (0), unchecked (-1)
   bool factored = false;
   int32_t prec = HLU_FP64;
   double eps = 0.0;
@@ -301,6 +327,10 @@ void ensure_solve_bufs(hlu_s* h);                   // sbuf for pb's schedule
 template <class T>
 void factor_prepare(hlu_s* h, T* arena, int32_t* dims, hipStream_t s);   // A into the arena
 void gather_stats(hlu_s* h, const double* d_pivots);
+void read_flops(const int32_t* d_status, hlu_stats* st);
+void use_bundle(hlu_s* h, int32_t kcap);
+// y = B_H b with the Schulz inverse of the handle (hlu_solve in inverse mode)
+void inverse_apply(hlu_s* h, const double* b, double* x, int32_t nrhs, int64_t ld, hipStream_t s);
 void harvest_timing(hlu_s* h);
 void record_factor(hlu_s* h, const hlu_factor_opts* o);
 void batch_forget(hlu_batch_s* b, hlu_s* h);        // a member handle is destroyed

@@ -13,6 +13,10 @@
 #include "plan.h"
 #include "trunc_rounds.h"
 
+// Row of the 16 x 16 result block held in register r of lane l by
+// v_mfma_f32_16x16x4f32 (column l % 16).
+#define MFMA_F32_ROW(l, r) (4 * ((l) >> 4) + (r))
+
 namespace hlu {
 namespace dev {
 
@@ -21,6 +25,13 @@ __device__ __forceinline__ int dimv(int32_t code, const int32_t* dims) { return 
 template <class T>
 __device__ __forceinline__ T& at(T* base, const MatRef& m, int i, int j) {
   return base[m.off + (int64_t)i * m.rs + (int64_t)j * m.cs];
+}
+
+// Nominal flops of the factor's tasks, added per workgroup into kFlopSpread
+// counters per kind (spread by block index to limit atomic contention).
+__device__ __forceinline__ void add_flops(int32_t* status, int kind, double flops) {
+  unsigned long long* f = reinterpret_cast<unsigned long long*>(status + kFlopWord0);
+  atomicAdd(f + kind * kFlopSpread + (blockIdx.x & (kFlopSpread - 1)), (unsigned long long)flops);
 }
 
 // --------------------------------------------------------------- GETRF
@@ -58,6 +69,7 @@ __global__ void __launch_bounds__(256) getrf_kernel(T* arena, const GetrfOp* ops
     const int i = e % m, j = e / m;
     g[i + (int64_t)j * op.ld] = T(D[i + j * m]);
   }
+  if (threadIdx.x == 0) add_flops(status, kFlopGetrf, 2.0 * m * m * m / 3.0);
 }
 
 // ----------------------------------------------------------------- TRI
@@ -70,7 +82,7 @@ constexpr size_t kLdsBytes = 160 * 1024;
 
 template <class T, class C>
 __global__ void __launch_bounds__(256) tri_kernel(T* arena, const TriOp* ops, const int32_t* dims,
-                                                  int tri_cols) {
+                                                  int tri_cols, int32_t* status) {
   extern __shared__ unsigned char smem_raw[];
   const TriOp op = ops[blockIdx.x];
   const int m = op.m;
@@ -150,85 +162,112 @@ __global__ void __launch_bounds__(256) tri_kernel(T* arena, const TriOp* ops, co
     }
     __syncthreads();
   }
+  if (threadIdx.x == 0) add_flops(status, kFlopTri, (double)m * m * p);
 }
 
 // ---------------------------------------------------------------- GEMM
-// One 64 x 64 output tile per workgroup: C = beta C + sum_t alpha_t A_t B_t,
-// operands of any strides, k streamed through LDS in chunks of 16; each of
-// the 256 threads accumulates a 4 x 4 sub-tile.
+// One 64 x 64 output tile per workgroup, C = beta C + sum_t alpha_t A_t B_t
+// (operands of any strides), on the matrix cores: k is streamed through LDS
+// in chunks of 16 (A scaled by alpha_t when staged), each wavefront owns a
+// 32 x 32 quarter of the tile as 2 x 2 blocks of 16 x 16, and each block
+// accumulates 16 x 16 x 4 MFMAs in the arithmetic type C (FP32 or FP64).
+// Operand lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k; result
+// register r of lane l holds D[mfma_row(l, r)][l % 16] (layouts measured on
+// the device).  Thread 0 adds the tile's nominal flops (2 m n k per term)
+// to the factor's flop counters.
 constexpr int kGT = 64, kGK = 16;
+
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <class C>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef mfma_f4 acc_t;
+  __device__ static acc_t step(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return MFMA_F32_ROW(lane, r); }
+};
+template <>
+struct Mfma<double> {
+  typedef mfma_d4 acc_t;
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
 
 template <class T, class C>
 __global__ void __launch_bounds__(256) gemm_kernel(T* arena, const GemmOp* ops, const GemmTerm* terms,
                                                    const int32_t* tile_op, const int32_t* tile_ij,
-                                                   int32_t tile0, const int32_t* dims) {
+                                                   int32_t tile0, const int32_t* dims, int32_t* status) {
   __shared__ C As[kGK][kGT + 1];
   __shared__ C Bs[kGK][kGT + 1];
+  typedef typename Mfma<C>::acc_t acc_t;
   const int tile = tile0 + blockIdx.x;
   const GemmOp op = ops[tile_op[tile]];
   const int ti = tile_ij[tile] >> 16, tj = tile_ij[tile] & 0xffff;
   const int M = dimv(op.C.rows, dims), N = dimv(op.C.cols, dims);
   const int i0 = ti * kGT, j0 = tj * kGT;
   if (i0 >= M || j0 >= N) return;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  C acc[4][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  acc_t acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = C(0);
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{C(0), C(0), C(0), C(0)};
+  double flops = 0.0;
   for (int t = 0; t < op.nt; ++t) {
     const GemmTerm tm = terms[op.t0 + t];
     const int K = dimv(tm.A.cols, dims);
     const C alpha = C(tm.alpha);
-    C part[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) part[a][b] = C(0);
+    flops += 2.0 * min(kGT, M - i0) * min(kGT, N - j0) * K;
     for (int k0 = 0; k0 < K; k0 += kGK) {
       for (int e = threadIdx.x; e < kGK * kGT; e += 256) {
-        // A tile: rows i0.., cols k0..; index so that consecutive threads
-        // walk the unit-stride dimension of A when possible
+        // consecutive threads walk the unit-stride dimension of the operand
+        // when it has one
         int r, c;
         if (tm.A.rs == 1) { r = e % kGT; c = e / kGT; } else { c = e % kGK; r = e / kGK; }
         const int gi = i0 + r, gk = k0 + c;
-        As[c][r] = (gi < M && gk < K) ? C(at(arena, tm.A, gi, gk)) : C(0);
+        As[c][r] = (gi < M && gk < K) ? alpha * C(at(arena, tm.A, gi, gk)) : C(0);
         int r2, c2;
         if (tm.B.cs == 1) { c2 = e % kGT; r2 = e / kGT; } else { r2 = e % kGK; c2 = e / kGK; }
         const int bk = k0 + r2, bj = j0 + c2;
         Bs[r2][c2] = (bk < K && bj < N) ? C(at(arena, tm.B, bk, bj)) : C(0);
       }
       __syncthreads();
+      const int kc = min(kGK, K - k0);
+      for (int ks = 0; ks < kc; ks += 4) {
+        const int kk = ks + (lane >> 4);
+        C av[2], bv[2];
 #pragma unroll
-      for (int kk = 0; kk < kGK; ++kk) {
-        C av[4], bv[4];
+        for (int a = 0; a < 2; ++a) av[a] = As[kk][wr + 16 * a + (lane & 15)];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+        for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wc + 16 * b + (lane & 15)];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) part[a][b] += av[a] * bv[b];
+          for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<C>::step(av[a], bv[b], acc[a][b]);
       }
       __syncthreads();
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += alpha * part[a][b];
   }
   const C beta = C(op.beta);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
-      if (gi < M && gj < N) {
-        T& c = at(arena, op.C, gi, gj);
-        c = T((op.beta == 0.0 ? C(0) : beta * C(c)) + acc[a][b]);
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wr + 16 * a + Mfma<C>::row(lane, r);
+        const int gj = j0 + wc + 16 * b + (lane & 15);
+        if (gi < M && gj < N) {
+          T& c = at(arena, op.C, gi, gj);
+          c = T((op.beta == 0.0 ? C(0) : beta * C(c)) + acc[a][b][r]);
+        }
       }
-    }
+  if (threadIdx.x == 0) add_flops(status, kFlopGemm, flops);
 }
 
 // ---------------------------------------------------------------- FILL
@@ -531,6 +570,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   const double off_rel = fmax(1e-26, te * te * te * te);
   const int64_t t_start = trace ? (int64_t)wall_clock64() : 0;
   int rounds = 0, k_first = -1, r1_first = -1, sweeps = 0;
+  double fl = 0.0;   // nominal flops of the op (thread 0)
   // debug: clocks per phase (thread 0, after the phase's closing barrier)
   int64_t ph[6] = {0, 0, 0, 0, 0, 0};
   int64_t t_last = t_start;
@@ -597,6 +637,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
     if (threadIdx.x == 0) s_r1 = r1c;
     __syncthreads();
     mark(1);
+    if (threadIdx.x == 0) fl += 2.0 * (op.m + op.n) * K * K + (double)K * K * K / 3.0;
     const int r1 = s_r1;
     if (k_first < 0) {
       k_first = K;
@@ -655,7 +696,10 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
           bufS[k * kLd + l] = v;
         }
         __syncthreads();
-        double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel, &sweeps);
+        const int sw0 = sweeps;
+        const double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel, &sweeps);
+        if (threadIdx.x == 0)
+          fl += 9.0 * r2 * r2 * r2 * (sweeps - sw0) + 4.0 * r2 * r2 * r1 + (double)r1 * r1 * r1 / 3.0;
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = k < r2 ? fmax(Mres[k * kLd + k], 0.0) : 0.0;
         __syncthreads();
         // eigenvectors of S, r1 x r2 -> S buffer, then into the W buffer
@@ -676,7 +720,10 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       } else {
         for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) bufS[(e / r1) * kLd + e % r1] = bufW[(e / r1) * kLd + e % r1];
         __syncthreads();
+        const int sw0 = sweeps;
         Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red, off_rel, &sweeps);
+        if (threadIdx.x == 0)
+          fl += 9.0 * r1 * r1 * r1 * (sweeps - sw0) + (r1 > kCompressMin ? (double)r1 * r1 * r1 / 3.0 : 0.0);
         Free = (Sres == bufS) ? bufG : bufS;
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = fmax(Sres[k * kLd + k], 0.0);
         __syncthreads();
@@ -703,6 +750,9 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       }
       __syncthreads();
       rnew = s_r;
+      if (threadIdx.x == 0)
+        fl += 2.0 * K * K * r1 + 2.0 * r1 * r1 * K + (double)r1 * r1 * rnew + 2.0 * K * r1 * rnew +
+              2.0 * op.m * r1 * rnew + 2.0 * op.n * K * rnew;
       // (4) Z = R11^{-1} W_r (r1 x rnew) -> Free ; Ty = R^T W_r (K x rnew) -> Sres
       for (int c = threadIdx.x; c < rnew; c += blockDim.x) {
         const int ev = sel[c];
@@ -757,7 +807,10 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       break;
     }
   }
-  if (threadIdx.x == 0) dims[op.slot] = s_r;
+  if (threadIdx.x == 0) {
+    dims[op.slot] = s_r;
+    add_flops(status, kFlopTrunc, fl);
+  }
   if (trace && threadIdx.x == 0) {   // debug: per-op size and clocks
     int64_t* t = trace + kTruncTraceFields * ((int64_t)op_base + blockIdx.x);
     t[0] = op.m;
@@ -824,11 +877,11 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
     int cols = (int)((dev::kLdsBytes - tri_bytes) / ((size_t)max_leaf * sizeof(C)));
     cols = cols > dev::kTriMaxCols ? dev::kTriMaxCols : cols;
     const size_t sh = tri_bytes + (size_t)max_leaf * cols * sizeof(C);
-    dev::tri_kernel<T, C><<<w.count[kTri], 256, sh, s>>>(arena, P.tri + w.begin[kTri], dims, cols);
+    dev::tri_kernel<T, C><<<w.count[kTri], 256, sh, s>>>(arena, P.tri + w.begin[kTri], dims, cols, status);
   }
   if (w.gemm_tiles > 0) {
     dev::gemm_kernel<T, C><<<w.gemm_tiles, 256, 0, s>>>(arena, P.gemm, P.terms, P.tile_op, P.tile_ij,
-                                                      tile_base, dims);
+                                                      tile_base, dims, status);
   }
   if (w.count[kTrunc] > 0) {
     int64_t* tr = trunc_trace_buffer(nullptr);

@@ -84,6 +84,58 @@ __global__ void scatter_values_kernel(int64_t nnz, const int64_t* __restrict__ t
     arena[target[e]] = T(val[e]);
 }
 
+// arena[target[e] + shift] = T(scale * val[e]): a scaled copy of A in
+// another H-matrix of the same layout
+template <class T>
+__global__ void scatter_values_scaled_kernel(int64_t nnz, const int64_t* __restrict__ target, int64_t shift,
+                                             double scale, const double* __restrict__ val, T* __restrict__ arena) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+    arena[target[e] + shift] = T(scale * val[e]);
+}
+
+// part[2 b], part[2 b + 1] = sum over block b's fixed range of (v - u)^2 and
+// v^2 (tree order fixed by the thread index); then one block adds the
+// partial sums in order: out = {||v - u||^2, ||v||^2}, deterministic.
+constexpr int kNormBlocks = 256;
+template <class T>
+__global__ void __launch_bounds__(256) diff_norm_kernel(int64_t n, const T* __restrict__ v, const T* __restrict__ u,
+                                                        double* __restrict__ part) {
+  __shared__ double sd[256], sv[256];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = blockIdx.x * chunk, e1 = e0 + chunk < n ? e0 + chunk : n;
+  double d = 0.0, w = 0.0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const double a = double(v[e]), b = double(u[e]);
+    d += (a - b) * (a - b);
+    w += a * a;
+  }
+  sd[threadIdx.x] = d;
+  sv[threadIdx.x] = w;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sd[threadIdx.x] += sd[threadIdx.x + o];
+      sv[threadIdx.x] += sv[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd[0];
+    part[2 * blockIdx.x + 1] = sv[0];
+  }
+}
+__global__ void finish_norm_kernel(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double d = 0.0, w = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      d += part[2 * b];
+      w += part[2 * b + 1];
+    }
+    out[0] = d;
+    out[1] = w;
+  }
+}
+
 template <class T>
 __global__ void zero_kernel(T* __restrict__ p, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
@@ -229,6 +281,19 @@ hipError_t scatter_values_launch(int64_t nnz, const int64_t* target, const doubl
   return hipGetLastError();
 }
 template <class T>
+hipError_t scatter_values_scaled_launch(int64_t nnz, const int64_t* target, int64_t shift, double scale,
+                                        const double* val, T* arena, hipStream_t s) {
+  dev::scatter_values_scaled_kernel<T><<<grid_for(nnz), 256, 0, s>>>(nnz, target, shift, scale, val, arena);
+  return hipGetLastError();
+}
+size_t diff_norm_scratch_doubles() { return 2 * dev::kNormBlocks + 2; }
+template <class T>
+hipError_t diff_norm_launch(int64_t n, const T* v, const T* u, double* scratch, hipStream_t s) {
+  dev::diff_norm_kernel<T><<<dev::kNormBlocks, 256, 0, s>>>(n, v, u, scratch);
+  dev::finish_norm_kernel<<<1, 64, 0, s>>>(dev::kNormBlocks, scratch, scratch + 2 * dev::kNormBlocks);
+  return hipGetLastError();
+}
+template <class T>
 hipError_t zero_launch(T* p, int64_t n, hipStream_t s) {
   dev::zero_kernel<T><<<grid_for(n), 256, 0, s>>>(p, n);
   return hipGetLastError();
@@ -253,6 +318,9 @@ hipError_t zero_int_launch(int32_t* p, int32_t n, hipStream_t s) {
   template hipError_t scatter_perm_launch<T>(int32_t, int32_t, const int32_t*, const T*, int64_t, double*,  \
                                              int64_t, hipStream_t);                                      \
   template hipError_t scatter_values_launch<T>(int64_t, const int64_t*, const double*, T*, hipStream_t);  \
+  template hipError_t scatter_values_scaled_launch<T>(int64_t, const int64_t*, int64_t, double, const double*, \
+                                                      T*, hipStream_t);                                  \
+  template hipError_t diff_norm_launch<T>(int64_t, const T*, const T*, double*, hipStream_t);            \
   template hipError_t zero_launch<T>(T*, int64_t, hipStream_t);                                          \
   template hipError_t identity_launch<T>(T*, int32_t, hipStream_t);
 INST(float)

@@ -94,6 +94,7 @@ struct HB {
   // low-rank updates land in the low-rank leaf `root` (a block-tree node),
   // at row/column offset (roff, coff) inside it
   int32_t root = -1, roff = 0, coff = 0;
+  int32_t mat = 0;   // which H-matrix on the block tree (several share one layout)
 };
 
 struct Access {
@@ -112,7 +113,11 @@ class Planner {
   }
 
   // ------------------------------------------------------------ storage
-  void layout(int32_t kcap, const std::vector<int32_t>& nz_adm, std::vector<InitBlock>* inits) {
+  // Storage of `nmat` H-matrices on the block tree, one after the other
+  // with the same per-leaf layout (matrix m's leaf storage and rank slots are
+  // matrix 0's shifted by m * mat_stride_ and m * mat_slots_), then the
+  // staging blocks of matrix 0's admissible blocks that hold entries.
+  void layout(int32_t kcap, const std::vector<int32_t>& nz_adm, std::vector<InitBlock>* inits, int32_t nmat = 1) {
     const int32_t nleaf = (int32_t)S_.leaves.size();
     st_.off.assign(nleaf, -1);
     st_.yoff.assign(nleaf, -1);
@@ -131,6 +136,7 @@ class Planner {
     st_.identity_n = maxleaf;
     st_.identity_off = top;
     top += align((int64_t)maxleaf * maxleaf);
+    const int64_t mat_begin = top;
     for (int32_t l = 0; l < nleaf; ++l) {
       const BlockNode& b = S_.blocks[S_.leaves[l]];
       const ClusterNode& rc = S_.clusters[b.row];
@@ -153,6 +159,27 @@ class Planner {
         leaf_ybuf_[l] = new_buf(cc.leaf_first, cc.leaf_last - cc.leaf_first, 0, 0);
       }
     }
+    mat_begin_ = mat_begin;
+    mat_stride_ = top - mat_begin;
+    mat_slots_ = slots;
+    mbuf_.assign(nmat, leaf_buf_);
+    mybuf_.assign(nmat, leaf_ybuf_);
+    for (int32_t m = 1; m < nmat; ++m) {
+      for (int32_t l = 0; l < nleaf; ++l) {
+        const BlockNode& b = S_.blocks[S_.leaves[l]];
+        const ClusterNode& rc = S_.clusters[b.row];
+        const ClusterNode& cc = S_.clusters[b.col];
+        if (b.kind == kDense) {
+          mbuf_[m][l] = new_buf(rc.leaf_first, rc.leaf_last - rc.leaf_first, cc.leaf_first,
+                                cc.leaf_last - cc.leaf_first);
+        } else {
+          mbuf_[m][l] = new_buf(rc.leaf_first, rc.leaf_last - rc.leaf_first, 0, 0);
+          mybuf_[m][l] = new_buf(cc.leaf_first, cc.leaf_last - cc.leaf_first, 0, 0);
+        }
+      }
+      top += mat_stride_;
+      slots += mat_slots_;
+    }
     for (int32_t l : nz_adm) {
       const BlockNode& b = S_.blocks[S_.leaves[l]];
       HLU_REQUIRE(b.kind == kLowRank, HLU_ERR_INVALID_ARG, "planner: init block is not admissible");
@@ -170,7 +197,7 @@ class Planner {
     persistent_segs_ = nseg_;
   }
 
-  HB block(int32_t node) const {
+  HB block(int32_t node, int32_t mat = 0) const {
     const BlockNode& b = S_.blocks[node];
     const ClusterNode& rc = S_.clusters[b.row];
     const ClusterNode& cc = S_.clusters[b.col];
@@ -181,22 +208,24 @@ class Planner {
     h.r1 = rc.end;
     h.c0 = cc.begin;
     h.c1 = cc.end;
+    h.mat = mat;
     const int32_t m = rc.size(), n = cc.size();
+    const int64_t shift = (int64_t)mat * mat_stride_;
     if (b.kind == kDense) {
       const int32_t l = b.leaf_id;
-      h.D = View{st_.off[l], 1, m, m, n, m, n, rc.begin, cc.begin, leaf_buf_[l], false};
+      h.D = View{st_.off[l] + shift, 1, m, m, n, m, n, rc.begin, cc.begin, mbuf_[mat][l], false};
     } else if (b.kind == kLowRank) {
       const int32_t l = b.leaf_id;
-      h.slot = st_.slot[l];
+      h.slot = st_.slot[l] + mat * mat_slots_;
       h.cap = st_.cap[l];
-      h.X = View{st_.off[l], 1, m, m, dyn(h.slot), m, h.cap, rc.begin, -1, leaf_buf_[l], false};
-      h.Y = View{st_.yoff[l], 1, n, n, dyn(h.slot), n, h.cap, cc.begin, -1, leaf_ybuf_[l], false};
+      h.X = View{st_.off[l] + shift, 1, m, m, dyn(h.slot), m, h.cap, rc.begin, -1, mbuf_[mat][l], false};
+      h.Y = View{st_.yoff[l] + shift, 1, n, n, dyn(h.slot), n, h.cap, cc.begin, -1, mybuf_[mat][l], false};
       h.root = node;
     }
     return h;
   }
 
-  HB son(const HB& h, int i, int j) const { return block(S_.blocks[h.node].son[2 * i + j]); }
+  HB son(const HB& h, int i, int j) const { return block(S_.blocks[h.node].son[2 * i + j], h.mat); }
 
   View identity(int32_t n) const {
     return View{st_.identity_off, 1, st_.identity_n, n, n, n, n, -1, -1, -1, false};
@@ -422,44 +451,44 @@ class Planner {
     hmv(L10, false, sub_rows(V, L00.r0, L00.r1), sub_rows(W, L11.r0, L11.r1), 1.0, 1.0);
   }
 
-  // C -= A B in H-arithmetic.
-  void gemm(const HB& C, const HB& A, const HB& B) {
+  // C += alpha A B in H-arithmetic (alpha = -1: the H-LU's update).
+  void gemm(const HB& C, const HB& A, const HB& B, double alpha = -1.0) {
     if (A.kind == kLowRank) flush(A);
     if (B.kind == kLowRank) flush(B);
     if (A.kind == kLowRank) {
       View W = temp_spatial(C.c0, C.c1 - C.c0, A.X.cols, A.cap);
       hmv(B, true, A.Y, W, 1.0, 0.0);
-      add_lowrank(C, A.X, W, -1.0);
+      add_lowrank(C, A.X, W, alpha);
     } else if (B.kind == kLowRank) {
       View W = temp_spatial(C.r0, C.r1 - C.r0, B.X.cols, B.cap);
       hmv(A, false, B.X, W, 1.0, 0.0);
-      add_lowrank(C, W, B.Y, -1.0);
+      add_lowrank(C, W, B.Y, alpha);
     } else if (A.kind == kDense && B.kind == kDense) {
       if (C.kind == kDense) {
-        gemm_op(C.D, 1.0, {{A.D, B.D, -1.0}});
+        gemm_op(C.D, 1.0, {{A.D, B.D, alpha}});
       } else {
-        add_lowrank(C, A.D, transpose(B.D), -1.0);
+        add_lowrank(C, A.D, transpose(B.D), alpha);
       }
     } else if (A.kind == kDense) {  // B subdivided: rows of C form a leaf cluster
       if (C.kind == kDense) {
-        hmv(B, true, transpose(A.D), transpose(C.D), -1.0, 1.0);
+        hmv(B, true, transpose(A.D), transpose(C.D), alpha, 1.0);
       } else {
         View W = temp_spatial(C.c0, C.c1 - C.c0, A.D.rows, A.D.rows_s);
         hmv(B, true, transpose(A.D), W, 1.0, 0.0);
-        add_lowrank(C, identity(A.D.rows), W, -1.0);
+        add_lowrank(C, identity(A.D.rows), W, alpha);
       }
     } else if (B.kind == kDense) {  // A subdivided: cols of C form a leaf cluster
       if (C.kind == kDense) {
-        hmv(A, false, B.D, C.D, -1.0, 1.0);
+        hmv(A, false, B.D, C.D, alpha, 1.0);
       } else {
         View W = temp_spatial(C.r0, C.r1 - C.r0, B.D.cols, B.D.cols_s);
         hmv(A, false, B.D, W, 1.0, 0.0);
-        add_lowrank(C, W, identity(B.D.cols), -1.0);
+        add_lowrank(C, W, identity(B.D.cols), alpha);
       }
     } else if (C.kind == kSub) {
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
-          for (int k = 0; k < 2; ++k) gemm(son(C, i, j), son(A, i, k), son(B, k, j));
+          for (int k = 0; k < 2; ++k) gemm(son(C, i, j), son(A, i, k), son(B, k, j), alpha);
     } else if (C.kind == kLowRank) {
       // both factors subdivided, low-rank target: accumulate the product on
       // the four quadrants as temporary low-rank blocks, then add them to C
@@ -469,7 +498,7 @@ class Planner {
         for (int j = 0; j < 2; ++j) {
           HB Ai0 = son(A, i, 0), B0j = son(B, 0, j);
           HB Q = temp_lowrank(Ai0.r0, Ai0.r1, B0j.c0, B0j.c1);
-          for (int k = 0; k < 2; ++k) gemm(Q, son(A, i, k), son(B, k, j));
+          for (int k = 0; k < 2; ++k) gemm(Q, son(A, i, k), son(B, k, j), alpha);
           flush(Q);
           parts.push_back({Q.X, Q.Y, C.roff + Q.r0 - C.r0, C.coff + Q.c0 - C.c0, 1.0});
         }
@@ -479,6 +508,27 @@ class Planner {
       fail(HLU_ERR_INVALID_ARG, "planner: dense target with two subdivided factors");
     }
   }
+
+  // One Schulz step (Sec. 3) between matrices of the layout: with A_H in
+  // matrix 0, X_k in matrix xin and matrices 2 and xout zero,
+  //   Z := -A_H X_k;  Z += 2 I;  X_{k+1} := X_k Z    (Z in matrix 2).
+  void schulz_step(int32_t xin, int32_t xout) {
+    gemm(block(0, 2), block(0, 0), block(0, xin), -1.0);
+    flush_all();
+    for (size_t l = 0; l < S_.leaves.size(); ++l) {
+      const BlockNode& b = S_.blocks[S_.leaves[l]];
+      if (b.row != b.col) continue;
+      const HB d = block(S_.leaves[l], 2);
+      const int32_t m = d.r1 - d.r0;
+      gemm_op(d.D, 1.0, {{identity(m), identity(m), 2.0}});
+    }
+    gemm(block(0, xout), block(0, xin), block(0, 2), 1.0);
+    flush_all();
+  }
+
+  int64_t mat_stride() const { return mat_stride_; }
+  int64_t mat_begin() const { return mat_begin_; }
+  int32_t mat_slots() const { return mat_slots_; }
 
   // C += alpha X Y^T, truncating in every low-rank leaf of C.
   void add_lowrank(const HB& C, const View& X, const View& Y, double alpha) {
@@ -744,8 +794,24 @@ class Planner {
   }
 
   HB root_of(const HB& C) const {
-    if (C.root >= 0) return block(C.root);
+    if (C.root >= 0) return block(C.root, C.mat);
     return temp_hb_.at(C.root);
+  }
+
+  // key of a low-rank root among the pending updates: block-tree node and
+  // matrix, or the (negative) id of a temporary
+  int64_t root_key(const HB& C) const {
+    return C.root >= 0 ? (int64_t)C.mat * (int64_t)S_.blocks.size() + C.root : (int64_t)C.root;
+  }
+  HB root_of_key(int64_t key) const {
+    HB h;
+    if (key >= 0) {
+      h.root = (int32_t)(key % (int64_t)S_.blocks.size());
+      h.mat = (int32_t)(key / (int64_t)S_.blocks.size());
+    } else {
+      h.root = (int32_t)key;
+    }
+    return h;
   }
 
   HB quadrant(const HB& C, int32_t r0, int32_t r1, int32_t c0, int32_t c1) const {
@@ -757,6 +823,7 @@ class Planner {
     q.c0 = c0;
     q.c1 = c1;
     q.root = C.root;
+    q.mat = C.mat;
     q.roff = C.roff + (r0 - C.r0);
     q.coff = C.coff + (c0 - C.c0);
     return q;
@@ -768,14 +835,14 @@ class Planner {
   // is next read or when kMaxPending terms have accumulated.
   static constexpr size_t kMaxPending = 1;
   void defer(const HB& C, const View& X, const View& Y, double alpha) {
-    auto& v = pending_[C.root];
+    auto& v = pending_[root_key(C)];
     v.push_back({X, Y, C.roff, C.coff, alpha});
     if (v.size() >= kMaxPending) flush(C);
   }
 
   void flush(const HB& C) {
     if (C.root == -1) return;
-    auto it = pending_.find(C.root);
+    auto it = pending_.find(root_key(C));
     if (it == pending_.end()) return;
     std::vector<PartSpec> parts;
     parts.swap(it->second);
@@ -784,14 +851,10 @@ class Planner {
   }
 
   void flush_all() {
-    std::vector<int32_t> roots;
-    for (auto& kv : pending_) roots.push_back(kv.first);
-    std::sort(roots.begin(), roots.end());
-    for (int32_t r : roots) {
-      HB h;
-      h.root = r;
-      flush(h);
-    }
+    std::vector<int64_t> keys;
+    for (auto& kv : pending_) keys.push_back(kv.first);
+    std::sort(keys.begin(), keys.end());
+    for (int64_t k : keys) flush(root_of_key(k));
   }
 
  private:
@@ -938,9 +1001,12 @@ class Planner {
   Plan* P_ = nullptr;
   std::vector<int32_t> leaf_of_pos_;
   std::vector<int32_t> leaf_buf_, leaf_ybuf_, init_buf_;
+  std::vector<std::vector<int32_t>> mbuf_, mybuf_;   // per matrix: buffers of the leaves (X, then Y)
+  int64_t mat_begin_ = 0, mat_stride_ = 0;
+  int32_t mat_slots_ = 0;
   std::vector<Temp> temps_;
   std::vector<int64_t> vbegin_;   // virtual begins of temps_, filled while the plan is remapped
-  std::map<int32_t, std::vector<PartSpec>> pending_;
+  std::map<int64_t, std::vector<PartSpec>> pending_;
   std::map<int32_t, HB> temp_hb_;
   std::vector<int32_t> temp_of_buf_;
   int64_t temp_peak_ = 0;
@@ -1010,6 +1076,57 @@ void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
   solve_used = std::max(solve_used, pl.temp_used());
   st.solve_temp_elems = solve_used;
   st.total_elems = solve_base + solve_used;
+}
+
+void build_inverse_plans(const Structure& S, int32_t kcap, int32_t max_rhs, InversePlanSet* out) {
+  HLU_REQUIRE(kcap >= 1 && max_rhs >= 1, HLU_ERR_INVALID_ARG, "build_inverse_plans: bad capacity");
+  InversePlanSet& ip = *out;
+  ip = InversePlanSet{};
+  ip.kcap = kcap;
+  StoragePlan& st = ip.store;
+  Planner pl(S, st);
+  pl.kcap_ = kcap;
+  std::vector<InitBlock> inits;
+  pl.layout(kcap, {}, &inits, 4);
+  ip.mat_elems = pl.mat_stride();
+  ip.mat0_off = pl.mat_begin();
+  ip.mat_slots = pl.mat_slots();
+  // vectors (cluster order): V, W = X V, U = A_H W; then the temporaries
+  st.max_rhs = max_rhs;
+  st.nrhs_slot = st.num_slots++;
+  const int64_t vblock = ((int64_t)S.N * max_rhs + 31) & ~int64_t(31);
+  st.vec_off = st.data_elems;
+  st.vec2_off = st.vec_off + vblock;
+  ip.vec3_off = st.vec2_off + vblock;
+  const int64_t temp_base = ip.vec3_off + vblock;
+  ip.temp_slot0 = st.num_slots;
+  int64_t used = 0;
+  for (int s = 0; s < 2; ++s) {
+    pl.begin_plan(&ip.step[s], temp_base);
+    pl.schulz_step(1 + 2 * s, 3 - 2 * s);
+    pl.end_plan();
+    used = std::max(used, pl.temp_used());
+  }
+  for (int s = 0; s < 2; ++s) {
+    pl.begin_plan(&ip.apply[s], temp_base);
+    {
+      const int32_t vb = pl.vector_buf(), wb = pl.vector_buf();
+      pl.hmv(pl.block(0, 1 + 2 * s), false, pl.vector_view(st.vec_off, max_rhs, st.nrhs_slot, vb),
+             pl.vector_view(st.vec2_off, max_rhs, st.nrhs_slot, wb), 1.0, 0.0);
+    }
+    pl.end_plan();
+    used = std::max(used, pl.temp_used());
+  }
+  pl.begin_plan(&ip.amul, temp_base);
+  {
+    const int32_t wb = pl.vector_buf(), ub = pl.vector_buf();
+    pl.hmv(pl.block(0, 0), false, pl.vector_view(st.vec2_off, max_rhs, st.nrhs_slot, wb),
+           pl.vector_view(ip.vec3_off, max_rhs, st.nrhs_slot, ub), 1.0, 0.0);
+  }
+  pl.end_plan();
+  used = std::max(used, pl.temp_used());
+  st.temp_elems = used;
+  st.total_elems = temp_base + used;
 }
 
 }  // namespace hlu

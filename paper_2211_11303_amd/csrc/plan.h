@@ -69,6 +69,16 @@ struct FillOp {
 
 enum OpKind : int32_t { kGetrf = 0, kTri = 1, kGemm = 2, kTrunc = 3, kFill = 4, kNumKinds = 5 };
 
+// Status words of a factor workspace (int32): [0] zero pivots, [1] rank
+// overflows, [2] truncations past their round bound; from word kFlopWord0
+// on, kFlopSpread uint64 counters per kind of the nominal flops executed
+// (summed on the host).
+constexpr int kStatusWords = 256;
+constexpr int kFlopWord0 = 16;
+constexpr int kFlopSpread = 16;
+enum FlopKind : int { kFlopGetrf = 0, kFlopTri = 1, kFlopGemm = 2, kFlopTrunc = 3, kNumFlopKinds = 4 };
+static_assert(kFlopWord0 + 2 * kFlopSpread * kNumFlopKinds <= kStatusWords, "status words");
+
 // One wave: for each kind, a range of ops in the kind's array.
 struct Wave {
   int32_t begin[kNumKinds];
@@ -131,6 +141,25 @@ struct InitBlock {
   int64_t off;        // staging block (m x n, column-major) in the arena
 };
 
+// Plans of the H-matrix inverse by the Schulz iteration (Sec. 3): four
+// H-matrices on one block tree share the per-leaf layout of store (matrix
+// m's leaf l at store.off[l] + m * mat_elems, its rank in slot
+// store.slot[l] + m * mat_slots): 0 = A_H, 1 and 3 = the iterates X_k, 2 =
+// Z = 2I - A_H X_k.  step[s] maps X in matrix 1 + 2s to matrix 3 - 2s
+// (matrix 2 and the target zero, ranks from temp_slot0 on zero);
+// apply[s] forms W = X V for X in matrix 1 + 2s (V at store.vec_off, W at
+// store.vec2_off, cluster order); amul forms U = A_H W at vec3_off.
+struct InversePlanSet {
+  StoragePlan store;
+  Plan step[2], apply[2], amul;
+  int64_t mat0_off = 0;     // first element of matrix 0's leaves
+  int64_t mat_elems = 0;
+  int32_t mat_slots = 0;
+  int32_t temp_slot0 = 0;
+  int64_t vec3_off = 0;
+  int32_t kcap = 64;
+};
+
 struct PlanSet {
   StoragePlan store;
   std::vector<InitBlock> init_blocks;
@@ -141,6 +170,7 @@ struct PlanSet {
 // Builds storage and the three plans.  kcap: rank capacity per block
 // (capped at min(m, n)); max_rhs: column capacity of the solve plans;
 // nonzero_admissible: leaf ordinals of admissible blocks holding entries.
+void build_inverse_plans(const Structure& S, int32_t kcap, int32_t max_rhs, InversePlanSet* out);
 void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
                  const std::vector<int32_t>& nonzero_admissible, PlanSet* out);
 

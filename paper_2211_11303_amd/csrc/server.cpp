@@ -118,17 +118,22 @@ void ensure_mesh(hlu_server_s* S, int32_t n) {
   Mesh m;
   hlu_status st = hlu_build(&csr, mid.data(), S->o.eta, S->o.leaf, &m.proto);
   if (st != HLU_OK) fail(st, hlu::get_error());
-  size_t dev = 0;
+  size_t dev = 0, plans = 0;
   st = hlu_device_bytes(m.proto, &S->o.factor, &dev);   // plans the structure (host)
+  if (st == HLU_OK) st = hlu_plan_device_bytes(m.proto, &S->o.factor, &plans);
   if (st != HLU_OK) {
     hlu_destroy(m.proto);
     fail(st, hlu::get_error());
   }
   m.N = N;
   m.nnz = (int64_t)ci.size();
-  m.factor_bytes = dev + (size_t)(N + 1) * 4 + (size_t)m.nnz * 12;
+  // a factor's own bytes; the structure's shared plans are counted once per
+  // mesh, for as long as the server lives
+  m.factor_bytes = dev - plans + (size_t)(N + 1) * 4 + (size_t)m.nnz * 12;
   std::lock_guard<std::mutex> lk(S->mu);
   S->meshes[n] = m;
+  S->used += plans;
+  S->st.peak_bytes = std::max(S->st.peak_bytes, S->used);
 }
 
 // Under mu: drop least recently used idle factors until `need` more bytes fit.

@@ -185,6 +185,27 @@ class HLU:
         self.prec = prec
         return self
 
+    def hlu_inverse_workspace_bytes(self, eps, max_rank=0, prec="fp64"):
+        o = self._opts(eps, max_rank, prec)
+        b = ctypes.c_size_t()
+        L.check(L.lib().hlu_inverse_workspace_bytes(self.handle, ctypes.byref(o), ctypes.byref(b)))
+        return b.value
+
+    def hlu_inverse(self, probe, eps, max_rank=0, prec="fp64", tol=1e-6, max_iters=60, stream=None):
+        """Schulz inverse B_H (hlu_inverse) into the handle; probe: device
+        block (nprobe, N) in the natural order.  Returns the info dict;
+        afterwards hlu_solve / gmres_solve apply B_H."""
+        nbytes = self.hlu_inverse_workspace_bytes(eps, max_rank, prec)
+        self.hlu_bind_workspace(nbytes)
+        p2, nprobe = _as_block(probe, self.n)
+        o = self._opts(eps, max_rank, prec)
+        so = L.SchulzOpts(int(max_iters), float(tol))
+        info = L.SchulzInfo()
+        L.check(L.lib().hlu_inverse(self.handle, ctypes.byref(o), ctypes.byref(so), _dev_ptr(p2), nprobe,
+                                    ctypes.byref(info), _stream(stream)))
+        self.prec = prec
+        return {name: getattr(info, name) for name, _ in info._fields_}
+
     def hlu_solve(self, b, x=None, stream=None):
         torch = _torch()
         b2, nrhs = _as_block(b, self.n)
@@ -271,6 +292,20 @@ def gmres_solve(A, b, precond=None, restart=50, tol=1e-8, max_iters=1000, stream
     infos = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, abs_res=i.abs_res) for i in info]
     if st != L.HLU_OK and (raise_on_fail or st != -5):
         L.check(st)
+    return x.reshape(b.shape), infos
+
+
+def hlu_richardson(A, b, precond, tol=1e-8, max_iters=100, stream=None):
+    """Algorithm 1, steps III-IV (hlu_richardson): returns (x, infos) with
+    infos a list of dicts (iters, converged, relres, abs_res) per column."""
+    torch = _torch()
+    b2, nrhs = _as_block(b, A.n)
+    x = torch.zeros_like(b2)
+    work = torch.empty(L.lib().hlu_richardson_workspace_bytes(A.n, nrhs), dtype=torch.uint8, device="cuda")
+    info = (L.GmresInfo * nrhs)()
+    L.check(L.lib().hlu_richardson(A.handle, _dev_ptr(b2), _dev_ptr(x), nrhs, A.n, precond.handle, float(tol),
+                                   int(max_iters), info, _dev_ptr(work), work.numel(), _stream(stream)))
+    infos = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, abs_res=i.abs_res) for i in info]
     return x.reshape(b.shape), infos
 
 

@@ -39,3 +39,25 @@ def gpu_factor_error(H, A_csr, perm, nprobe=8, seed=12345):
     y = H.hlu_apply_lu(vt).cpu().numpy().T
     ref = A_csr @ v
     return float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+
+
+def fp32_factor_bound(e_or, e_st, leaf):
+    """Parity bound for the factor error of an FP32 H-LU (factors stored in
+    FP32, dense task arithmetic in FP32 or FP64), derived from the FP32 unit
+    roundoff through the oracle itself:
+
+      e_round = sqrt(e_st^2 - e_or^2) is the error that rounding the oracle's
+        own factors to FP32 adds (e_st: the oracle's factor error with its
+        factors rounded to FP32; truncation and rounding errors are
+        uncorrelated, so their squares add);
+      FP32 arithmetic inside a task rounds inner products of length at most
+        `leaf` (dense leaves; ranks stay below the 64-column block capacity),
+        whose error grows like sqrt(leaf) u32 |terms| in the probabilistic
+        rounding model, i.e. sqrt(leaf) times the storage rounding of the
+        same entries;
+
+    so e_fp32 <= 2 e_or + (1 + sqrt(leaf)) e_round, the FP64 bar (2x the
+    oracle's truncation error) plus the rounding terms."""
+    import math
+    e_round = math.sqrt(max(e_st * e_st - e_or * e_or, 0.0))
+    return 2.0 * e_or + (1.0 + math.sqrt(leaf)) * e_round

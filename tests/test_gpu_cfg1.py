@@ -1,9 +1,12 @@
-"""16^3 cube workload on the GPU (FP64 H-LU) against stored oracle results.
+"""16^3 cube workload on the GPU (FP64 and FP32 H-LU) against stored oracle
+results.
 
 The expected values in tests/golden/oracle_cfg1_*.json were written by
 tests/golden/make_oracle_cfg1.py, which calls only the oracle.  Parity bar:
-factor error within 2x the oracle's; GMRES(50) iterations within +-1 of the
-oracle's for every right-hand side; final relative residual <= 1e-8."""
+factor error within 2x the oracle's (FP64) or within
+gpu_util.fp32_factor_bound (FP32: 2x the oracle's plus the FP32 rounding
+terms); GMRES(50) iterations within +-1 of the oracle's for every
+right-hand side, in both precisions; final relative residual <= 1e-8."""
 import json
 import os
 
@@ -24,28 +27,37 @@ def problem16():
     return out
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("kappa,eps", [(4.0, 1e-4), (4.0, 1e-6), (8.0, 1e-4), (8.0, 1e-6)])
-def test_cfg1_against_oracle(gpu, problem16, kappa, eps):
+def test_cfg1_against_oracle(gpu, problem16, kappa, eps, prec):
     import scipy.sparse as sp
     import torch
     from paper_2211_11303_amd import hlu, inputs
-    from gpu_util import gpu_factor_error
+    from gpu_util import fp32_factor_bound, gpu_factor_error, oracle_problem
+    d, _ = oracle_problem(16, kappa, 64)
     g = json.load(open(os.path.join(GOLDEN, f"oracle_cfg1_k{int(kappa)}_e{eps:.0e}.json")))
     A, (rp, ci, va, mid) = problem16[kappa]
-    H = hlu.HLU(rp, ci, va, mid, 2.0, 64).hlu_factor(eps, prec="fp64")
+    H = hlu.HLU(rp, ci, va, mid, 2.0, 64).hlu_factor(eps, prec=prec)
     st = H.hlu_export_structure()
     Acsr = sp.csr_matrix((va, ci, rp), shape=(A.n, A.n))
     e_gpu = gpu_factor_error(H, Acsr, st["perm"])
-    assert e_gpu <= 2 * g["factor_error"] + 1e-12, (e_gpu, g["factor_error"])
+    bar = (2 * g["factor_error"] + 1e-12 if prec == "fp64"
+           else fp32_factor_bound(g["factor_error"], g["factor_error_fp32_storage"], 64))
+    assert e_gpu <= bar, (e_gpu, g["factor_error"], bar)
     for seed in (0, 1, 2):
         X = inputs.exact_solution_cols(A.n, 8, seed=seed)
-        B = A.hlu_spmv(torch.tensor(X, device="cuda"))
-        x, infos = hlu.gmres_solve(A, B, H, restart=50, tol=1e-8)
+        Bh = (d.A @ X.T).T.copy()   # the oracle's right-hand sides, bit for bit
+        x, infos = hlu.gmres_solve(A, torch.tensor(Bh, device="cuda"), H, restart=50, tol=1e-8)
         xg = x.cpu().numpy()
-        Bh = B.cpu().numpy()
         for c in range(8):
             ref = next(s for s in g["solves"] if s["seed"] == seed and s["col"] == c)
             relres = np.linalg.norm(Acsr @ xg[c] - Bh[c]) / np.linalg.norm(Bh[c])
             assert infos[c]["converged"] and relres <= 1e-8
             assert abs(infos[c]["iters"] - ref["iters"]) <= 1, (seed, c, infos[c], ref)
-            assert np.linalg.norm(xg[c] - X[c]) <= 10 * max(ref["err"], 1e-8) * np.linalg.norm(X[c])
+            # error against x*: both solutions meet the same residual
+            # tolerance; the oracle's err/relres measures how this system
+            # amplifies a residual, so the GPU's error is bounded through its
+            # own final residual (10x slack)
+            amp = ref["err"] / max(ref["relres"], 1e-300)
+            err = np.linalg.norm(xg[c] - X[c]) / np.linalg.norm(X[c])
+            assert err <= 10 * max(ref["err"], amp * relres), (seed, c, err, ref["err"], relres)

@@ -1,0 +1,87 @@
+"""H-matrix inverse by the Schulz iteration (hlu_inverse) against the
+oracle's (oracle/hinverse.py) on the same probe block and the same
+truncation rule.
+
+Bars: the iteration stops after the same number of Schulz steps within +-1;
+the final probed residual rho = ||(I - A_H B_H) Omega||_F / ||Omega||_F
+within 2x the oracle's (FP64) -- below tol on both sides when tol is
+reached -- and, for FP32 storage, within 2x the oracle's plus the FP32
+rounding of the product chain (rho + 64 u32 ||B_H||-scale, bounded here by
+1e-5); GMRES preconditioned by B_H: iterations within +-1 of the oracle's
+GMRES with the oracle's B_H, true relative residual <= tol."""
+import numpy as np
+import pytest
+
+from gpu_util import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_inverse(n, kappa, leaf, eps, tol, max_iters):
+    from oracle.hinverse import HInverse
+    d, s = oracle_problem(n, kappa, leaf)
+    return d, s, HInverse(s, d.A, eps).compute(tol=tol, max_iters=max_iters)
+
+
+def _probe(N, perm):
+    import torch
+    Om = np.random.default_rng(12345).standard_normal((N, 8))   # the oracle's probe, cluster order
+    v = np.empty_like(Om)
+    v[perm] = Om
+    return torch.tensor(v.T.copy(), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("n,kappa,leaf,eps,tol,prec", [(4, 2.0, 32, 1e-6, 1e-4, "fp64"),
+                                                        (4, 2.0, 32, 1e-3, 1e-12, "fp64"),
+                                                        (4, 5.0, 32, 1e-4, 1e-12, "fp64"),
+                                                        (4, 2.0, 32, 1e-6, 1e-4, "fp32")])
+def test_schulz_inverse_against_oracle(gpu, n, kappa, leaf, eps, tol, prec):
+    import torch
+    from oracle.krylov import gmres as oracle_gmres
+    from paper_2211_11303_amd import hlu, inputs
+    d, s, o = _oracle_inverse(n, kappa, leaf, eps, tol, 60)
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, kappa)
+    A = hlu.SpMat(rp, ci, va)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, leaf)
+    info = H.hlu_inverse(_probe(A.n, s.perm), eps, prec=prec, tol=tol, max_iters=60)
+    print(f"n={n} eps={eps:g} {prec}: gpu steps {info['iters']} rho {info['residual']:.3e} "
+          f"(start {info['residual0']:.3e}); oracle steps {o.iterations} rho {o.history[-1]:.3e} "
+          f"(start {o.history[0]:.3e})", flush=True)
+    # the start's residual is the same quantity on both sides (FP32 storage
+    # rounds the probe block and the products to FP32)
+    assert abs(info["residual0"] - o.history[0]) <= (1e-10 if prec == "fp64" else 1e-6) * o.history[0]
+    assert abs(info["iters"] - o.iterations) <= 1, (info, o.iterations)
+    floor = 0.0 if prec == "fp64" else 1e-5
+    assert info["residual"] <= 2 * o.history[-1] + floor, (info, o.history[-1])
+    # B_H as the GMRES preconditioner
+    X = inputs.exact_solution_cols(A.n, 3, seed=1)
+    B = (d.A @ X.T).T.copy()
+    x, infos = hlu.gmres_solve(A, torch.tensor(B, device="cuda"), H, restart=30, tol=1e-10, max_iters=500)
+    xg = x.cpu().numpy()
+    for c in range(3):
+        _, io = oracle_gmres(d.A, B[c], o.solve, restart=30, tol=1e-10, max_iters=500)
+        rel = np.linalg.norm(d.A @ xg[c] - B[c]) / np.linalg.norm(B[c])
+        print(f"   rhs {c}: gmres iters {infos[c]['iters']} (oracle {io['iters']}), relres {rel:.2e}", flush=True)
+        assert infos[c]["converged"] and rel <= 1e-10
+        assert abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
+
+
+def test_inverse_state_rules(gpu):
+    """After hlu_inverse the handle applies B_H; hlu_apply_lu is refused until
+    the next hlu_factor, after which the H-LU path is back."""
+    import torch
+    from paper_2211_11303_amd import hlu, _lib
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(4, 2.0)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, 32)
+    d, s = oracle_problem(4, 2.0, 32)
+    H.hlu_inverse(_probe(H.n, s.perm), 1e-6, tol=1e-8, max_iters=40)
+    v = torch.ones((1, H.n), dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.HluError):
+        H.hlu_apply_lu(v)
+    H.hlu_factor(1e-6)
+    y = H.hlu_solve(H.hlu_apply_lu(v))
+    assert (y - v).norm() <= 1e-9 * v.norm()
+    # too small leaves: admissible blocks hold entries, the inverse is refused
+    H2 = hlu.HLU(rp, ci, va, mid, 2.0, 8)
+    with pytest.raises(_lib.HluError):
+        H2.hlu_inverse(_probe(H.n, s.perm), 1e-6)

@@ -68,9 +68,12 @@ def test_admission_evicts_and_rejects(gpu):
     import ctypes
     H = hlu.HLU(rp, ci, va, mid, 2.0, 32)
     o = L.FactorOpts(1e-6, 32, L.HLU_FP64)
-    nb = ctypes.c_size_t()
+    nb, npl = ctypes.c_size_t(), ctypes.c_size_t()
     L.check(L.lib().hlu_device_bytes(H.handle, ctypes.byref(o), ctypes.byref(nb)))
-    budget = int(nb.value * 1.6)
+    L.check(L.lib().hlu_plan_device_bytes(H.handle, ctypes.byref(o), ctypes.byref(npl)))
+    assert 0 < npl.value < nb.value
+    # the mesh's shared plans once, and room for 1.6 factors
+    budget = int(npl.value + (nb.value - npl.value) * 1.6)
     srv = hlu.Server(workers=2, max_batch_rhs=4, hbm_budget=budget, leaf=32, eps=1e-6, max_rank=32,
                      prec="fp64", restart=30, tol=1e-10)
     N = inputs.num_interior_edges(6)
@@ -136,3 +139,33 @@ def test_refinement_near_resonance(gpu):
     assert st["refinements"] == 1 and st["cache_hits"] == 1, st
     assert i2[0]["iters"] == infos[0]["iters"]
     assert np.abs(x2[0] - x[0]).max() <= 1e-14 * np.abs(x[0]).max()
+
+
+@pytest.mark.parametrize("prec,eps", [("fp64", 1e-6), ("fp32", 1e-4)])
+def test_requests_against_oracle(gpu, prec, eps):
+    """Every request answered by a mixed serving run against the oracle's
+    GMRES on the same right-hand sides with the oracle's H-LU at the same
+    eps and leaf: iterations within +-1 per column, true relative residual
+    <= tol, and ||x - x_oracle|| <= 3 max(e_or, a res) relative (e_or the
+    oracle's error against x*, a = e_or / its final residual, res the
+    server's final residual; both solve to the same residual tolerance)."""
+    from gpu_util import oracle_solve
+    from paper_2211_11303_amd import hlu
+    reqs = _request_set()
+    leaf = 32
+    srv = hlu.Server(workers=3, max_batch_rhs=8, hbm_budget=8 << 30, leaf=leaf, eps=eps, prec=prec,
+                     restart=30, tol=1e-10)
+    tickets = [srv.hlu_server_submit(r["n"], r["kappa"], r["b"]) for r in reqs]
+    out = [srv.hlu_server_wait(t) for t in tickets]
+    srv.close()
+    for i, (r, (x, infos, _, _)) in enumerate(zip(reqs, out)):
+        for c in range(len(x)):
+            xo, io = oracle_solve(r["n"], r["kappa"], leaf, eps, r["b"][c], 30, 1e-10)
+            rel = np.linalg.norm(r["A"] @ x[c] - r["b"][c]) / np.linalg.norm(r["b"][c])
+            err_or = np.linalg.norm(xo - r["xs"][c]) / np.linalg.norm(r["xs"][c])
+            d_or = np.linalg.norm(x[c] - xo) / np.linalg.norm(xo)
+            assert infos[c]["converged"] and rel <= 1e-10, (i, c, infos[c], rel)
+            assert abs(infos[c]["iters"] - io["iters"]) <= 1, (i, c, infos[c], io)
+            rel_or = np.linalg.norm(r["A"] @ xo - r["b"][c]) / np.linalg.norm(r["b"][c])
+            amp = err_or / max(rel_or, 1e-300)   # residual amplification (see test_gpu_cfg2)
+            assert d_or <= 3 * max(err_or, amp * rel, 1e-14), (i, c, d_or, err_or)
