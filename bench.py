@@ -62,7 +62,7 @@ def parse():
                    help="refinement levels k (n = 2^(k-1) cubes per side)")
     p.add_argument("--table1-max-iters", type=int, default=500)
     p.add_argument("--batch-count", type=int, default=64)
-    p.add_argument("--batch-leaves", type=str, default="32,48,64",
+    p.add_argument("--batch-leaves", type=str, default="32,48,64,96,128",
                    help="leaf sizes the autotuner measures per mesh size (one value: fixed leaf)")
     p.add_argument("--serve", action="store_true",
                    help="serving workload instead: Poisson arrivals of solve requests answered by hlu_server")

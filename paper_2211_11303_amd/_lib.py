@@ -4,7 +4,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhlu.so")
+# HLU_LIB selects another build of the library (the host-sanitizer build in
+# the CPU tests); the default is the in-tree libhlu.so.
+LIB_PATH = os.environ.get("HLU_LIB") or os.path.join(HERE, "libhlu.so")
 
 c_int32 = ctypes.c_int32
 c_int64 = ctypes.c_int64

@@ -23,11 +23,24 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-I" + os.path.join(HERE, "..", "include")]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the same
+# sources (libhlu_asan.so): every -fsanitize flag applies to the host pass
+# only, the device code is built as usual.  For CPU runs of the host logic
+# (planner, schedules, assembly) with the ASan runtime preloaded; see
+# tests/test_lib_asan.py.
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+ASAN_OUT = os.path.join(HERE, "libhlu_asan.so")
+ASAN_BUILD_DIR = os.path.join(HERE, "_build_asan")
+
+
+def _compile(src, sanitize=False):
+    bdir = ASAN_BUILD_DIR if sanitize else BUILD_DIR
+    obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+    flags = COMMON + (SAN_HOST if sanitize else [])
+    cmd = [HIPCC] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + flags + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     errs = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
     if r.returncode != 0:
@@ -35,21 +48,22 @@ def _compile(src):
     return obj
 
 
-def build(verbose=False):
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose=False, sanitize=False):
+    bdir, out = (ASAN_BUILD_DIR, ASAN_OUT) if sanitize else (BUILD_DIR, OUT)
+    os.makedirs(bdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp] + objs
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    tmp = out + ".tmp"
+    cmd = [HIPCC, "-shared", "--offload-arch=gfx950"] + (SAN_HOST if sanitize else []) + ["-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed\n" + r.stderr)
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--asan" in sys.argv)
     sys.exit(0)

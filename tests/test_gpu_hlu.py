@@ -186,3 +186,29 @@ def test_autotune_leaf(gpu):
     best, secs = hlu.hlu_autotune_leaf(4, 2.0, leaves=leaves, eps=1e-6, prec="fp64", restart=30, tol=1e-10)
     assert all(np.isfinite(s) and s > 0 for s in secs), secs
     assert best == leaves[int(np.argmin(secs))]
+
+
+@pytest.mark.parametrize("leaf", [96, 128])
+def test_large_leaves_against_oracle(gpu, leaf):
+    """Leaf sizes above the chain's 64 register rows (the autotuner's larger
+    candidates): FP32 factor within the FP32 bound of the oracle's, GMRES
+    iterations +-1."""
+    import torch
+    hlu, inputs = _lib()
+    n, kappa, eps = 8, 4.0, 1e-3
+    A, (rp, ci, va, mid) = _setup(n, kappa, leaf)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(eps, prec="fp32")
+    d, s = oracle_problem(n, kappa, leaf)
+    o = oracle_factor(n, kappa, leaf, eps)
+    e_gpu = gpu_factor_error(H, d.A, s.perm)
+    bar = fp32_factor_bound(o.factor_error(), o.factor_error(storage=np.float32), leaf)
+    assert e_gpu <= bar, (e_gpu, o.factor_error(), bar)
+    X = inputs.exact_solution_cols(A.n, 3, seed=5)
+    B = (d.A @ X.T).T.copy()
+    x, infos = hlu.gmres_solve(A, torch.tensor(B, device="cuda"), H, restart=50, tol=1e-8)
+    xg = x.cpu().numpy()
+    for c in range(3):
+        relres = np.linalg.norm(d.A @ xg[c] - B[c]) / np.linalg.norm(B[c])
+        assert infos[c]["converged"] and relres <= 1e-8
+        _, io = oracle_solve(n, kappa, leaf, eps, B[c], 50, 1e-8)
+        assert abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
