@@ -155,6 +155,17 @@ hlu_status hlu_kuhn_sizes(int32_t n, int32_t* N, int64_t* nnz);
  * p_tail + p_head of each edge midpoint (row-major N x 3). */
 hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col,
                              double* val, int32_t* mid2);
+/* The same with a piecewise constant coefficient of the curl-curl term
+ * (the 1/mu of eq. (1); beta of Sec. 2.1, a magnet block of Example 3):
+ * tetrahedra of the cubes (i, j, k) with beta_box[0] <= i < beta_box[3],
+ * beta_box[1] <= j < beta_box[4], beta_box[2] <= k < beta_box[5] (host, 6
+ * cube indices; NULL: none) get K scaled by beta_in > 0, the others by 1. */
+hlu_status hlu_kuhn_assemble_beta(int32_t n, double kappa, const int32_t* beta_box, double beta_in,
+                                  int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2);
+/* Support box of every interior edge's basis function: the bounding box of
+ * the tetrahedra containing the edge, in doubled lattice units (those of
+ * mid2), lo2 and hi2 host N x 3.  For hlu_build_boxes. */
+hlu_status hlu_kuhn_support_boxes(int32_t n, int32_t* lo2, int32_t* hi2);
 
 /* Right-hand side of the weak form (Sec. 2.1) for a constant source field
  * J[3] (Example 1: J_S = (0, 0, 1)): b[j] = <J, Phi_j> over the interior
@@ -180,6 +191,14 @@ hlu_status hlu_spmv(hlu_spmat A, const double* d_x, double* d_y, int32_t nrhs, i
  * leaf_size indices); eta: admissibility parameter (min diam <= eta dist). */
 hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t leaf_size,
                      hlu_handle* out);
+/* hlu_build with the admissibility test (Sec. 3, Definition 1) on given
+ * boxes instead of the midpoint boxes: box_lo2/box_hi2 host N x 3 (doubled
+ * lattice units, each containing its index's midpoint), e.g. the supports
+ * of the basis functions (hlu_kuhn_support_boxes).  A cluster's box is the
+ * union of its indices' boxes; the cluster tree is still split on the
+ * midpoints.  Admissible blocks then hold no matrix entry at all. */
+hlu_status hlu_build_boxes(const hlu_csr* A, const int32_t* mid2, const int32_t* box_lo2,
+                           const int32_t* box_hi2, double eta, int32_t leaf_size, hlu_handle* out);
 
 /* A new handle for a matrix with exactly the sparsity pattern of proto's
  * (same n, row_ptr and col; values may differ, e.g. another kappa on the
@@ -195,6 +214,17 @@ void hlu_destroy(hlu_handle h);
 
 /* Device bytes hlu_factor needs for these options (plans the schedule). */
 hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
+
+/* Caller-owned memory for the persistent H-solve's buffers (triangle
+ * inverses, stacked operators, gather records, T products, flags; Algorithm
+ * 1, step III).  Without it the library allocates them on the first solve.
+ * hlu_solve_workspace_bytes: bytes for options o (the rank capacity decides
+ * the schedule).  hlu_bind_solve_workspace: d_work device memory, 256-byte
+ * aligned, at least that many bytes, owned by the caller and used until the
+ * handle is destroyed or bound again (NULL, 0 returns to library-owned
+ * buffers); the next solve rebuilds its buffers there. */
+hlu_status hlu_solve_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes);
+hlu_status hlu_bind_solve_workspace(hlu_handle h, void* d_work, size_t bytes);
 
 /* All device bytes a factored handle holds for these options: the bound
  * workspace, the library-owned buffers of its own solves, its matrix values,

@@ -73,15 +73,36 @@ def local_to_global_edges(mesh):
     return idx
 
 
-class Discretisation:
-    """K, M on all edges; A = K - kappa^2 M on interior edges (CSR, FP64)."""
+def cube_of_tet(mesh):
+    """Cube index (i, j, k) of every tetrahedron: its first vertex is the
+    lowest corner of the cube it was cut from."""
+    return mesh.coords[mesh.tets[:, 0]]
 
-    def __init__(self, n, kappa):
+
+class Discretisation:
+    """K, M on all edges; A = K - kappa^2 M on interior edges (CSR, FP64).
+
+    ``beta_box = (i0, j0, k0, i1, j1, k1)`` with ``beta_in``: the curl-curl
+    term carries the coefficient beta (eq. (5) has beta = 1; Sec. 2.1 allows
+    a piecewise constant one, e.g. a magnetic block as in Example 3) equal
+    to ``beta_in`` on the tetrahedra of the cubes i0 <= i < i1, j0 <= j < j1,
+    k0 <= k < k1 and 1 elsewhere, so K_ij = sum_T beta_T int_T curl Phi_i .
+    curl Phi_j.  Only the values change; the pattern stays that of beta = 1."""
+
+    def __init__(self, n, kappa, beta_box=None, beta_in=1.0):
         self.mesh = KuhnMesh(n)
         self.kappa = float(kappa)
         vol, g = element_geometry(self.mesh)
         self.volumes = vol
         Kl, Ml = element_matrices(vol, g)
+        self.beta = np.ones(len(vol))
+        if beta_box is not None:
+            lo = np.asarray(beta_box[:3])
+            hi = np.asarray(beta_box[3:])
+            c = cube_of_tet(self.mesh)
+            inside = np.all((c >= lo) & (c < hi), axis=1)
+            self.beta[inside] = float(beta_in)
+        Kl = Kl * self.beta[:, None, None]
         l2g = local_to_global_edges(self.mesh)
         E = len(self.mesh.edges)
         rows = np.repeat(l2g, 6, axis=1).ravel()

@@ -17,7 +17,11 @@ arithmetic on doubled lattice midpoints c = p_tail + p_head):
 * admissibility of a block (tau, sigma): dist > 0 and
   min(diam(tau), diam(sigma)) <= eta * dist, diam being the Euclidean
   diagonal of the tight box and dist the Euclidean gap between the two boxes
-  (compared in squares, exactly).
+  (compared in squares, exactly).  The box of a cluster is the tight box of
+  its midpoints, or, when a box is given for every index (e.g. the support
+  of its basis function, as Definition 1 measures clusters by the supports
+  of their basis functions), the bounding box of its indices' boxes; the
+  splitting above always uses the midpoints.
 * block tree: from (root, root); an admissible block is a low-rank leaf;
   otherwise, if tau or sigma is a leaf cluster the block is a dense leaf;
   otherwise it splits into the four products of the sons.
@@ -27,11 +31,12 @@ import numpy as np
 
 
 class Cluster:
-    __slots__ = ("begin", "end", "lo", "hi", "sons", "level", "id")
+    __slots__ = ("begin", "end", "lo", "hi", "alo", "ahi", "sons", "level", "id")
 
     def __init__(self, begin, end, lo, hi, level):
         self.begin, self.end = begin, end
         self.lo, self.hi = lo, hi
+        self.alo, self.ahi = lo, hi       # box of the admissibility test
         self.sons = []
         self.level = level
         self.id = -1
@@ -45,10 +50,11 @@ class Cluster:
         return not self.sons
 
 
-def build_cluster_tree(mid2, leaf):
+def build_cluster_tree(mid2, leaf, boxes=None):
     """Return (root, perm, clusters in pre-order).
 
     ``perm[i]`` is the natural index of the i-th index in cluster order.
+    ``boxes = (lo2, hi2)`` (N x 3 each): the boxes of the admissibility test.
     """
     mid2 = np.asarray(mid2, dtype=np.int64)
     N = len(mid2)
@@ -60,6 +66,9 @@ def build_cluster_tree(mid2, leaf):
         lo = pts.min(axis=0)
         hi = pts.max(axis=0)
         c = Cluster(begin, begin + len(idx), lo, hi, level)
+        if boxes is not None:
+            c.alo = np.asarray(boxes[0], dtype=np.int64)[idx].min(axis=0)
+            c.ahi = np.asarray(boxes[1], dtype=np.int64)[idx].max(axis=0)
         c.id = len(clusters)
         clusters.append(c)
         if len(idx) <= leaf:
@@ -79,12 +88,12 @@ def build_cluster_tree(mid2, leaf):
 
 
 def diam2(c):
-    d = c.hi - c.lo
+    d = c.ahi - c.alo
     return int(d @ d)
 
 
 def dist2(a, b):
-    gap = np.maximum(0, np.maximum(b.lo - a.hi, a.lo - b.hi))
+    gap = np.maximum(0, np.maximum(b.alo - a.ahi, a.alo - b.ahi))
     return int(gap @ gap)
 
 
@@ -130,10 +139,10 @@ def build_block_tree(root, eta):
 class Structure:
     """Cluster tree + block tree of one problem."""
 
-    def __init__(self, mid2, leaf, eta=2.0):
+    def __init__(self, mid2, leaf, eta=2.0, boxes=None):
         self.leaf = int(leaf)
         self.eta = float(eta)
-        self.root, self.perm, self.clusters = build_cluster_tree(mid2, leaf)
+        self.root, self.perm, self.clusters = build_cluster_tree(mid2, leaf, boxes)
         self.block_root, self.block_leaves = build_block_tree(self.root, eta)
         self.N = len(self.perm)
 

@@ -109,6 +109,25 @@ class KuhnMesh:
         e = self.interior_edges
         return self.coords[e[:, 0]] + self.coords[e[:, 1]]
 
+    def support_boxes2(self):
+        """Support of every interior edge's basis function as a box: the
+        bounding box of the tetrahedra containing the edge (the Whitney form
+        of an edge vanishes on every other tetrahedron), in doubled lattice
+        units like midpoints2; returns (lo2, hi2), each (N, 3)."""
+        N = self.num_dofs
+        lo = np.full((N, 3), np.iinfo(np.int64).max, dtype=np.int64)
+        hi = np.full((N, 3), np.iinfo(np.int64).min, dtype=np.int64)
+        for t in self.tets:
+            pts = 2 * self.coords[t]
+            tlo, thi = pts.min(axis=0), pts.max(axis=0)
+            for a in range(4):
+                for b in range(a + 1, 4):
+                    d = self.dof_of_edge[self.edge_index[(int(t[a]), int(t[b]))]]
+                    if d >= 0:
+                        lo[d] = np.minimum(lo[d], tlo)
+                        hi[d] = np.maximum(hi[d], thi)
+        return lo, hi
+
     def interior_vertices(self):
         """Ids of vertices not on the boundary, increasing."""
         c = self.coords

@@ -89,6 +89,10 @@ SIGNATURES = {
     "hlu_kuhn_sizes": (c_int32, [c_int32, P_i32, ctypes.POINTER(c_int64)]),
     "hlu_kuhn_load": (c_int32, [c_int32, P_f64, P_f64]),
     "hlu_kuhn_assemble": (c_int32, [c_int32, c_double, P_i32, P_i32, P_f64, P_i32]),
+    "hlu_kuhn_assemble_beta": (c_int32, [c_int32, c_double, P_i32, c_double, P_i32, P_i32, P_f64, P_i32]),
+    "hlu_kuhn_support_boxes": (c_int32, [c_int32, P_i32, P_i32]),
+    "hlu_build_boxes": (c_int32, [ctypes.POINTER(HluCsr), P_i32, P_i32, P_i32, c_double, c_int32,
+                                  ctypes.POINTER(c_void_p)]),
     "hlu_spmat_create": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
     "hlu_spmat_destroy": (None, [c_void_p]),
     "hlu_spmv": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_double, c_double, c_void_p]),
@@ -137,6 +141,8 @@ SIGNATURES = {
                                     ctypes.POINTER(GmresInfo), c_void_p, c_size_t, c_void_p]),
     "hlu_device_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
     "hlu_plan_device_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
+    "hlu_solve_workspace_bytes": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), ctypes.POINTER(c_size_t)]),
+    "hlu_bind_solve_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "hlu_server_create": (c_int32, [ctypes.POINTER(ServerOpts), ctypes.POINTER(c_void_p)]),
     "hlu_server_prepare": (c_int32, [c_void_p, c_int32]),
     "hlu_server_submit": (c_int32, [c_void_p, c_int32, c_double, c_int32, c_void_p, c_void_p,

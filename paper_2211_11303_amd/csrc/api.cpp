@@ -24,7 +24,9 @@ const char* get_error() { return g_last_error.c_str(); }
 
 void kuhn_load(int n, const double J[3], std::vector<double>* b);
 void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
-                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N);
+                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N,
+                   const int32_t* beta_box = nullptr, double beta_in = 1.0);
+void kuhn_support_boxes(int n, std::vector<int32_t>* lo2, std::vector<int32_t>* hi2);
 
 // ------------------------------------------------------------- layout
 WorkLayout work_layout(const PlanSet& ps, int32_t prec) {
@@ -96,37 +98,56 @@ size_t bundle_device_bytes(const Shared& sh, const PlanBundle& pb) {
   return b;
 }
 
-void SolveBufs::alloc(const ChainSched& sc, int32_t N, int32_t rhs) {
-  max_rhs = rhs;
-  inv = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.inv_elems)));   // sized for FP64
-  stack = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.stack_elems)));
-  pivots = mem.keep(dmalloc<double>((size_t)N));
-  y = mem.keep(dmalloc<double>((size_t)N * rhs));
-  tbuf = mem.keep(dmalloc<double>((size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs));
-  rstride = (int64_t)sc.max_m * rhs;
-  fbuf = mem.keep(dmalloc<double>((size_t)std::max(1, sc.num_recs) * (size_t)rstride));
+// The buffers of a persistent solve, carved in this order from one region
+// (caller memory bound with hlu_bind_solve_workspace) or each allocated by
+// the library; `take(bytes)` hands out the next piece.
+template <class Take>
+void carve_solve_bufs(SolveBufs& b, const ChainSched& sc, int32_t N, int32_t rhs, Take take) {
+  b.max_rhs = rhs;
+  b.inv = take((size_t)std::max<int64_t>(1, sc.inv_elems) * sizeof(double));   // sized for FP64
+  b.stack = take((size_t)std::max<int64_t>(1, sc.stack_elems) * sizeof(double));
+  b.pivots = static_cast<double*>(take((size_t)N * sizeof(double)));
+  b.y = static_cast<double*>(take((size_t)N * rhs * sizeof(double)));
+  b.tbuf = static_cast<double*>(take((size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs * sizeof(double)));
+  b.rstride = (int64_t)sc.max_m * rhs;
+  b.fbuf = static_cast<double*>(take((size_t)std::max(1, sc.num_recs) * (size_t)b.rstride * sizeof(double)));
   const size_t nflags = sc.tprod.size() + (size_t)sc.num_recs + 1;
-  flags = mem.keep(dmalloc<int32_t>(nflags));
-  HIP_OK(hipMemset(flags, 0, nflags * sizeof(int32_t)));
-  prog = mem.keep(dmalloc<int32_t>(2 * kMaxChains));
-  HIP_OK(hipMemset(prog, 0, 2 * kMaxChains * sizeof(int32_t)));
-  ctr = mem.keep(dmalloc<int32_t>(kSolveCtrWords));
-  HIP_OK(hipMemset(ctr, 0, kSolveCtrWords * sizeof(int32_t)));
+  b.flags = static_cast<int32_t*>(take(nflags * sizeof(int32_t)));
+  b.prog = static_cast<int32_t*>(take(2 * kMaxChains * sizeof(int32_t)));
+  b.ctr = static_cast<int32_t*>(take(kSolveCtrWords * sizeof(int32_t)));
+  b.kargs = take(kChainArgBytes);
+  if (b.flags) {
+    HIP_OK(hipMemset(b.flags, 0, nflags * sizeof(int32_t)));
+    HIP_OK(hipMemset(b.prog, 0, 2 * kMaxChains * sizeof(int32_t)));
+    HIP_OK(hipMemset(b.ctr, 0, kSolveCtrWords * sizeof(int32_t)));
+  }
+  b.epoch = 0;
+}
+
+void SolveBufs::alloc(const ChainSched& sc, int32_t N, int32_t rhs) {
+  carve_solve_bufs(*this, sc, N, rhs, [&](size_t bytes) -> void* { return mem.keep(dmalloc<unsigned char>(bytes)); });
   if (getenv("HLU_DEBUG_SOLVE_TRACE"))
     trace = mem.keep(dmalloc<int64_t>(10 * (size_t)std::max(1, sc.L) + 6 * (size_t)std::max(1, sc.num_recs)));
-  kargs = mem.keep(dmalloc<unsigned char>(kChainArgBytes));
-  epoch = 0;
+}
+
+void SolveBufs::place(const ChainSched& sc, int32_t N, int32_t rhs, void* base, size_t bytes) {
+  size_t used = 0;
+  carve_solve_bufs(*this, sc, N, rhs, [&](size_t n) -> void* {
+    void* p = static_cast<char*>(base) + used;
+    used += align256(n);
+    HLU_REQUIRE(used <= bytes, HLU_ERR_OUT_OF_MEMORY, "solve workspace too small");
+    return p;
+  });
 }
 
 size_t solve_buffer_bytes(const ChainSched& sc, int32_t N, int32_t rhs) {
-  size_t b = 0;
-  b += (size_t)std::max<int64_t>(1, sc.inv_elems) * sizeof(double);
-  b += (size_t)std::max<int64_t>(1, sc.stack_elems) * sizeof(double);
-  b += (size_t)N * sizeof(double) * (1 + rhs);
-  b += (size_t)std::max<int64_t>(1, sc.tbuf_per_rhs) * rhs * sizeof(double);
-  b += (size_t)std::max(1, sc.num_recs) * sc.max_m * rhs * sizeof(double);
-  b += (sc.tprod.size() + (size_t)sc.num_recs + 1 + 2 * kMaxChains) * sizeof(int32_t);
-  return b + kSolveCtrWords * sizeof(int32_t) + kChainArgBytes;
+  size_t used = 0;
+  SolveBufs probe;
+  carve_solve_bufs(probe, sc, N, rhs, [&](size_t n) -> void* {
+    used += align256(n);
+    return nullptr;
+  });
+  return used;
 }
 
 int64_t solve_wait_ticks() {
@@ -231,7 +252,8 @@ void ensure_targets(Shared& sh, PlanBundle& pb) {
 void ensure_solve_bufs(hlu_s* h) {
   if (h->sbuf) return;
   auto b = std::make_unique<SolveBufs>();
-  b->alloc(h->pb->sc, h->sh->S.N, kMaxRhs);
+  if (h->solve_work) b->place(h->pb->sc, h->sh->S.N, kMaxRhs, h->solve_work, h->solve_work_bytes);
+  else b->alloc(h->pb->sc, h->sh->S.N, kMaxRhs);
   h->sbuf = std::move(b);
   h->inv_ready = false;
 }
@@ -520,19 +542,36 @@ hlu_status hlu_kuhn_sizes(int32_t n, int32_t* N, int64_t* nnz) {
   });
 }
 
-hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2) {
+hlu_status hlu_kuhn_assemble_beta(int32_t n, double kappa, const int32_t* beta_box, double beta_in, int32_t* row_ptr,
+                                  int32_t* col, double* val, int32_t* mid2) {
   return guard([&] {
     HLU_REQUIRE(n >= 1 && n <= 128 && row_ptr && col && val && mid2, HLU_ERR_INVALID_ARG,
                 "hlu_kuhn_assemble: bad arguments");
     HLU_REQUIRE(std::isfinite(kappa), HLU_ERR_INVALID_ARG, "hlu_kuhn_assemble: kappa must be finite");
+    HLU_REQUIRE(!beta_box || (std::isfinite(beta_in) && beta_in > 0.0), HLU_ERR_INVALID_ARG,
+                "hlu_kuhn_assemble_beta: the coefficient must be finite and positive");
     std::vector<int32_t> rp, ci, mid;
     std::vector<double> v;
     int32_t NN;
-    kuhn_assemble(n, kappa, &rp, &ci, &v, &mid, &NN);
+    kuhn_assemble(n, kappa, &rp, &ci, &v, &mid, &NN, beta_box, beta_in);
     std::memcpy(row_ptr, rp.data(), rp.size() * sizeof(int32_t));
     std::memcpy(col, ci.data(), ci.size() * sizeof(int32_t));
     std::memcpy(val, v.data(), v.size() * sizeof(double));
     std::memcpy(mid2, mid.data(), mid.size() * sizeof(int32_t));
+  });
+}
+
+hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2) {
+  return hlu_kuhn_assemble_beta(n, kappa, nullptr, 1.0, row_ptr, col, val, mid2);
+}
+
+hlu_status hlu_kuhn_support_boxes(int32_t n, int32_t* lo2, int32_t* hi2) {
+  return guard([&] {
+    HLU_REQUIRE(n >= 1 && n <= 128 && lo2 && hi2, HLU_ERR_INVALID_ARG, "hlu_kuhn_support_boxes: bad arguments");
+    std::vector<int32_t> l, h;
+    kuhn_support_boxes(n, &l, &h);
+    std::memcpy(lo2, l.data(), l.size() * sizeof(int32_t));
+    std::memcpy(hi2, h.data(), h.size() * sizeof(int32_t));
   });
 }
 
@@ -567,15 +606,22 @@ hlu_status hlu_spmv(hlu_spmat A, const double* d_x, double* d_y, int32_t nrhs, i
   });
 }
 
-hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t leaf_size, hlu_handle* out) {
+hlu_status hlu_build_boxes(const hlu_csr* A, const int32_t* mid2, const int32_t* box_lo2, const int32_t* box_hi2,
+                           double eta, int32_t leaf_size, hlu_handle* out) {
   return guard([&] {
     HLU_REQUIRE(A && mid2 && out, HLU_ERR_INVALID_ARG, "hlu_build: NULL argument");
+    HLU_REQUIRE((box_lo2 == nullptr) == (box_hi2 == nullptr), HLU_ERR_INVALID_ARG,
+                "hlu_build_boxes: give both box corners or neither");
     HLU_REQUIRE(leaf_size >= 1 && leaf_size <= 128 && eta > 0 && std::isfinite(eta), HLU_ERR_INVALID_ARG,
                 "hlu_build: need 1 <= leaf_size <= 128, eta > 0");
     check_csr(A);
     const int32_t n = A->n;
+    if (box_lo2)
+      for (int64_t e = 0; e < 3 * (int64_t)n; ++e)
+        HLU_REQUIRE(box_lo2[e] <= mid2[e] && mid2[e] <= box_hi2[e], HLU_ERR_INVALID_ARG,
+                    "hlu_build_boxes: a box does not contain its index's midpoint");
     auto sh = std::make_shared<Shared>();
-    sh->S.build(mid2, n, leaf_size, eta);
+    sh->S.build(mid2, n, leaf_size, eta, box_lo2, box_hi2);
     sh->row_ptr.assign(A->row_ptr, A->row_ptr + n + 1);
     sh->col.assign(A->col, A->col + A->nnz);
     for (int32_t c : sh->S.leaf_clusters) sh->max_leaf = std::max(sh->max_leaf, sh->S.clusters[c].size());
@@ -606,6 +652,10 @@ hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t 
     fill_structure_stats(h.get());
     *out = h.release();
   });
+}
+
+hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t leaf_size, hlu_handle* out) {
+  return hlu_build_boxes(A, mid2, nullptr, nullptr, eta, leaf_size, out);
 }
 
 hlu_status hlu_build_shared(hlu_handle proto, const hlu_csr* A, hlu_handle* out) {
@@ -644,6 +694,30 @@ hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* b
   });
 }
 
+hlu_status hlu_solve_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes) {
+  return guard([&] {
+    HLU_REQUIRE(h && bytes, HLU_ERR_INVALID_ARG, "hlu_solve_workspace_bytes: NULL argument");
+    check_opts(o);
+    use_bundle(h, kcap_for(o));
+    *bytes = solve_buffer_bytes(h->pb->sc, h->sh->S.N, kMaxRhs);
+  });
+}
+
+hlu_status hlu_bind_solve_workspace(hlu_handle h, void* d_work, size_t bytes) {
+  return guard([&] {
+    HLU_REQUIRE(h, HLU_ERR_INVALID_ARG, "hlu_bind_solve_workspace: NULL handle");
+    HLU_REQUIRE(!h->batch, HLU_ERR_STATE, "hlu_bind_solve_workspace: handle is bound through a batch");
+    HLU_REQUIRE((d_work == nullptr) == (bytes == 0), HLU_ERR_INVALID_ARG,
+                "hlu_bind_solve_workspace: pointer and size must both be given or both be zero");
+    HLU_REQUIRE(((uintptr_t)d_work & 255) == 0, HLU_ERR_INVALID_ARG,
+                "hlu_bind_solve_workspace: the workspace must be 256-byte aligned");
+    h->solve_work = d_work;
+    h->solve_work_bytes = bytes;
+    h->sbuf.reset();   // made again, in the new memory, by the next solve
+    h->inv_ready = false;
+  });
+}
+
 hlu_status hlu_plan_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* bytes) {
   return guard([&] {
     HLU_REQUIRE(h && bytes, HLU_ERR_INVALID_ARG, "hlu_plan_device_bytes: NULL argument");
@@ -660,7 +734,7 @@ hlu_status hlu_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* byte
     use_bundle(h, kcap_for(o));
     const size_t ws = work_layout(h->pb->ps, o->prec).total;
     *bytes = ws + solve_buffer_bytes(h->pb->sc, h->sh->S.N, kMaxRhs) + h->val.size() * sizeof(double) +
-             bundle_device_bytes(*h->sh, *h->pb);
+             bundle_device_bytes(*h->sh, *h->pb);   // a bound solve workspace counts as the solve buffers
   });
 }
 

@@ -141,7 +141,8 @@ struct SolveBufs {
   int64_t rstride = 0;
   int32_t max_rhs = 0;
   int32_t epoch = 0;
-  void alloc(const ChainSched& sc, int32_t N, int32_t max_rhs);
+  void alloc(const ChainSched& sc, int32_t N, int32_t max_rhs);   // library-owned memory
+  void place(const ChainSched& sc, int32_t N, int32_t max_rhs, void* base, size_t bytes);   // caller memory
 };
 
 // Words of a persistent solve's counter block (kernels_chain.hip: claim
@@ -292,6 +293,9 @@ struct hlu_s {
   // workspace bound by hlu_bind_workspace
   void* work = nullptr;
   size_t work_bytes = 0;
+  // persistent-solve buffers bound by hlu_bind_solve_workspace (null: library-owned)
+  void* solve_work = nullptr;
+  size_t solve_work_bytes = 0;
   hlu_batch_s* batch = nullptr;          // batch whose workspace holds this factor
   // where the current factor lives (set when it is computed)
   void* arena = nullptr;

@@ -141,8 +141,11 @@ void local_dofs(const KuhnDofs& D, const int v[4][3], int32_t ld[6]) {
   }
 }
 
+// beta_box (cube indices lo[3], hi[3], half-open; null: none): the cubes
+// whose tetrahedra carry the curl-curl coefficient beta_in (1 elsewhere).
 void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
-              std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* Nout) {
+              std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* Nout, const int32_t* beta_box,
+              double beta_in) {
   KuhnDofs D(n);
   const int N = D.N;
   const double k2 = kappa * kappa;
@@ -159,13 +162,16 @@ void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<in
             for (int a = 0; a < 3; ++a) x[s][a] = double(v[s][a]) / n;
           double Kl[6][6], Ml[6][6];
           element(x, Kl, Ml);
+          const bool in_box = beta_box && i >= beta_box[0] && i < beta_box[3] && j >= beta_box[1] &&
+                              j < beta_box[4] && k >= beta_box[2] && k < beta_box[5];
+          const double beta = in_box ? beta_in : 1.0;
           int32_t ld[6];
           local_dofs(D, v, ld);
           for (int e = 0; e < 6; ++e) {
             if (ld[e] < 0) continue;
             for (int f = 0; f < 6; ++f) {
               if (ld[f] < 0) continue;
-              trip.push_back({ld[e], ld[f], Kl[e][f] - k2 * Ml[e][f]});
+              trip.push_back({ld[e], ld[f], beta * Kl[e][f] - k2 * Ml[e][f]});
             }
           }
         }
@@ -202,8 +208,37 @@ void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<in
 }  // namespace
 
 void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
-                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N) {
-  assemble(n, kappa, row_ptr, col, val, mid2, N);
+                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N, const int32_t* beta_box,
+                   double beta_in) {
+  assemble(n, kappa, row_ptr, col, val, mid2, N, beta_box, beta_in);
+}
+
+// Support box of every interior edge's basis function: the bounding box of
+// the tetrahedra that contain the edge, in doubled lattice units (the units
+// of the midpoints), lo2 and hi2 N x 3.
+void kuhn_support_boxes(int n, std::vector<int32_t>* lo2, std::vector<int32_t>* hi2) {
+  KuhnDofs D(n);
+  lo2->assign((size_t)3 * D.N, INT32_MAX);
+  hi2->assign((size_t)3 * D.N, INT32_MIN);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i)
+        for (int p = 0; p < 6; ++p) {
+          int v[4][3];
+          tet_vertices(i, j, k, p, v);
+          int32_t ld[6];
+          local_dofs(D, v, ld);
+          for (int e = 0; e < 6; ++e) {
+            if (ld[e] < 0) continue;
+            for (int s = 0; s < 4; ++s)
+              for (int a = 0; a < 3; ++a) {
+                int32_t& l = (*lo2)[3 * (size_t)ld[e] + a];
+                int32_t& h = (*hi2)[3 * (size_t)ld[e] + a];
+                l = std::min(l, 2 * v[s][a]);
+                h = std::max(h, 2 * v[s][a]);
+              }
+          }
+        }
 }
 
 // b_j = <J, Phi_j> for a constant field J (the right-hand side of the weak

@@ -8,7 +8,11 @@
 // (low-rank) leaf if dist > 0 and min(diam tau, diam sigma) <= eta dist,
 // with diam the box diagonal and dist the gap between the two boxes,
 // compared in squares; else a dense leaf if tau or sigma is a leaf cluster;
-// else it splits into the four products of the sons.
+// else it splits into the four products of the sons.  The boxes of the
+// admissibility test are the midpoint boxes, or, when a box per index is
+// given (the support of each basis function), the union of those boxes:
+// blocks of disjoint supports are admissible only if the supports, not
+// just the midpoints, are far apart.
 #include "structure.h"
 
 #include <algorithm>
@@ -21,7 +25,7 @@ namespace {
 int64_t diam2(const ClusterNode& c) {
   int64_t s = 0;
   for (int a = 0; a < 3; ++a) {
-    int64_t d = c.hi[a] - c.lo[a];
+    int64_t d = c.ahi[a] - c.alo[a];
     s += d * d;
   }
   return s;
@@ -30,7 +34,7 @@ int64_t diam2(const ClusterNode& c) {
 int64_t dist2(const ClusterNode& x, const ClusterNode& y) {
   int64_t s = 0;
   for (int a = 0; a < 3; ++a) {
-    int64_t g = std::max<int64_t>(0, std::max<int64_t>(y.lo[a] - x.hi[a], x.lo[a] - y.hi[a]));
+    int64_t g = std::max<int64_t>(0, std::max<int64_t>(y.alo[a] - x.ahi[a], x.alo[a] - y.ahi[a]));
     s += g * g;
   }
   return s;
@@ -38,7 +42,8 @@ int64_t dist2(const ClusterNode& x, const ClusterNode& y) {
 
 }  // namespace
 
-void Structure::build(const int32_t* mid2, int32_t n, int32_t leaf, double eta_) {
+void Structure::build(const int32_t* mid2, int32_t n, int32_t leaf, double eta_, const int32_t* box_lo2,
+                      const int32_t* box_hi2) {
   HLU_REQUIRE(n > 0 && leaf > 0 && eta_ > 0, HLU_ERR_INVALID_ARG, "hlu_build: N, leaf_size and eta must be positive");
   N = n;
   leaf_size = leaf;
@@ -74,6 +79,19 @@ void Structure::build(const int32_t* mid2, int32_t n, int32_t leaf, double eta_)
         c.lo[a] = std::min(c.lo[a], v);
         c.hi[a] = std::max(c.hi[a], v);
       }
+    c.alo = c.lo;
+    c.ahi = c.hi;
+    if (box_lo2) {
+      for (int a = 0; a < 3; ++a) {
+        c.alo[a] = INT32_MAX;
+        c.ahi[a] = INT32_MIN;
+      }
+      for (int32_t i = it.b; i < it.e; ++i)
+        for (int a = 0; a < 3; ++a) {
+          c.alo[a] = std::min(c.alo[a], box_lo2[3 * (int64_t)idx[i] + a]);
+          c.ahi[a] = std::max(c.ahi[a], box_hi2[3 * (int64_t)idx[i] + a]);
+        }
+    }
     int32_t id = (int32_t)clusters.size();
     clusters.push_back(c);
     if (it.parent >= 0) clusters[it.parent].son[it.which] = id;

@@ -12,7 +12,9 @@ struct ClusterNode {
   int32_t level;
   int32_t son[2] = {-1, -1};
   int32_t leaf_first, leaf_last;  // range of leaf-cluster ordinals covered [first, last)
-  std::array<int32_t, 3> lo, hi;  // tight box of doubled midpoints
+  std::array<int32_t, 3> lo, hi;  // tight box of doubled midpoints (splitting)
+  std::array<int32_t, 3> alo, ahi;  // box of the admissibility test: the midpoint box, or the
+                                    // union of the indices' own boxes (supports) when given
   bool is_leaf() const { return son[0] < 0; }
   int32_t size() const { return end - begin; }
 };
@@ -36,7 +38,11 @@ struct Structure {
   std::vector<int32_t> leaves;         // block-tree leaves (node ids) in pre-order
   int32_t depth = 0;
 
-  void build(const int32_t* mid2, int32_t N, int32_t leaf, double eta);
+  // box_lo2/box_hi2 (N x 3, doubled lattice units, may be null): a box per
+  // index for the admissibility test, e.g. the support of its basis
+  // function; null: the midpoints themselves.
+  void build(const int32_t* mid2, int32_t N, int32_t leaf, double eta, const int32_t* box_lo2 = nullptr,
+             const int32_t* box_hi2 = nullptr);
 };
 
 }  // namespace hlu

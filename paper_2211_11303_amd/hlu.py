@@ -65,6 +65,32 @@ def hlu_kuhn_assemble(n, kappa):
     return rp, ci, va, mid
 
 
+def hlu_kuhn_assemble_beta(n, kappa, beta_box, beta_in):
+    """hlu_kuhn_assemble_beta: A = K_beta - kappa^2 M with the curl-curl
+    coefficient beta_in on the cubes (i, j, k) of the half-open index box
+    beta_box = (i0, j0, k0, i1, j1, k1), 1 elsewhere."""
+    N, nnz = hlu_kuhn_sizes(n)
+    box = np.ascontiguousarray(beta_box, np.int32)
+    assert box.shape == (6,)
+    rp = np.empty(N + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    va = np.empty(nnz, np.float64)
+    mid = np.empty((N, 3), np.int32)
+    L.check(L.lib().hlu_kuhn_assemble_beta(n, float(kappa), _ptr(box, ctypes.c_int32), float(beta_in),
+                                           _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32),
+                                           _ptr(va, ctypes.c_double), _ptr(mid, ctypes.c_int32)))
+    return rp, ci, va, mid
+
+
+def hlu_kuhn_support_boxes(n):
+    """hlu_kuhn_support_boxes: (lo2, hi2), N x 3 each, doubled lattice units."""
+    N, _ = hlu_kuhn_sizes(n)
+    lo = np.empty((N, 3), np.int32)
+    hi = np.empty((N, 3), np.int32)
+    L.check(L.lib().hlu_kuhn_support_boxes(int(n), _ptr(lo, ctypes.c_int32), _ptr(hi, ctypes.c_int32)))
+    return lo, hi
+
+
 def hlu_autotune_leaf(n, kappa, leaves=(32, 48, 64), eta=2.0, eps=1e-3, max_rank=0, prec="fp32", restart=50,
                       max_iters=1000, tol=1e-8, nrhs=1, stream=None):
     """hlu_autotune_leaf: (best leaf, [device seconds of factor + GMRES per
@@ -128,9 +154,10 @@ class SpMat:
 class HLU:
     """hlu_build + workspace + hlu_factor / hlu_solve / hlu_apply_lu."""
 
-    def __init__(self, row_ptr, col, val, mid2=None, eta=2.0, leaf=64, share=None):
+    def __init__(self, row_ptr, col, val, mid2=None, eta=2.0, leaf=64, share=None, boxes=None):
         """hlu_build; with share=<HLU of the same sparsity pattern>,
-        hlu_build_shared (mid2, eta and leaf are then the prototype's)."""
+        hlu_build_shared (mid2, eta and leaf are then the prototype's); with
+        boxes=(lo2, hi2), hlu_build_boxes (admissibility on those boxes)."""
         self._rp = np.ascontiguousarray(row_ptr, np.int32)
         self._ci = np.ascontiguousarray(col, np.int32)
         self._va = np.ascontiguousarray(val, np.float64)
@@ -142,8 +169,15 @@ class HLU:
             eta, leaf = share.eta, share.leaf
         else:
             mid = np.ascontiguousarray(mid2, np.int32)
-            L.check(L.lib().hlu_build(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), float(eta), int(leaf),
-                                      ctypes.byref(h)))
+            if boxes is None:
+                L.check(L.lib().hlu_build(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), float(eta), int(leaf),
+                                          ctypes.byref(h)))
+            else:
+                lo = np.ascontiguousarray(boxes[0], np.int32)
+                hi = np.ascontiguousarray(boxes[1], np.int32)
+                assert lo.shape == mid.shape and hi.shape == mid.shape
+                L.check(L.lib().hlu_build_boxes(ctypes.byref(csr), _ptr(mid, ctypes.c_int32), _ptr(lo, ctypes.c_int32),
+                                                _ptr(hi, ctypes.c_int32), float(eta), int(leaf), ctypes.byref(h)))
         self.handle = h
         self._destroy = L.lib().hlu_destroy
         self.n = len(self._rp) - 1
@@ -184,6 +218,16 @@ class HLU:
         L.check(st)
         self.prec = prec
         return self
+
+    def hlu_bind_solve_workspace(self, eps, max_rank=0, prec="fp64"):
+        """Caller-owned (torch) memory for the persistent solve's buffers."""
+        torch = _torch()
+        o = self._opts(eps, max_rank, prec)
+        b = ctypes.c_size_t()
+        L.check(L.lib().hlu_solve_workspace_bytes(self.handle, ctypes.byref(o), ctypes.byref(b)))
+        self.solve_work = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+        L.check(L.lib().hlu_bind_solve_workspace(self.handle, _dev_ptr(self.solve_work), self.solve_work.numel()))
+        return b.value
 
     def hlu_inverse_workspace_bytes(self, eps, max_rank=0, prec="fp64"):
         o = self._opts(eps, max_rank, prec)

@@ -212,3 +212,63 @@ def test_large_leaves_against_oracle(gpu, leaf):
         assert infos[c]["converged"] and relres <= 1e-8
         _, io = oracle_solve(n, kappa, leaf, eps, B[c], 50, 1e-8)
         assert abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
+
+
+def test_caller_owned_solve_workspace(gpu):
+    """hlu_bind_solve_workspace: the persistent solve's buffers in caller
+    memory give the same results, bit for bit, as library-owned ones."""
+    import torch
+    hlu, inputs = _lib()
+    A, (rp, ci, va, mid) = _setup(8, 4.0, 64)
+    Ha = hlu.HLU(rp, ci, va, mid, 2.0, 64).hlu_factor(1e-4, prec="fp32")
+    Hb = hlu.HLU(rp, ci, va, mid, 2.0, 64)
+    nb = Hb.hlu_bind_solve_workspace(1e-4, prec="fp32")
+    Hb.hlu_factor(1e-4, prec="fp32")
+    assert nb > 0
+    v = torch.tensor(inputs.exact_solution_cols(A.n, 5, seed=9), device="cuda")
+    za, zb = Ha.hlu_solve(v), Hb.hlu_solve(v)
+    torch.cuda.synchronize()
+    assert torch.equal(za, zb)
+    x, infos = hlu.gmres_solve(A, A.hlu_spmv(v), Hb, restart=30, tol=1e-10)
+    assert all(i["converged"] for i in infos)
+
+
+@pytest.mark.parametrize("boxes,beta", [(True, None), (False, 10.0)])
+def test_support_boxes_and_coefficient_against_oracle(gpu, boxes, beta):
+    """Admissibility on the basis functions' supports (hlu_build_boxes) and a
+    piecewise constant curl-curl coefficient (hlu_kuhn_assemble_beta, a block
+    of beta = 10 in the middle of the cube), each against the oracle built
+    the same way: FP64 factor error within 2x the oracle's, GMRES iterations
+    within +-1, final relative residual <= 1e-8."""
+    import scipy.sparse as sp
+    import torch
+    from paper_2211_11303_amd import hlu, inputs
+    from oracle.assemble import Discretisation
+    from oracle.cluster import Structure
+    from oracle.hmatrix import HLU as OracleHLU
+    from oracle.krylov import gmres as oracle_gmres
+    n, kappa, leaf, eps, box = 8, 4.0, 32, 1e-2, (2, 2, 2, 6, 6, 6)
+    d = Discretisation(n, kappa, box if beta else None, beta or 1.0)
+    s = Structure(d.mesh.midpoints2(), leaf, 2.0, boxes=d.mesh.support_boxes2() if boxes else None)
+    o = OracleHLU(s, d.A, eps).factor()
+    if beta:
+        rp, ci, va, mid = hlu.hlu_kuhn_assemble_beta(n, kappa, box, beta)
+    else:
+        rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, kappa)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, leaf, boxes=hlu.hlu_kuhn_support_boxes(n) if boxes else None)
+    H.hlu_factor(eps, prec="fp64")
+    st = H.hlu_export_structure()
+    assert np.array_equal(st["bkind"], [b.kind for b in s.block_leaves])
+    Acsr = sp.csr_matrix((va, ci, rp), shape=(d.N, d.N))
+    e_or = o.factor_error()
+    e_gpu = gpu_factor_error(H, Acsr, st["perm"])
+    assert e_gpu <= 2 * e_or + 1e-12, (e_gpu, e_or)
+    A = hlu.SpMat(rp, ci, va)
+    X = inputs.exact_solution_cols(d.N, 4, seed=3)
+    B = (d.A @ X.T).T.copy()
+    x, infos = hlu.gmres_solve(A, torch.tensor(B, device="cuda"), H, restart=50, tol=1e-8)
+    xg = x.cpu().numpy()
+    for c in range(4):
+        _, io = oracle_gmres(d.A, B[c], o.solve, restart=50, tol=1e-8, max_iters=2000)
+        assert infos[c]["converged"] and abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
+        assert np.linalg.norm(Acsr @ xg[c] - B[c]) <= 1e-8 * np.linalg.norm(B[c])

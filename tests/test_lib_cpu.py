@@ -212,3 +212,51 @@ def test_truncation_rounds_terminate(n, leaf):
     # a capacity cap below the round limit never stalls
     r = H.hlu_check_trunc_rounds(1e-3, 200, max_rank=32)
     assert r["unfinished"] == 0 and r["stalled_rounds"] == 0, r
+
+
+@pytest.mark.parametrize("n,box,beta", [(2, (0, 0, 0, 1, 2, 1), 10.0), (4, (1, 1, 1, 3, 3, 3), 100.0),
+                                        (8, (0, 2, 3, 8, 5, 6), 0.1)])
+def test_coefficient_box_matches_oracle(n, box, beta):
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble_beta(n, 3.0, box, beta)
+    d = Discretisation(n, 3.0, box, beta)
+    assert np.array_equal(rp, d.A.indptr) and np.array_equal(ci, d.A.indices)
+    assert np.abs(va - d.A.data).max() <= 1e-14 * np.abs(d.A.data).max()
+    assert np.array_equal(mid, d.mesh.midpoints2())
+
+
+@pytest.mark.parametrize("n", [1, 3, 8])
+def test_support_boxes_match_oracle(n):
+    from paper_2211_11303_amd import hlu
+    from oracle.mesh import KuhnMesh
+    lo, hi = hlu.hlu_kuhn_support_boxes(n)
+    olo, ohi = KuhnMesh(n).support_boxes2()
+    assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+
+
+@pytest.mark.parametrize("n,leaf", [(4, 8), (6, 16), (8, 64)])
+def test_support_box_structure_bit_exact(n, leaf):
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, 2.0)
+    boxes = hlu.hlu_kuhn_support_boxes(n)
+    h = hlu.HLU(rp, ci, va, mid, 2.0, leaf, boxes=boxes)
+    st = h.hlu_export_structure()
+    s = Structure(mid, leaf, 2.0, boxes=boxes)
+    assert np.array_equal(st["perm"], s.perm)
+    assert np.array_equal(st["brow"], [b.row.id for b in s.block_leaves])
+    assert np.array_equal(st["bcol"], [b.col.id for b in s.block_leaves])
+    assert np.array_equal(st["bkind"], [b.kind for b in s.block_leaves])
+    assert h.hlu_get_stats()["dense_entries"] == s.summary()["dense_entries"]
+
+
+def test_box_arguments_rejected():
+    from paper_2211_11303_amd import hlu
+    from paper_2211_11303_amd import _lib as L
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(3, 2.0)
+    lo, hi = hlu.hlu_kuhn_support_boxes(3)
+    bad = lo.copy()
+    bad[5, 1] = mid[5, 1] + 1           # box no longer contains its midpoint
+    with pytest.raises(L.HluError):
+        hlu.HLU(rp, ci, va, mid, 2.0, 16, boxes=(bad, hi))
+    with pytest.raises(L.HluError):
+        hlu.hlu_kuhn_assemble_beta(3, 2.0, (0, 0, 0, 1, 1, 1), -1.0)

@@ -100,3 +100,39 @@ def test_load_of_constant_field(n):
         G = d.discrete_gradient()
         assert np.abs(G.T @ b).max() <= 1e-14 * np.abs(b).max()
         assert np.abs(b).max() > 0
+
+
+@pytest.mark.parametrize("n,box,beta", [(2, (0, 0, 0, 1, 2, 1), 10.0), (3, (1, 0, 1, 3, 2, 3), 0.25),
+                                        (4, (1, 1, 1, 3, 3, 3), 100.0)])
+def test_coefficient_box_energy(n, box, beta):
+    """Piecewise constant curl-curl coefficient (Sec. 2.1): for E = a + b x x
+    the curl is the constant 2b, so u^T K_beta u = 4 |b|^2 sum_T beta_T |T|
+    = 4 |b|^2 (1 + (beta - 1) |box|) with |box| the box's volume; the mass
+    matrix does not change and K_beta still annihilates the gradients."""
+    d = Discretisation(n, 1.0, box, beta)
+    d1 = Discretisation(n, 1.0)
+    vol_box = np.prod(np.subtract(box[3:], box[:3])) / n ** 3
+    m = d.mesh
+    p = m.coords.astype(np.float64) / n
+    tail, head = p[m.edges[:, 0]], p[m.edges[:, 1]]
+    mid = 0.5 * (tail + head)
+    rng = np.random.default_rng(7 + n)
+    for _ in range(3):
+        a, b = rng.standard_normal(3), rng.standard_normal(3)
+        u = np.einsum("ij,ij->i", a + np.cross(b, mid), head - tail)
+        ref = 4 * (b @ b) * (1 + (beta - 1) * vol_box)
+        assert abs(u @ (d.K_full @ u) - ref) <= 1e-12 * ref
+    assert abs(d.M - d1.M).max() == 0
+    G = d.discrete_gradient()
+    if G.shape[1]:
+        assert abs(d.K @ G).max() <= 1e-13 * abs(d.K).max()
+
+
+def test_coefficient_box_special_cases():
+    """beta = 1 on any box, or no box, is the plain matrix; beta on the whole
+    cube scales K exactly."""
+    d1 = Discretisation(3, 2.0)
+    assert abs(Discretisation(3, 2.0, (0, 1, 0, 2, 3, 1), 1.0).A - d1.A).max() == 0
+    dw = Discretisation(3, 2.0, (0, 0, 0, 3, 3, 3), 4.0)
+    assert abs(dw.K - 4.0 * d1.K).max() <= 1e-15 * abs(d1.K).max() * 4
+    assert np.array_equal(dw.A.indptr, d1.A.indptr) and np.array_equal(dw.A.indices, d1.A.indices)

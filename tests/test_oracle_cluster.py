@@ -107,3 +107,56 @@ def test_structure_counts_16():
     sm = s.summary()
     assert (sm["clusters"], sm["leaves"], sm["depth"]) == (1021, 511, 9)
     assert (sm["admissible"], sm["dense"], sm["dense_entries"]) == (14824, 10623, 29829200)
+
+
+def _box_test_union(s, t, u, eta, lo2, hi2):
+    """Admissibility by brute force on the union of the indices' boxes."""
+    it, iu = s.perm[t.begin:t.end], s.perm[u.begin:u.end]
+    tl, th = lo2[it].min(axis=0), hi2[it].max(axis=0)
+    ul, uh = lo2[iu].min(axis=0), hi2[iu].max(axis=0)
+    gap = np.maximum(0, np.maximum(ul - th, tl - uh)).astype(float)
+    dist = float(np.sqrt(gap @ gap))
+    dt = float(np.sqrt(((th - tl) ** 2).sum()))
+    du = float(np.sqrt(((uh - ul) ** 2).sum()))
+    return dist > 0 and min(dt, du) <= eta * dist + 1e-9 * max(dt, du)
+
+
+@pytest.mark.parametrize("n,leaf", [(4, 8), (4, 32), (6, 16), (8, 64)])
+def test_support_box_structure(n, leaf):
+    """Admissibility on the basis functions' supports (Definition 1 measures
+    clusters by the supports): the cluster tree is the midpoint tree; the
+    blocks pass or fail the brute-force test on the union of the supports;
+    and, at every leaf size, no entry of A falls in an admissible block (two
+    basis functions couple only if their supports meet)."""
+    d = Discretisation(n, 1.0)
+    mid2 = d.mesh.midpoints2()
+    lo2, hi2 = d.mesh.support_boxes2()
+    s = Structure(mid2, leaf, 2.0, boxes=(lo2, hi2))
+    s0 = Structure(mid2, leaf, 2.0)
+    _check_cluster_tree(s, mid2, leaf)
+    assert np.array_equal(s.perm, s0.perm)
+    Ap = d.A[s.perm][:, s.perm].tocsr()
+    area = 0
+    for b in s.block_leaves:
+        area += b.row.size * b.col.size
+        adm = _box_test_union(s, b.row, b.col, 2.0, lo2, hi2)
+        assert adm == (b.kind == LOWRANK)
+        if b.kind == LOWRANK:
+            assert Ap[b.row.begin:b.row.end, b.col.begin:b.col.end].nnz == 0
+        else:
+            assert b.row.is_leaf or b.col.is_leaf
+    assert area == s.N * s.N
+    # a support box contains its midpoint, so a block admissible on the
+    # supports is admissible on the midpoints (there or at an ancestor): the
+    # dense area can only grow, and it does at these sizes
+    assert s.summary()["dense_entries"] > s0.summary()["dense_entries"]
+
+
+def test_support_box_special_case():
+    """Point boxes (each index's box its own midpoint) reproduce the midpoint
+    structure exactly."""
+    mid2 = KuhnMesh(5).midpoints2()
+    s = Structure(mid2, 20, 2.0, boxes=(mid2, mid2))
+    s0 = Structure(mid2, 20, 2.0)
+    assert [b.kind for b in s.block_leaves] == [b.kind for b in s0.block_leaves]
+    assert [(b.row.id, b.col.id) for b in s.block_leaves] == [(b.row.id, b.col.id) for b in s0.block_leaves]

@@ -99,3 +99,22 @@ def test_edge_orientation_and_order():
     # midpoints are unique
     mid = m.midpoints2()
     assert len({tuple(x) for x in mid}) == len(mid)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_support_boxes_closed_form(n):
+    """The edge from p to p + d (d a 0/1 vector on the Kuhn lattice) lies in
+    the cubes with corner c, c_a = p_a where d_a = 1 and c_a in {p_a - 1, p_a}
+    where d_a = 0 (both exist for an interior edge), and every tetrahedron's
+    bounding box is its whole cube; so the support box is [p_a, p_a + 1] along
+    the edge's axes and [p_a - 1, p_a + 1] across them."""
+    m = KuhnMesh(n)
+    lo, hi = m.support_boxes2()
+    p = m.coords[m.interior_edges[:, 0]]
+    d = m.coords[m.interior_edges[:, 1]] - p
+    assert np.all((d == 0) | (d == 1))
+    assert np.array_equal(lo, 2 * np.where(d == 1, p, p - 1))
+    assert np.array_equal(hi, 2 * (p + 1))
+    mid = m.midpoints2()
+    assert np.all(lo <= mid) and np.all(mid <= hi)
+    assert lo.min() >= 0 and hi.max() <= 2 * n
