@@ -124,6 +124,10 @@ typedef struct {
    * 2(m r + n K) r_new (K stacked columns, r their numerical rank). */
   double factor_flops;
   double factor_flops_getrf, factor_flops_tri, factor_flops_gemm, factor_flops_trunc;
+  /* Rank storage reserved in the workspace: sum over admissible blocks of
+   * (m + n) times the block's capacity (min(m, n, 64 or max_rank), or the
+   * fitted capacity after hlu_fit_ranks). */
+  double rank_capacity_entries;
 } hlu_stats;
 
 /* Schulz iteration for the H-matrix inverse (hlu_inverse). */
@@ -240,6 +244,28 @@ hlu_status hlu_plan_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t*
 /* Hands the library a caller-owned device buffer of at least the bytes
  * reported above (256-byte aligned).  It stays in use until re-bound or the
  * handle is destroyed. */
+/* Fit the rank capacities to the ranks the last hlu_factor of this handle
+ * asked for (Sec. 4: each truncation keeps the singular values above
+ * eps * sigma_1).  Every admissible block and every temporary low-rank
+ * accumulator of the factorisation gets capacity min(m, n, kcap,
+ * peak + margin), peak being the largest eps-rank any of its truncations
+ * asked for (also when a capacity cut it), instead of min(m, n, kcap) with
+ * kcap = 64 (or max_rank).  The plans are rebuilt for the new layout (host
+ * work of the same order as hlu_build's first factorisation); the factor is
+ * dropped (the handle is no longer factored) and *workspace_bytes receives
+ * the workspace hlu_factor with options o now needs: bind a workspace of
+ * that size and factor again.  With the same eps and values the new
+ * factorisation is the same (bit for bit) as long as no capacity is
+ * exceeded; a block that needs more is reported as by hlu_factor
+ * (HLU_ERR_RANK_OVERFLOW, or counted in capped_blocks with max_rank > 0),
+ * and fitting again after that factorisation raises its capacity.  The
+ * peaks may come from a factorisation with a small max_rank (a capped run
+ * that needs little memory) and o may then have max_rank = 0.  margin < 0
+ * drops the fitted capacities.  Needs the handle's own workspace (not a
+ * batch).  Batches built afterwards from the handle use its fitted
+ * capacities when their options have the same kcap. */
+hlu_status hlu_fit_ranks(hlu_handle h, const hlu_factor_opts* o, int32_t margin, size_t* workspace_bytes);
+
 hlu_status hlu_bind_workspace(hlu_handle h, void* d_work, size_t bytes);
 
 /* Algorithm 1, step II: copies A into the H-matrix and computes L (unit

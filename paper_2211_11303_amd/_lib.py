@@ -53,6 +53,7 @@ class Stats(ctypes.Structure):
         ("solve_launches", c_int64), ("solve_columns", c_int64), ("solve_kernel_ms", c_double),
         ("factor_flops", c_double), ("factor_flops_getrf", c_double), ("factor_flops_tri", c_double),
         ("factor_flops_gemm", c_double), ("factor_flops_trunc", c_double),
+        ("rank_capacity_entries", c_double),
     ]
 
     def as_dict(self):
@@ -91,6 +92,7 @@ SIGNATURES = {
     "hlu_kuhn_assemble": (c_int32, [c_int32, c_double, P_i32, P_i32, P_f64, P_i32]),
     "hlu_kuhn_assemble_beta": (c_int32, [c_int32, c_double, P_i32, c_double, P_i32, P_i32, P_f64, P_i32]),
     "hlu_kuhn_support_boxes": (c_int32, [c_int32, P_i32, P_i32]),
+    "hlu_fit_ranks": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), c_int32, ctypes.POINTER(c_size_t)]),
     "hlu_build_boxes": (c_int32, [ctypes.POINTER(HluCsr), P_i32, P_i32, P_i32, c_double, c_int32,
                                   ctypes.POINTER(c_void_p)]),
     "hlu_spmat_create": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),

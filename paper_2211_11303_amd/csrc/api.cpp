@@ -34,7 +34,8 @@ WorkLayout work_layout(const PlanSet& ps, int32_t prec) {
   L.arena_bytes = align256((size_t)ps.store.total_elems * elem_size(prec));
   L.dims_off = L.arena_bytes;
   L.status_off = L.dims_off + align256((size_t)ps.store.num_slots * sizeof(int32_t));
-  L.total = L.status_off + kStatusWords * sizeof(int32_t);
+  L.peak_off = L.status_off + align256(kStatusWords * sizeof(int32_t));
+  L.total = L.peak_off + (size_t)ps.store.num_slots * sizeof(int32_t);
   return L;
 }
 
@@ -352,12 +353,23 @@ void dump_trunc_trace(const Plan& pl) {
   }
 }
 
+double rank_capacity_entries(const Structure& S, const StoragePlan& st) {
+  double e = 0.0;
+  for (size_t l = 0; l < S.leaves.size(); ++l) {
+    if (st.slot[l] < 0) continue;
+    const BlockNode& b = S.blocks[S.leaves[l]];
+    e += (double)(S.clusters[b.row].size() + S.clusters[b.col].size()) * st.cap[l];
+  }
+  return e;
+}
+
 void record_factor(hlu_s* h, const hlu_factor_opts* o) {
   h->prec = o->prec;
   h->eps = o->eps;
   h->factor_compute64 = fp64_tasks(o->prec);
   const PlanSet& ps = h->pb->ps;
   h->stats.workspace_bytes = (int64_t)work_layout(ps, o->prec).total;
+  h->stats.rank_capacity_entries = rank_capacity_entries(h->sh->S, ps.store);
   h->stats.factor_waves = (int64_t)ps.factor.waves.size();
   h->stats.factor_tasks = ps.factor.num_tasks;
   h->stats.solve_waves = (int64_t)ps.fwd_bwd.waves.size();
@@ -366,12 +378,13 @@ void record_factor(hlu_s* h, const hlu_factor_opts* o) {
 namespace {
 
 template <class T>
-void run_plan(hlu_s* h, const Plan& pl, const DevArrays& d, bool compute64, hipStream_t s) {
+void run_plan(hlu_s* h, const Plan& pl, const DevArrays& d, bool compute64, hipStream_t s,
+              int32_t* peak = nullptr) {
   T* arena = static_cast<T*>(h->arena);
   int32_t tile_base = 0;
   for (const Wave& w : pl.waves) {
     HIP_OK(launch_wave<T>(arena, d.P, w, h->dims, h->status, h->eps, kFloorRel, h->sh->max_leaf, tile_base,
-                          compute64, s));
+                          compute64, s, peak));
     tile_base += w.gemm_tiles;
   }
 }
@@ -390,7 +403,8 @@ void factor_impl(hlu_s* h, hipStream_t s) {
   T* arena = static_cast<T*>(h->arena);
   factor_prepare<T>(h, arena, h->dims, s);
   HIP_OK(zero_int_launch(h->status, kStatusWords, s));
-  run_plan<T>(h, h->pb->ps.factor, h->pb->dfactor, h->factor_compute64, s);
+  if (h->peak) HIP_OK(zero_int_launch(h->peak, h->pb->ps.store.num_slots, s));   // not for batch members
+  run_plan<T>(h, h->pb->ps.factor, h->pb->dfactor, h->factor_compute64, s, h->peak);
   // the persistent solve applies the diagonal leaves through their inverses
   h->inv_ready = false;
   ensure_inverses<T>(h, s);
@@ -497,6 +511,7 @@ void resolve_memory(hlu_s* h, const hlu_factor_opts* o) {
   if (h->batch) {
     HLU_REQUIRE(h->arena && h->prec == o->prec && h->pb->kcap == kcap_for(o), HLU_ERR_STATE,
                 "hlu_factor: handle is bound through a batch with other options");
+    h->peak = nullptr;
     return;
   }
   const WorkLayout L = work_layout(h->pb->ps, o->prec);
@@ -505,6 +520,7 @@ void resolve_memory(hlu_s* h, const hlu_factor_opts* o) {
   h->arena = h->work;
   h->dims = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.dims_off);
   h->status = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.status_off);
+  h->peak = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.peak_off);
 }
 
 }  // namespace
@@ -512,7 +528,8 @@ void resolve_memory(hlu_s* h, const hlu_factor_opts* o) {
 void use_bundle(hlu_s* h, int32_t kcap) {
   if (h->pb && h->pb->kcap == kcap) return;
   HLU_REQUIRE(!h->batch, HLU_ERR_STATE, "handle is bound through a batch with another rank capacity");
-  h->pb = get_bundle(*h->sh, kcap);
+  h->pb = (h->fitted && h->fitted->kcap == kcap) ? h->fitted : get_bundle(*h->sh, kcap);
+  h->peak_valid = false;
   h->sbuf.reset();   // solve buffers follow the schedule
   h->factored = false;
 }
@@ -688,6 +705,7 @@ hlu_status hlu_workspace_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* b
     use_bundle(h, kcap_for(o));
     *bytes = work_layout(h->pb->ps, o->prec).total;
     h->stats.workspace_bytes = (int64_t)*bytes;
+    h->stats.rank_capacity_entries = rank_capacity_entries(h->sh->S, h->pb->ps.store);
     h->stats.factor_waves = (int64_t)h->pb->ps.factor.waves.size();
     h->stats.factor_tasks = h->pb->ps.factor.num_tasks;
     h->stats.solve_waves = (int64_t)h->pb->ps.fwd_bwd.waves.size();
@@ -738,6 +756,44 @@ hlu_status hlu_device_bytes(hlu_handle h, const hlu_factor_opts* o, size_t* byte
   });
 }
 
+hlu_status hlu_fit_ranks(hlu_handle h, const hlu_factor_opts* o, int32_t margin, size_t* workspace_bytes) {
+  return guard([&] {
+    HLU_REQUIRE(h && workspace_bytes, HLU_ERR_INVALID_ARG, "hlu_fit_ranks: NULL argument");
+    check_opts(o);
+    HLU_REQUIRE(margin <= 4096, HLU_ERR_INVALID_ARG, "hlu_fit_ranks: margin too large");
+    HLU_REQUIRE(!h->batch, HLU_ERR_STATE, "hlu_fit_ranks: handle belongs to a batch");
+    const int32_t kcap = kcap_for(o);
+    if (margin < 0) {   // back to the uniform capacity
+      h->fitted.reset();
+      h->pb.reset();
+      use_bundle(h, kcap);
+    } else {
+      HLU_REQUIRE(h->peak_valid && h->mode == 0 && h->peak, HLU_ERR_STATE,
+                  "hlu_fit_ranks: needs an hlu_factor of this handle with its own workspace first");
+      // rank slots of blocks and temporaries come first and depend on the
+      // structure only, so they match between capacities
+      const int32_t nslot = h->pb->ps.store.nrhs_slot;
+      std::vector<int32_t> peak((size_t)nslot);
+      HIP_OK(hipMemcpy(peak.data(), h->peak, peak.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+      auto pb = std::make_shared<PlanBundle>();
+      pb->kcap = kcap;
+      pb->slot_cap.resize((size_t)nslot);
+      for (int32_t i = 0; i < nslot; ++i) pb->slot_cap[i] = std::max(1, peak[i] + margin);
+      build_plans(h->sh->S, kcap, kMaxRhs, h->sh->nonzero_admissible, &pb->ps, &pb->slot_cap);
+      build_chain_sched(h->sh->S, pb->ps.store, &pb->sc);
+      h->fitted = pb;
+      h->pb = pb;
+    }
+    h->sbuf.reset();
+    h->inv_ready = false;
+    h->factored = false;
+    h->peak_valid = false;
+    *workspace_bytes = work_layout(h->pb->ps, o->prec).total;
+    h->stats.workspace_bytes = (int64_t)*workspace_bytes;
+    h->stats.rank_capacity_entries = rank_capacity_entries(h->sh->S, h->pb->ps.store);
+  });
+}
+
 hlu_status hlu_bind_workspace(hlu_handle h, void* d_work, size_t bytes) {
   return guard([&] {
     HLU_REQUIRE(h && d_work, HLU_ERR_INVALID_ARG, "hlu_bind_workspace: NULL argument");
@@ -772,6 +828,7 @@ hlu_status hlu_factor(hlu_handle h, const hlu_factor_opts* o, void* stream) {
     gather_stats(h, h->sbuf->pivots);
     read_flops(h->status, &h->stats);
     h->stats.capped_blocks = status[1];
+    h->peak_valid = h->peak != nullptr;
     dump_trunc_trace(h->pb->ps.factor);
     if (status[1] > 0 && o->max_rank == 0) {
       set_error("hlu_factor: a truncated rank exceeded the block capacity");

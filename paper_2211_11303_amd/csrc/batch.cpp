@@ -244,7 +244,7 @@ hlu_status hlu_batch_create(const hlu_handle* hs, int32_t count, const hlu_facto
     b->hs.assign(hs, hs + count);
     std::vector<std::shared_ptr<PlanBundle>> pbs;
     for (hlu_s* h : b->hs) {
-      pbs.push_back(get_bundle(*h->sh, b->kcap));
+      pbs.push_back((h->fitted && h->fitted->kcap == b->kcap) ? h->fitted : get_bundle(*h->sh, b->kcap));
       ensure_device(*h->sh, *pbs.back());
     }
     // layout: arenas, then all rank tables, then the status words
@@ -330,6 +330,8 @@ hlu_status hlu_batch_bind_workspace(hlu_batch b, void* d_work, size_t bytes) {
       h->arena = base + b->arena_off[p];
       h->dims = reinterpret_cast<int32_t*>(base + b->dims_off) + b->slot_base[p];
       h->status = reinterpret_cast<int32_t*>(base + b->status_off);
+      h->peak = nullptr;
+      h->peak_valid = false;
       h->factored = false;
     }
   });
@@ -452,6 +454,8 @@ void hlu_batch_destroy(hlu_batch b) {
     h->arena = nullptr;
     h->dims = nullptr;
     h->status = nullptr;
+    h->peak = nullptr;
+    h->peak_valid = false;
     h->factored = false;
   }
   delete b;

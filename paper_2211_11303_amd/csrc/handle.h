@@ -173,6 +173,7 @@ struct InverseBundle {
 // Host part built by get_bundle; device copies made by ensure_device.
 struct PlanBundle {
   int32_t kcap = 0;
+  std::vector<int32_t> slot_cap;   // fitted capacities per rank slot (empty: uniform kcap)
   PlanSet ps;
   ChainSched sc;
   bool on_device = false;
@@ -206,7 +207,7 @@ std::shared_ptr<PlanBundle> get_bundle(Shared& sh, int32_t kcap);
 void ensure_device(Shared& sh, PlanBundle& pb);
 
 struct WorkLayout {
-  size_t arena_bytes, dims_off, status_off, total;
+  size_t arena_bytes, dims_off, status_off, peak_off, total;
 };
 WorkLayout work_layout(const PlanSet& ps, int32_t prec);
 
@@ -232,8 +233,11 @@ hlu_status guard(F&& f) {
 
 // ------------------------------------------------------------ kernels
 template <class T>
+// peak (optional, one int per rank slot): each truncation raises its slot's
+// entry to the eps-rank it asked for, before any capacity cap.
 hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status, double eps,
-                       double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64, hipStream_t s);
+                       double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64, hipStream_t s,
+                       int32_t* peak = nullptr);
 hipError_t spmv_launch(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                        double* y, int32_t nrhs, int64_t ld, double alpha, double beta, hipStream_t s);
 template <class T>
@@ -287,6 +291,9 @@ struct hlu_spmat_s {
 struct hlu_s {
   std::shared_ptr<hlu::Shared> sh;
   std::shared_ptr<hlu::PlanBundle> pb;   // plans of the capacity last asked for
+  std::shared_ptr<hlu::PlanBundle> fitted;   // plans with capacities fitted to measured ranks (hlu_fit_ranks)
+  int32_t* peak = nullptr;               // per rank slot: largest eps-rank asked for by the last factorisation
+  bool peak_valid = false;
   std::vector<double> val;               // values of A (natural order, pattern of sh)
   hlu::Owned mem;
   double* d_val = nullptr;

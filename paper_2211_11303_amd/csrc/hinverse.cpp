@@ -254,6 +254,8 @@ hlu_status hlu_inverse(hlu_handle h, const hlu_factor_opts* o, const hlu_schulz_
     h->dims = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.dims_off);
     h->status = reinterpret_cast<int32_t*>(static_cast<char*>(h->work) + L.status_off);
     h->red = reinterpret_cast<double*>(static_cast<char*>(h->work) + L.red_off);
+    h->peak = nullptr;
+    h->peak_valid = false;
     h->prec = o->prec;
     h->eps = o->eps;
     h->factor_compute64 = fp64_tasks(o->prec);

@@ -52,19 +52,23 @@ __device__ __forceinline__ void store_relaxed(int32_t* p, int32_t v) {
 // Spin until *f satisfies the predicate, for at most `ticks` of the
 // constant-rate wall clock; on timeout set the launch's error word.  After
 // an error every wait returns at once, so the launch drains.
+// The error word and the clock are looked at every 32nd poll only: each poll
+// is a load from memory (agent scope), and the flag is what is waited for.
 template <class Pred>
 __device__ bool spin_until(const int32_t* f, Pred ok, int32_t* err, int64_t ticks) {
   if (ok(load_relaxed(f))) return true;
   const int64_t t0 = (int64_t)wall_clock64();
-  while (!ok(load_relaxed(f))) {
-    if (load_relaxed(err) != 0) return false;
+  for (uint32_t it = 1;; ++it) {
     __builtin_amdgcn_s_sleep(2);
-    if ((int64_t)wall_clock64() - t0 > ticks) {
-      store_relaxed(err, 1);
-      return false;
+    if (ok(load_relaxed(f))) return true;
+    if ((it & 31u) == 0) {
+      if (load_relaxed(err) != 0) return false;
+      if ((int64_t)wall_clock64() - t0 > ticks) {
+        store_relaxed(err, 1);
+        return false;
+      }
     }
   }
-  return true;
 }
 
 // After flags were observed by some threads: order the workgroup's later

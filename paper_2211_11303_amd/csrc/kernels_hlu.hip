@@ -547,7 +547,7 @@ template <class T>
 __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops, const TruncPart* parts,
                                                     int32_t* dims, double eps, double floor_rel,
                                                     int32_t* status, int64_t* trace, int32_t op_base,
-                                                    int round_cols) {
+                                                    int round_cols, int32_t* peak) {
   __shared__ double bufG[kKMax * kLd];
   __shared__ double bufR[kKMax * kLd];
   __shared__ double bufS[kKMax * kLd];
@@ -746,6 +746,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         const int lim = trunc_rank_limit(op, s_done != 0, round_cols);
         const int r = cnt < lim ? cnt : lim;
         if (cnt > lim) atomicAdd(&status[1], 1);
+        if (peak) atomicMax(&peak[op.slot], cnt);   // the eps-rank asked for, before any cap
         s_r = r;
       }
       __syncthreads();
@@ -855,7 +856,7 @@ int trunc_round_cols() {
 template <class T, class C>
 hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
                          double eps, double floor_rel, int32_t max_leaf, int32_t tile_base,
-                         hipStream_t s) {
+                         hipStream_t s, int32_t* peak) {
   static std::once_flag attrs_set;   // launchers run on several server threads
   std::call_once(attrs_set, [] {
     // allow dynamic LDS up to the 160 KB of a gfx950 CU
@@ -888,7 +889,7 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
     if (tr && w.begin[kTrunc] + w.count[kTrunc] > kTruncTraceOps) tr = nullptr;
     dev::trunc_kernel<T><<<w.count[kTrunc], 256, 0, s>>>(arena, P.trunc + w.begin[kTrunc], P.parts, dims,
                                                           eps, floor_rel, status, tr, w.begin[kTrunc],
-                                                          trunc_round_cols());
+                                                          trunc_round_cols(), peak);
   }
   return hipGetLastError();
 }
@@ -898,15 +899,15 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
 template <class T>
 hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
                        double eps, double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64,
-                       hipStream_t s) {
+                       hipStream_t s, int32_t* peak) {
   if (compute64)
-    return launch_wave_c<T, double>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s);
-  return launch_wave_c<T, T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s);
+    return launch_wave_c<T, double>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s, peak);
+  return launch_wave_c<T, T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s, peak);
 }
 
 template hipError_t launch_wave<float>(float*, const DevPlan&, const Wave&, int32_t*, int32_t*, double,
-                                       double, int32_t, int32_t, bool, hipStream_t);
+                                       double, int32_t, int32_t, bool, hipStream_t, int32_t*);
 template hipError_t launch_wave<double>(double*, const DevPlan&, const Wave&, int32_t*, int32_t*, double,
-                                        double, int32_t, int32_t, bool, hipStream_t);
+                                        double, int32_t, int32_t, bool, hipStream_t, int32_t*);
 
 }  // namespace hlu

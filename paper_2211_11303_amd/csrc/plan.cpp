@@ -148,7 +148,7 @@ class Planner {
         leaf_buf_[l] = new_buf(rc.leaf_first, rc.leaf_last - rc.leaf_first, cc.leaf_first,
                                cc.leaf_last - cc.leaf_first);
       } else {
-        const int32_t cap = std::max(1, std::min(std::min(m, n), kcap));
+        const int32_t cap = cap_for(m, n, kcap, slots);
         st_.cap[l] = cap;
         st_.slot[l] = slots++;
         st_.off[l] = top;
@@ -605,6 +605,14 @@ class Planner {
 
   static int32_t cap_of(int32_t code, int32_t s) { return code >= 0 ? code : s; }
 
+  // rank capacity of a low-rank block or temporary m x n with rank slot
+  // `slot`: min(m, n, kcap), lowered to the slot's fitted capacity if given
+  int32_t cap_for(int32_t m, int32_t n, int32_t kcap, int32_t slot) const {
+    int32_t c = std::min(std::min(m, n), kcap);
+    if (slot_cap_ && slot < (int32_t)slot_cap_->size()) c = std::min(c, (*slot_cap_)[slot]);
+    return std::max(1, c);
+  }
+
   // restriction of a view whose row 0 sits at absolute position base
   View rows_of(const View& v, int32_t base, int32_t a0, int32_t a1) const {
     if (v.r0 >= 0) return sub_rows(v, a0, a1);
@@ -784,8 +792,8 @@ class Planner {
     h.c0 = c0;
     h.c1 = c1;
     const int32_t m = r1 - r0, n = c1 - c0;
-    h.cap = std::max(1, std::min(std::min(m, n), kcap_));
     h.slot = st_.num_slots++;
+    h.cap = cap_for(m, n, kcap_, h.slot);
     h.X = temp_spatial(r0, m, dyn(h.slot), h.cap);
     h.Y = temp_spatial(c0, n, dyn(h.slot), h.cap);
     h.root = -2 - h.slot;              // temporaries are their own root
@@ -985,6 +993,7 @@ class Planner {
 
  public:
   int32_t kcap_ = 64;
+  const std::vector<int32_t>* slot_cap_ = nullptr;   // fitted capacity per rank slot (null: uniform)
 
   View vector_view(int64_t off, int32_t max_rhs, int32_t nrhs_slot, int32_t buf) const {
     return View{off, 1, S_.N, S_.N, dyn(nrhs_slot), S_.N, max_rhs, 0, -1, buf, false};
@@ -1024,7 +1033,8 @@ class Planner {
 }  // namespace
 
 void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
-                 const std::vector<int32_t>& nonzero_admissible, PlanSet* out) {
+                 const std::vector<int32_t>& nonzero_admissible, PlanSet* out,
+                 const std::vector<int32_t>* slot_cap) {
   HLU_REQUIRE(kcap >= 1 && max_rhs >= 1, HLU_ERR_INVALID_ARG, "build_plans: bad capacity");
   PlanSet& ps = *out;
   ps = PlanSet{};
@@ -1032,6 +1042,7 @@ void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
   StoragePlan& st = ps.store;
   Planner pl(S, st);
   pl.kcap_ = kcap;
+  pl.slot_cap_ = slot_cap;
   pl.layout(kcap, nonzero_admissible, &ps.init_blocks);
 
   // factorisation plan; temporaries follow the data
@@ -1042,6 +1053,11 @@ void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
   pl.flush_all();
   pl.end_plan();
   st.temp_elems = pl.temp_used();
+
+  // the rank slots of blocks and temporaries depend on the structure only,
+  // so a fitted capacity table matches them one to one
+  HLU_REQUIRE(!slot_cap || (int64_t)slot_cap->size() == st.num_slots, HLU_ERR_INVALID_ARG,
+              "build_plans: fitted capacities do not match the rank slots of this structure");
 
   // solve plans: vectors and their temporaries after the factor temporaries
   st.max_rhs = max_rhs;

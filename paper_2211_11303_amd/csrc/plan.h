@@ -171,7 +171,11 @@ struct PlanSet {
 // (capped at min(m, n)); max_rhs: column capacity of the solve plans;
 // nonzero_admissible: leaf ordinals of admissible blocks holding entries.
 void build_inverse_plans(const Structure& S, int32_t kcap, int32_t max_rhs, InversePlanSet* out);
+// slot_cap (optional, one entry per rank slot of the factor, i.e. the
+// num_slots of a plan of the same structure before the solve's slot): fitted
+// capacities, each block's or temporary's capacity min(m, n, kcap, slot_cap).
 void build_plans(const Structure& S, int32_t kcap, int32_t max_rhs,
-                 const std::vector<int32_t>& nonzero_admissible, PlanSet* out);
+                 const std::vector<int32_t>& nonzero_admissible, PlanSet* out,
+                 const std::vector<int32_t>* slot_cap = nullptr);
 
 }  // namespace hlu

@@ -219,6 +219,17 @@ class HLU:
         self.prec = prec
         return self
 
+    def hlu_fit_ranks(self, eps, margin=4, max_rank=0, prec="fp64"):
+        """hlu_fit_ranks: capacities fitted to the ranks of the last
+        hlu_factor (margin < 0: back to uniform).  Drops the old workspace;
+        the next hlu_factor(eps, max_rank, prec) binds one of the returned
+        size."""
+        o = self._opts(eps, max_rank, prec)
+        b = ctypes.c_size_t()
+        L.check(L.lib().hlu_fit_ranks(self.handle, ctypes.byref(o), int(margin), ctypes.byref(b)))
+        self.work = None
+        return b.value
+
     def hlu_bind_solve_workspace(self, eps, max_rank=0, prec="fp64"):
         """Caller-owned (torch) memory for the persistent solve's buffers."""
         torch = _torch()

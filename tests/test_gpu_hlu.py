@@ -272,3 +272,50 @@ def test_support_boxes_and_coefficient_against_oracle(gpu, boxes, beta):
         _, io = oracle_gmres(d.A, B[c], o.solve, restart=50, tol=1e-8, max_iters=2000)
         assert infos[c]["converged"] and abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
         assert np.linalg.norm(Acsr @ xg[c] - B[c]) <= 1e-8 * np.linalg.norm(B[c])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fitted_rank_capacity(gpu, prec):
+    """hlu_fit_ranks: capacities fitted to the measured eps-ranks give the
+    same factorisation (bit for bit: no truncation is cut) in a smaller
+    workspace; fitting from a capped run (max_rank 8) converges to it in a
+    few refits; GMRES against the oracle as for the uniform capacity."""
+    import torch
+    hlu, inputs = _lib()
+    n, kappa, leaf, eps = 8, 4.0, 32, 1e-4
+    A, (rp, ci, va, mid) = _setup(n, kappa, leaf)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(eps, prec=prec)
+    st0 = H.hlu_get_stats()
+    ranks0 = H.hlu_get_ranks()
+    V = torch.tensor(inputs.exact_solution_cols(A.n, 5, seed=4), device="cuda")
+    y0 = H.hlu_apply_lu(V).clone()
+    z0 = H.hlu_solve(V).clone()
+    nb = H.hlu_fit_ranks(eps, margin=0, prec=prec)
+    H.hlu_factor(eps, prec=prec)
+    st1 = H.hlu_get_stats()
+    assert nb == st1["workspace_bytes"] < st0["workspace_bytes"]
+    assert st1["rank_capacity_entries"] < 0.6 * st0["rank_capacity_entries"], (st0, st1)
+    assert st1["capped_blocks"] == 0
+    assert np.array_equal(H.hlu_get_ranks(), ranks0)
+    assert torch.equal(H.hlu_apply_lu(V), y0)
+    assert torch.equal(H.hlu_solve(V), z0)
+    # from a capped run: ranks cut at 8, then refit until nothing is cut
+    G = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(eps, max_rank=8, prec=prec)
+    assert G.hlu_get_stats()["capped_blocks"] > 0
+    for refit in range(4):
+        G.hlu_fit_ranks(eps, margin=2, prec=prec)
+        G.hlu_factor(eps, prec=prec, allow_overflow=True)
+        if G.hlu_get_stats()["capped_blocks"] == 0:
+            break
+    assert G.hlu_get_stats()["capped_blocks"] == 0, refit
+    assert np.array_equal(G.hlu_get_ranks(), ranks0)
+    assert torch.equal(G.hlu_apply_lu(V), y0)
+    # GMRES with the fitted factor against the oracle's iterations
+    d, s = oracle_problem(n, kappa, leaf)
+    B = (d.A @ inputs.exact_solution_cols(A.n, 2, seed=6).T).T.copy()
+    x, infos = hlu.gmres_solve(A, torch.tensor(B, device="cuda"), G, restart=50, tol=1e-8)
+    for c in range(2):
+        _, io = oracle_solve(n, kappa, leaf, eps, B[c], 50, 1e-8)
+        assert infos[c]["converged"] and abs(infos[c]["iters"] - io["iters"]) <= 1
+    # back to the uniform capacity
+    assert G.hlu_fit_ranks(eps, margin=-1, prec=prec) == st0["workspace_bytes"]

@@ -260,3 +260,17 @@ def test_box_arguments_rejected():
         hlu.HLU(rp, ci, va, mid, 2.0, 16, boxes=(bad, hi))
     with pytest.raises(L.HluError):
         hlu.hlu_kuhn_assemble_beta(3, 2.0, (0, 0, 0, 1, 1, 1), -1.0)
+
+
+def test_fit_ranks_needs_a_factorisation():
+    """hlu_fit_ranks reads the ranks of the handle's last factorisation; before
+    one it is a state error (no device work is started)."""
+    from paper_2211_11303_amd import hlu
+    from paper_2211_11303_amd import _lib as L
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(3, 2.0)
+    h = hlu.HLU(rp, ci, va, mid, 2.0, 16)
+    with pytest.raises(L.HluError) as e:
+        h.hlu_fit_ranks(1e-4, margin=2)
+    assert L.STATUS.get(e.value.status) == "HLU_ERR_STATE"
+    # dropping a fit that was never made gives back the uniform workspace
+    assert h.hlu_fit_ranks(1e-4, margin=-1) == h.hlu_workspace_bytes(1e-4)
