@@ -50,6 +50,9 @@ def parse():
                    help="first run one plain device-to-device copy of this many GiB, whose HBM counter "
                         "readings calibrate those of the solve kernel under rocprofv3 --pmc")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--fit-margin", type=int, default=4,
+                   help="after the timed runs, refit the rank capacities to the measured ranks plus this "
+                        "margin (hlu_fit_ranks) and factor and solve once more in FP32 (-1: skip)")
     p.add_argument("--cpu-level", type=int, default=4,
                    help="cluster-tree level of the principal block the oracle sample factors")
     p.add_argument("--batch", action="store_true",
@@ -75,6 +78,14 @@ def parse():
                    help="first-try GMRES iterations before a cached factor is refined (0: never refine)")
     p.add_argument("--serve-warm", action="store_true",
                    help="factor every (n, kappa) of the request list before the timed arrivals (steady state)")
+    p.add_argument("--serve-rates", type=str, default="",
+                   help="comma list of arrival rates: one run per rate on one server (cache kept between "
+                        "rates), a JSON line per rate and a summary line (replaces --serve-rate)")
+    p.add_argument("--serve-window", type=float, default=10.0,
+                   help="seconds of arrivals per rate of --serve-rates (at most --serve-count requests)")
+    p.add_argument("--serve-kappas", type=str, default="",
+                   help="comma list of the wavenumbers requests draw from (default 1..16)")
+    p.add_argument("--serve-max-rank", type=int, default=32, help="rank capacity of the served H-LUs")
     p.add_argument("--batch-max-rank", type=int, default=32,
                    help="rank capacity per low-rank block in the batched workload")
     return p.parse_args()
@@ -356,22 +367,68 @@ def batch_main(args):
 
 
 def serve_main(args):
-    """Serving workload: requests from inputs.serving_requests (default_rng(11),
-    Poisson arrivals at --serve-rate, n from --serve-sizes, kappa in 1..16,
-    1..32 right-hand sides, x* seed = 1000 + request index), answered by
-    hlu_server (FP32 H-LU eps 1e-3, rank capacity 32, FP64 GMRES(50) to 1e-8,
-    factor cache per (n, kappa), continuous batching, refinement of a factor
-    whose columns miss tol within --serve-refine-iters iterations).  Latency
-    is measured by the server from submission to completion (host wall
-    clock)."""
+    """Serving workload: requests from inputs.serving_requests (Poisson
+    arrivals at --serve-rate, or at each rate of --serve-rates; n from
+    --serve-sizes, kappa from --serve-kappas (default 1..16), 1..32
+    right-hand sides, x* seed = 1000 + request index), answered by
+    hlu_server (FP32 H-LU eps 1e-3, rank capacity --serve-max-rank, FP64
+    GMRES(50) to 1e-8, factor cache per (n, kappa), continuous batching,
+    refinement of a factor whose columns miss tol within
+    --serve-refine-iters iterations).  Latency is measured by the server
+    from submission to completion (host wall clock)."""
     import numpy as np
-    import scipy.sparse as sp
     from paper_2211_11303_amd import hlu, inputs
 
     sizes = tuple(int(v) for v in args.serve_sizes.split(","))
-    reqs = inputs.serving_requests(args.serve_count, args.serve_rate, seed=11, sizes=sizes)
+    kappas = (tuple(float(v) for v in args.serve_kappas.split(",")) if args.serve_kappas
+              else tuple(float(k) for k in range(1, 17)))
+    rates = [float(v) for v in args.serve_rates.split(",")] if args.serve_rates else [args.serve_rate]
+    runs = []
+    for i, rate in enumerate(rates):
+        count = args.serve_count if not args.serve_rates else max(10, min(args.serve_count,
+                                                                          int(round(rate * args.serve_window))))
+        runs.append((rate, inputs.serving_requests(count, rate, seed=11 + i, sizes=sizes, kappas=kappas)))
     t = time.perf_counter()
+    srv = hlu.Server(workers=args.serve_workers, max_batch_rhs=32, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
+                     eta=2.0, leaf=args.leaf, eps=1e-3, max_rank=args.serve_max_rank, prec="fp32",
+                     restart=args.restart, max_iters=1000, tol=args.tol, refine_iters=args.serve_refine_iters,
+                     max_refines=2, refine_eps_factor=0.1)
+    for n in sizes:
+        log(f"planning {n}^3")
+        srv.hlu_server_prepare(n)
+    if args.serve_warm:
+        keys = sorted({(r["n"], r["kappa"]) for _, reqs in runs for r in reqs})
+        log(f"warming the factor cache: {len(keys)} (n, kappa) pairs")
+        for i, (n, k) in enumerate(keys):
+            N, _ = hlu.hlu_kuhn_sizes(n)
+            srv.hlu_server_wait(srv.hlu_server_submit(n, k, np.zeros((1, N))), raise_on_fail=False)
+            if i % 10 == 9:
+                log(f"warmed {i + 1}")
+    setup_s = time.perf_counter() - t
     mats = {}
+    lines = []
+    for rate, reqs in runs:
+        lines.append(serve_rate(args, srv, rate, reqs, sizes, kappas, mats, setup_s))
+        print(json.dumps(lines[-1]), flush=True)
+    srv.close()
+    if len(lines) > 1:
+        table = [{k: l[k] for k in ("rate", "requests", "value", "requests_per_s", "p50_latency_s", "p99_latency_s",
+                                    "p50_queue_s", "not_converged", "cache_hit_rate")} for l in lines]
+        summary = dict(lines[0])
+        summary.update({"metric": "H-LU preconditioned GMRES serving: p50/p99 request latency and solves/s per "
+                                  "arrival rate",
+                        "value": max(l["value"] for l in lines), "rates": table})
+        summary["config"] = dict(lines[0]["config"], rate=None, rates=rates,
+                                 workload=lines[0]["config"]["workload"].replace(
+                                     f"at {rates[0]:g}/s", "at " + ",".join(f"{r:g}" for r in rates) + "/s"))
+        print(json.dumps(summary), flush=True)
+
+
+def serve_rate(args, srv, rate, reqs, sizes, kappas, mats, setup_s):
+    """One timed run of Poisson arrivals `reqs` on the server; its JSON line."""
+    import numpy as np
+    import scipy.sparse as sp
+    from paper_2211_11303_amd import hlu, inputs
     for r in reqs:
         key = (r["n"], r["kappa"])
         if key not in mats:
@@ -382,24 +439,8 @@ def serve_main(args):
         A = mats[(r["n"], r["kappa"])]
         xs = inputs.exact_solution_cols(A.shape[0], r["nrhs"], seed=r["seed"])
         rhs.append((xs, np.ascontiguousarray((A @ xs.T).T)))
-    srv = hlu.Server(workers=args.serve_workers, max_batch_rhs=32, hbm_budget=int(args.serve_budget_gb * (1 << 30)),
-                     eta=2.0, leaf=args.leaf, eps=1e-3, max_rank=32, prec="fp32", restart=args.restart,
-                     max_iters=1000, tol=args.tol, refine_iters=args.serve_refine_iters, max_refines=2,
-                     refine_eps_factor=0.1)
-    for n in sizes:
-        log(f"planning {n}^3")
-        srv.hlu_server_prepare(n)
-    if args.serve_warm:
-        keys = sorted(mats)
-        log(f"warming the factor cache: {len(keys)} (n, kappa) pairs")
-        warm = [srv.hlu_server_submit(n, k, np.zeros((1, mats[(n, k)].shape[0]))) for n, k in keys]
-        for i, tk in enumerate(warm):
-            srv.hlu_server_wait(tk, raise_on_fail=False)
-            if i % 10 == 9:
-                log(f"warmed {i + 1}")
     st0 = srv.hlu_server_get_stats()
-    setup_s = time.perf_counter() - t
-    log(f"serving {len(reqs)} requests at {args.serve_rate}/s")
+    log(f"serving {len(reqs)} requests at {rate}/s")
     tickets = []
     t0 = time.perf_counter()
     for i, r in enumerate(reqs):
@@ -426,10 +467,10 @@ def serve_main(args):
             log(f"answered {i + 1}")
     T = time.perf_counter() - t0
     st = srv.hlu_server_get_stats()
-    srv.close()
     nrhs_total = sum(r["nrhs"] for r in reqs)
     lat = np.asarray(lat)
-    line = {
+    ktxt = "1..16" if kappas == tuple(float(k) for k in range(1, 17)) else ",".join(f"{k:g}" for k in kappas)
+    return {
         "metric": "H-LU preconditioned GMRES serving: p50/p99 request latency and solves/s",
         "value": nrhs_total / T,
         "unit": "solves/s",
@@ -437,12 +478,15 @@ def serve_main(args):
         "higher_is_better": True,
         "dtype": "f32-hlu+f64-gmres",
         "data": "synthetic",
-        "config": {"workload": f"{len(reqs)} Poisson requests at {args.serve_rate:g}/s (default_rng(11)), n in "
-                               f"{list(sizes)}, kappa in 1..16, 1..32 rhs; FP32 H-LU eps 1e-3 rank capacity 32, "
-                               f"GMRES({args.restart}) to {args.tol:g}, refinement after {args.serve_refine_iters} "
-                               f"iterations (eps x 0.1, at most twice); {args.serve_workers} workers, "
-                               f"budget {args.serve_budget_gb:g} GB" + ("; cache warmed" if args.serve_warm else ""),
-                   "requests": len(reqs), "rate": args.serve_rate, "sizes": list(sizes)},
+        "config": {"workload": f"{len(reqs)} Poisson requests at {rate:g}/s (default_rng), n in "
+                               f"{list(sizes)}, kappa in {ktxt}, 1..32 rhs; FP32 H-LU eps 1e-3 rank capacity "
+                               f"{args.serve_max_rank}, GMRES({args.restart}) to {args.tol:g}, refinement after "
+                               f"{args.serve_refine_iters} iterations (eps x 0.1, at most twice); "
+                               f"{args.serve_workers} workers, budget {args.serve_budget_gb:g} GB"
+                               + ("; cache warmed" if args.serve_warm else ""),
+                   "requests": len(reqs), "rate": rate, "sizes": list(sizes), "kappas": list(kappas)},
+        "rate": rate,
+        "requests": len(reqs),
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "p50_queue_s": float(np.percentile(que, 50)),
@@ -461,7 +505,6 @@ def serve_main(args):
         "peak_gb": st["peak_bytes"] / 1e9,
         "setup_s": setup_s,
     }
-    print(json.dumps(line), flush=True)
 
 
 # Table 1 of the paper: GMRES iterations for Example 1 per refinement level k
@@ -521,6 +564,44 @@ def table1_main(args):
         "rank_overflow": overflow,
     }
     print(json.dumps(line), flush=True)
+
+
+def fitted_capacity(args, H, A, B, r32, stream):
+    """Rank capacities fitted to the ranks the last factorisation asked for
+    (hlu_fit_ranks, margin --fit-margin), then the FP32 factorisation (timed)
+    and one GMRES call on the step's block again: workspace and device bytes
+    against the uniform capacity, and whether the solutions are those of the
+    uniform-capacity run bit for bit (they are when no capacity is cut)."""
+    import torch
+    from paper_2211_11303_amd import hlu
+    ws_u = H.hlu_workspace_bytes(args.eps, prec="fp32")
+    dev_u = H.hlu_device_bytes(args.eps, prec="fp32")
+    cap_u = H.hlu_get_stats()["rank_capacity_entries"]
+    log("fitting the rank capacities to the last factorisation")
+    t = time.perf_counter()
+    ws_f = H.hlu_fit_ranks(args.eps, margin=args.fit_margin, prec="fp32")
+    fit_s = time.perf_counter() - t
+    torch.cuda.empty_cache()
+    H.hlu_factor(args.eps, prec="fp32", allow_overflow=True)
+    _, tf = event_time(lambda: H.hlu_factor(args.eps, prec="fp32", allow_overflow=True), stream)
+    st = H.hlu_get_stats()
+    dev_f = H.hlu_device_bytes(args.eps, prec="fp32")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x, infos = hlu.gmres_solve(A, B, H, restart=args.restart, tol=args.tol, max_iters=1000, raise_on_fail=False)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t
+    out = {"margin": args.fit_margin, "refit_plan_s": fit_s, "factor_s": tf,
+           "workspace_gb_uniform": ws_u / 1e9, "workspace_gb": ws_f / 1e9,
+           "device_gb_uniform": dev_u / 1e9, "device_gb": dev_f / 1e9,
+           "rank_capacity_entries_uniform": cap_u, "rank_capacity_entries": st["rank_capacity_entries"],
+           "capped_blocks": st["capped_blocks"], "iters": sorted({i["iters"] for i in infos}),
+           "solves_per_s": x.shape[0] / T,
+           "same_solutions_as_uniform": bool(torch.equal(x, r32["x0"]))}
+    log(f"fitted capacities: workspace {ws_u / 1e9:.1f} -> {ws_f / 1e9:.1f} GB, factor {tf:.2f}s, "
+        f"same solutions {out['same_solutions_as_uniform']}")
+    H.hlu_fit_ranks(args.eps, margin=-1, prec="fp32")
+    return out
 
 
 def second_kappa(args, H1, Xs, stream):
@@ -644,7 +725,7 @@ def main():
         errs = [((x - X[0]).norm(dim=1) / X[0].norm(dim=1)).max().item() for x in xs]
         ts = H.hlu_get_stats()
         H.hlu_set_timing(False)
-        result[prec] = dict(factor_s=tf, T=T, solves_per_s=args.steps * nrhs_step / T, iters=iters,
+        result[prec] = dict(factor_s=tf, T=T, solves_per_s=args.steps * nrhs_step / T, iters=iters, x0=xs[0],
                             relres_max=max(relres), err_xstar_max=max(errs),
                             solve_launches=ts["solve_launches"], solve_columns=ts["solve_columns"],
                             solve_kernel_s=ts["solve_kernel_ms"] / 1e3,
@@ -726,6 +807,8 @@ def main():
             "factor_s": ra["factor_s"], "solves_per_s": ra["solves_per_s"], "iters": sorted(set(ra["iters"])),
             "relres_max": ra["relres_max"], "err_vs_xstar_max": ra["err_xstar_max"],
             "ranks": {"max": ra["max_rank"], "mean": ra["mean_rank"]}}
+    if args.fit_margin >= 0:
+        line["fitted_capacity_fp32"] = fitted_capacity(args, H, A, B[0], r32, stream)
     if args.kappa2 > 0:
         line["kappa2"] = second_kappa(args, H, X[0], stream)
     if not args.no_cpu_baseline:

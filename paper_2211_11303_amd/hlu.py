@@ -219,6 +219,13 @@ class HLU:
         self.prec = prec
         return self
 
+    def hlu_device_bytes(self, eps, max_rank=0, prec="fp64"):
+        """hlu_device_bytes: workspace, solve buffers, values and plans."""
+        o = self._opts(eps, max_rank, prec)
+        b = ctypes.c_size_t()
+        L.check(L.lib().hlu_device_bytes(self.handle, ctypes.byref(o), ctypes.byref(b)))
+        return b.value
+
     def hlu_fit_ranks(self, eps, margin=4, max_rank=0, prec="fp64"):
         """hlu_fit_ranks: capacities fitted to the ranks of the last
         hlu_factor (margin < 0: back to uniform).  Drops the old workspace;
