@@ -50,6 +50,9 @@ def parse():
                    help="first run one plain device-to-device copy of this many GiB, whose HBM counter "
                         "readings calibrate those of the solve kernel under rocprofv3 --pmc")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--factor-only", action="store_true",
+                   help="only the FP32 factorisation of the workload, twice (the second timed), for counter "
+                        "runs of the factor kernels")
     p.add_argument("--fit-margin", type=int, default=4,
                    help="after the timed runs, refit the rank capacities to the measured ranks plus this "
                         "margin (hlu_fit_ranks) and factor and solve once more in FP32 (-1: skip)")
@@ -91,12 +94,13 @@ def parse():
     return p.parse_args()
 
 
-# HBM traffic of one persistent solve launch (24 columns, 32^3, FP32 factors)
+# HBM traffic of one chain-solve launch (24 columns, 32^3, FP32 factors)
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, each scaled by the reading
-# of a plain copy kernel of known size; valid only for the sources it was
-# measured on (profiles/solve_persistent_32cube_fp32_hbm_traffic.md).
-SOLVE_TRAFFIC = {"sha256": "534f9e253cfc708889edf8ab40b28b350909119adbc7c093d37f2531115b440b", "columns": 24,
-                 "bytes_per_launch": 7351435015}
+# of a plain copy kernel of known size (FETCH 2.0, WRITE 1.0), the mean over
+# the 9 launches of the timed step; valid only for the sources it was
+# measured on (SHA-256 of SOLVE_SOURCES), and reported as null otherwise.
+SOLVE_TRAFFIC = {"sha256": "962285794c6adf35fc3fe5c8cd60ea0b37d255d57eae3348c53c297d0b2338cf", "columns": 24,
+                 "bytes_per_launch": 17764875897, "fetch_bytes": 9583219040, "write_bytes": 8181656856}
 SOLVE_SOURCES = ("paper_2211_11303_amd/csrc/kernels_chain.hip", "paper_2211_11303_amd/csrc/chain_sched.cpp",
                  "paper_2211_11303_amd/csrc/chain_sched.h")
 
@@ -566,6 +570,25 @@ def table1_main(args):
     print(json.dumps(line), flush=True)
 
 
+def factor_only(args, stream):
+    """--factor-only: the FP32 factorisation of the workload twice (the first
+    uploads the plans); a JSON line with the second one's time and flops."""
+    from paper_2211_11303_amd import hlu
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(args.n, args.kappa)
+    H = hlu.HLU(rp, ci, va, mid, eta=2.0, leaf=args.leaf)
+    H.hlu_factor(args.eps, prec="fp32", allow_overflow=True)
+    _, tf = event_time(lambda: H.hlu_factor(args.eps, prec="fp32", allow_overflow=True), stream)
+    st = H.hlu_get_stats()
+    print(json.dumps({"metric": "H-LU factorisation time (FP32)", "value": tf, "unit": "s", "n_gpus": 1,
+                      "higher_is_better": False, "dtype": "f32-hlu", "data": "synthetic",
+                      "config": {"workload": f"kuhn-cube-{args.n}^3 Nedelec, kappa={args.kappa:g}, eta=2, "
+                                             f"leaf={args.leaf}, eps={args.eps:g}", "n": args.n},
+                      "factor_flops": st["factor_flops"],
+                      "factor_flops_by_kind": {k: st["factor_flops_" + k] for k in ("getrf", "tri", "gemm",
+                                                                                    "trunc")},
+                      "max_rank": st["max_rank"], "mean_rank": st["mean_rank"]}), flush=True)
+
+
 def fitted_capacity(args, H, A, B, r32, stream):
     """Rank capacities fitted to the ranks the last factorisation asked for
     (hlu_fit_ranks, margin --fit-margin), then the FP32 factorisation (timed)
@@ -670,6 +693,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {nb} bytes read and {nb} bytes written by one copy kernel")
         del src, dst
+    if args.factor_only:
+        return factor_only(args, stream)
     t = time.perf_counter()
     log(f"assembling n={args.n}")
     rp, ci, va, mid = hlu.hlu_kuhn_assemble(args.n, args.kappa)
