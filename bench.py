@@ -600,12 +600,19 @@ def fitted_capacity(args, H, A, B, r32, stream):
     ws_u = H.hlu_workspace_bytes(args.eps, prec="fp32")
     dev_u = H.hlu_device_bytes(args.eps, prec="fp32")
     cap_u = H.hlu_get_stats()["rank_capacity_entries"]
-    log("fitting the rank capacities to the last factorisation")
-    t = time.perf_counter()
-    ws_f = H.hlu_fit_ranks(args.eps, margin=args.fit_margin, prec="fp32")
-    fit_s = time.perf_counter() - t
-    torch.cuda.empty_cache()
+    log("fp32: factorisation with the uniform capacity, for the ranks it asks for")
     H.hlu_factor(args.eps, prec="fp32", allow_overflow=True)
+    fit_s, refits = 0.0, 0
+    while True:
+        log("fitting the rank capacities to the last factorisation")
+        t = time.perf_counter()
+        ws_f = H.hlu_fit_ranks(args.eps, margin=args.fit_margin, prec="fp32")
+        fit_s += time.perf_counter() - t
+        torch.cuda.empty_cache()
+        H.hlu_factor(args.eps, prec="fp32", allow_overflow=True)
+        if H.hlu_get_stats()["capped_blocks"] == 0 or refits == 2:
+            break
+        refits += 1   # a block asked for more than its fitted capacity: fit again to these ranks
     _, tf = event_time(lambda: H.hlu_factor(args.eps, prec="fp32", allow_overflow=True), stream)
     st = H.hlu_get_stats()
     dev_f = H.hlu_device_bytes(args.eps, prec="fp32")
@@ -614,7 +621,7 @@ def fitted_capacity(args, H, A, B, r32, stream):
     x, infos = hlu.gmres_solve(A, B, H, restart=args.restart, tol=args.tol, max_iters=1000, raise_on_fail=False)
     torch.cuda.synchronize()
     T = time.perf_counter() - t
-    out = {"margin": args.fit_margin, "refit_plan_s": fit_s, "factor_s": tf,
+    out = {"margin": args.fit_margin, "refits": refits, "refit_plan_s": fit_s, "factor_s": tf,
            "workspace_gb_uniform": ws_u / 1e9, "workspace_gb": ws_f / 1e9,
            "device_gb_uniform": dev_u / 1e9, "device_gb": dev_f / 1e9,
            "rank_capacity_entries_uniform": cap_u, "rank_capacity_entries": st["rank_capacity_entries"],
