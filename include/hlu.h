@@ -176,6 +176,21 @@ hlu_status hlu_kuhn_support_boxes(int32_t n, int32_t* lo2, int32_t* hi2);
  * edges, exact, into the caller's host array b[N]. */
 hlu_status hlu_kuhn_load(int32_t n, const double* J, double* b);
 
+/* ----------------------------------------------------- lattice domains
+ * The same discretisation on a union of cubes of the n^3 lattice (e.g. the
+ * two boxes of Example 2): mask[i + n (j + n k)] != 0 (host, n^3 bytes)
+ * puts cube (i, j, k) in the domain.  The mesh is the Kuhn split of those
+ * cubes; the unknowns are the edges not lying in a boundary face (a square
+ * with exactly one of its two cubes in the domain: the perfect-conductor
+ * condition of eq. (4) on the domain's boundary), numbered as for the cube.
+ * mask = NULL is the whole cube, so these calls generalise the ones above.
+ * A domain without interior edges is an invalid argument. */
+hlu_status hlu_kuhn_domain_sizes(int32_t n, const uint8_t* mask, int32_t* N, int64_t* nnz);
+hlu_status hlu_kuhn_assemble_domain(int32_t n, double kappa, const uint8_t* mask, const int32_t* beta_box,
+                                    double beta_in, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2);
+hlu_status hlu_kuhn_load_domain(int32_t n, const uint8_t* mask, const double* J, double* b);
+hlu_status hlu_kuhn_domain_support_boxes(int32_t n, const uint8_t* mask, int32_t* lo2, int32_t* hi2);
+
 /* ----------------------------------------------------------- sparse matrix
  * Wraps a device CSR (borrowed: the caller keeps d_row_ptr[n+1], d_col[nnz],
  * d_val[nnz] alive until hlu_spmat_destroy). */

@@ -87,10 +87,11 @@ class Discretisation:
     a piecewise constant one, e.g. a magnetic block as in Example 3) equal
     to ``beta_in`` on the tetrahedra of the cubes i0 <= i < i1, j0 <= j < j1,
     k0 <= k < k1 and 1 elsewhere, so K_ij = sum_T beta_T int_T curl Phi_i .
-    curl Phi_j.  Only the values change; the pattern stays that of beta = 1."""
+    curl Phi_j.  Only the values change; the pattern stays that of beta = 1.
+    ``mask``: the domain as a union of cubes (KuhnMesh)."""
 
-    def __init__(self, n, kappa, beta_box=None, beta_in=1.0):
-        self.mesh = KuhnMesh(n)
+    def __init__(self, n, kappa, beta_box=None, beta_in=1.0, mask=None):
+        self.mesh = KuhnMesh(n, mask)
         self.kappa = float(kappa)
         vol, g = element_geometry(self.mesh)
         self.volumes = vol

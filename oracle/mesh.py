@@ -37,8 +37,9 @@ def vertex_coords(n):
     return np.stack([i, j, k], axis=1)
 
 
-def tetrahedra(n):
-    """All 6 n^3 Kuhn tetrahedra as rows of 4 vertex ids.
+def tetrahedra(n, mask=None):
+    """The Kuhn tetrahedra of all n^3 cubes (or of the cubes (i, j, k) with
+    mask[i + n (j + n k)] set) as rows of 4 vertex ids.
 
     For the cube with lowest corner c and each permutation p of the axes the
     tetrahedron is {c, c + e_p0, c + e_p0 + e_p1, c + (1, 1, 1)}.  Along each
@@ -48,6 +49,8 @@ def tetrahedra(n):
     for k in range(n):
         for j in range(n):
             for i in range(n):
+                if mask is not None and not mask[i + n * (j + n * k)]:
+                    continue
                 c = np.array([i, j, k])
                 for p in permutations(range(3)):
                     v = [c.copy()]
@@ -60,9 +63,10 @@ def tetrahedra(n):
     return np.array(tets, dtype=np.int64)
 
 
-def all_edges(n):
+def all_edges(n, tets=None):
     """Sorted unique (tail, head) pairs of all mesh edges, tail < head."""
-    tets = tetrahedra(n)
+    if tets is None:
+        tets = tetrahedra(n)
     pairs = set()
     for t in tets:
         for a in range(4):
@@ -81,18 +85,49 @@ def is_boundary_edge(n, coords, tail, head):
     return False
 
 
-class KuhnMesh:
-    """The mesh, its edges and the interior-edge unknowns."""
+def boundary_triangles(tets):
+    """The faces that belong to exactly one tetrahedron: the triangles of the
+    domain's boundary surface (sorted vertex-id triples)."""
+    count = {}
+    for t in tets:
+        for skip in range(4):
+            f = tuple(int(t[a]) for a in range(4) if a != skip)
+            count[f] = count.get(f, 0) + 1
+    return sorted(f for f, c in count.items() if c == 1)
 
-    def __init__(self, n):
+
+class KuhnMesh:
+    """The mesh, its edges and the interior-edge unknowns.
+
+    ``mask`` (n^3 flags, cube (i, j, k) at i + n (j + n k)): the domain is
+    the union of the flagged cubes, e.g. the two boxes of Example 2 on the
+    lattice; an edge is then a boundary edge if it lies on a triangle of the
+    boundary surface (a face of exactly one tetrahedron), so that the
+    perfect-conductor condition of eq. (4) removes it.  Without a mask the
+    domain is the whole cube and the face-plane rule below gives the same
+    edges."""
+
+    def __init__(self, n, mask=None):
         if n < 1:
             raise ValueError("n must be >= 1")
         self.n = n
+        self.mask = None if mask is None else np.asarray(mask, dtype=bool).reshape(-1)
+        if self.mask is not None and len(self.mask) != n ** 3:
+            raise ValueError("mask needs n^3 entries")
         self.coords = vertex_coords(n)            # integer lattice coords
-        self.tets = tetrahedra(n)                 # (6 n^3, 4) vertex ids
-        self.edges = all_edges(n)                 # (E, 2), lexicographic
+        self.tets = tetrahedra(n, self.mask)      # (6 cubes, 4) vertex ids
+        self.edges = all_edges(n, self.tets)      # (E, 2), lexicographic
         self.edge_index = {(int(a), int(b)): e for e, (a, b) in enumerate(self.edges)}
-        interior = [not is_boundary_edge(n, self.coords, a, b) for a, b in self.edges]
+        if self.mask is None:
+            interior = [not is_boundary_edge(n, self.coords, a, b) for a, b in self.edges]
+            self._boundary_vertices = None
+        else:
+            bedges, bverts = set(), set()
+            for f in boundary_triangles(self.tets):
+                bverts.update(f)
+                bedges.update({(f[0], f[1]), (f[0], f[2]), (f[1], f[2])})
+            interior = [(int(a), int(b)) not in bedges for a, b in self.edges]
+            self._boundary_vertices = bverts
         self.interior = np.array(interior, dtype=bool)
         self.interior_edges = self.edges[self.interior]   # (N, 2), lexicographic
         # global edge index -> interior dof index (or -1)
@@ -129,7 +164,10 @@ class KuhnMesh:
         return lo, hi
 
     def interior_vertices(self):
-        """Ids of vertices not on the boundary, increasing."""
+        """Ids of the domain's vertices not on its boundary, increasing."""
+        if self.mask is not None:
+            used = set(int(v) for v in np.unique(self.tets))
+            return np.array(sorted(used - self._boundary_vertices), dtype=np.int64)
         c = self.coords
         mask = np.all((c > 0) & (c < self.n), axis=1)
         return np.nonzero(mask)[0]

@@ -15,6 +15,7 @@ c_size_t = ctypes.c_size_t
 c_void_p = ctypes.c_void_p
 P_i32 = ctypes.POINTER(ctypes.c_int32)
 P_f64 = ctypes.POINTER(ctypes.c_double)
+P_u8 = ctypes.POINTER(ctypes.c_uint8)
 
 HLU_OK = 0
 STATUS = {
@@ -90,6 +91,10 @@ SIGNATURES = {
     "hlu_kuhn_sizes": (c_int32, [c_int32, P_i32, ctypes.POINTER(c_int64)]),
     "hlu_kuhn_load": (c_int32, [c_int32, P_f64, P_f64]),
     "hlu_kuhn_assemble": (c_int32, [c_int32, c_double, P_i32, P_i32, P_f64, P_i32]),
+    "hlu_kuhn_domain_sizes": (c_int32, [c_int32, P_u8, P_i32, ctypes.POINTER(ctypes.c_int64)]),
+    "hlu_kuhn_assemble_domain": (c_int32, [c_int32, c_double, P_u8, P_i32, c_double, P_i32, P_i32, P_f64, P_i32]),
+    "hlu_kuhn_load_domain": (c_int32, [c_int32, P_u8, P_f64, P_f64]),
+    "hlu_kuhn_domain_support_boxes": (c_int32, [c_int32, P_u8, P_i32, P_i32]),
     "hlu_kuhn_assemble_beta": (c_int32, [c_int32, c_double, P_i32, c_double, P_i32, P_i32, P_f64, P_i32]),
     "hlu_kuhn_support_boxes": (c_int32, [c_int32, P_i32, P_i32]),
     "hlu_fit_ranks": (c_int32, [c_void_p, ctypes.POINTER(FactorOpts), c_int32, ctypes.POINTER(c_size_t)]),

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "mesh.h"
 #include "trunc_rounds.h"
 
 namespace hlu {
@@ -22,11 +23,6 @@ thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 const char* get_error() { return g_last_error.c_str(); }
 
-void kuhn_load(int n, const double J[3], std::vector<double>* b);
-void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
-                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N,
-                   const int32_t* beta_box = nullptr, double beta_in = 1.0);
-void kuhn_support_boxes(int n, std::vector<int32_t>* lo2, std::vector<int32_t>* hi2);
 
 // ------------------------------------------------------------- layout
 WorkLayout work_layout(const PlanSet& ps, int32_t prec) {
@@ -547,20 +543,22 @@ extern "C" {
 
 const char* hlu_last_error(void) { return get_error(); }
 
-hlu_status hlu_kuhn_sizes(int32_t n, int32_t* N, int64_t* nnz) {
+hlu_status hlu_kuhn_domain_sizes(int32_t n, const uint8_t* mask, int32_t* N, int64_t* nnz) {
   return guard([&] {
     HLU_REQUIRE(n >= 1 && n <= 128 && N && nnz, HLU_ERR_INVALID_ARG, "hlu_kuhn_sizes: need 1 <= n <= 128");
     std::vector<int32_t> rp, ci, mid;
     std::vector<double> v;
     int32_t NN;
-    kuhn_assemble(n, 1.0, &rp, &ci, &v, &mid, &NN);
+    kuhn_assemble(n, 1.0, &rp, &ci, &v, &mid, &NN, nullptr, 1.0, mask);
     *N = NN;
     *nnz = (int64_t)ci.size();
   });
 }
 
-hlu_status hlu_kuhn_assemble_beta(int32_t n, double kappa, const int32_t* beta_box, double beta_in, int32_t* row_ptr,
-                                  int32_t* col, double* val, int32_t* mid2) {
+hlu_status hlu_kuhn_sizes(int32_t n, int32_t* N, int64_t* nnz) { return hlu_kuhn_domain_sizes(n, nullptr, N, nnz); }
+
+hlu_status hlu_kuhn_assemble_domain(int32_t n, double kappa, const uint8_t* mask, const int32_t* beta_box,
+                                    double beta_in, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2) {
   return guard([&] {
     HLU_REQUIRE(n >= 1 && n <= 128 && row_ptr && col && val && mid2, HLU_ERR_INVALID_ARG,
                 "hlu_kuhn_assemble: bad arguments");
@@ -570,7 +568,8 @@ hlu_status hlu_kuhn_assemble_beta(int32_t n, double kappa, const int32_t* beta_b
     std::vector<int32_t> rp, ci, mid;
     std::vector<double> v;
     int32_t NN;
-    kuhn_assemble(n, kappa, &rp, &ci, &v, &mid, &NN, beta_box, beta_in);
+    kuhn_assemble(n, kappa, &rp, &ci, &v, &mid, &NN, beta_box, beta_in, mask);
+    HLU_REQUIRE(NN > 0, HLU_ERR_INVALID_ARG, "hlu_kuhn_assemble_domain: the domain has no interior edge");
     std::memcpy(row_ptr, rp.data(), rp.size() * sizeof(int32_t));
     std::memcpy(col, ci.data(), ci.size() * sizeof(int32_t));
     std::memcpy(val, v.data(), v.size() * sizeof(double));
@@ -578,30 +577,41 @@ hlu_status hlu_kuhn_assemble_beta(int32_t n, double kappa, const int32_t* beta_b
   });
 }
 
-hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2) {
-  return hlu_kuhn_assemble_beta(n, kappa, nullptr, 1.0, row_ptr, col, val, mid2);
+hlu_status hlu_kuhn_assemble_beta(int32_t n, double kappa, const int32_t* beta_box, double beta_in, int32_t* row_ptr,
+                                  int32_t* col, double* val, int32_t* mid2) {
+  return hlu_kuhn_assemble_domain(n, kappa, nullptr, beta_box, beta_in, row_ptr, col, val, mid2);
 }
 
-hlu_status hlu_kuhn_support_boxes(int32_t n, int32_t* lo2, int32_t* hi2) {
+hlu_status hlu_kuhn_assemble(int32_t n, double kappa, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2) {
+  return hlu_kuhn_assemble_domain(n, kappa, nullptr, nullptr, 1.0, row_ptr, col, val, mid2);
+}
+
+hlu_status hlu_kuhn_domain_support_boxes(int32_t n, const uint8_t* mask, int32_t* lo2, int32_t* hi2) {
   return guard([&] {
     HLU_REQUIRE(n >= 1 && n <= 128 && lo2 && hi2, HLU_ERR_INVALID_ARG, "hlu_kuhn_support_boxes: bad arguments");
     std::vector<int32_t> l, h;
-    kuhn_support_boxes(n, &l, &h);
+    kuhn_support_boxes(n, &l, &h, mask);
     std::memcpy(lo2, l.data(), l.size() * sizeof(int32_t));
     std::memcpy(hi2, h.data(), h.size() * sizeof(int32_t));
   });
 }
 
-hlu_status hlu_kuhn_load(int32_t n, const double* J, double* b) {
+hlu_status hlu_kuhn_support_boxes(int32_t n, int32_t* lo2, int32_t* hi2) {
+  return hlu_kuhn_domain_support_boxes(n, nullptr, lo2, hi2);
+}
+
+hlu_status hlu_kuhn_load_domain(int32_t n, const uint8_t* mask, const double* J, double* b) {
   return guard([&] {
     HLU_REQUIRE(n >= 1 && n <= 128 && J && b, HLU_ERR_INVALID_ARG, "hlu_kuhn_load: bad arguments");
     HLU_REQUIRE(std::isfinite(J[0]) && std::isfinite(J[1]) && std::isfinite(J[2]), HLU_ERR_INVALID_ARG,
                 "hlu_kuhn_load: J must be finite");
     std::vector<double> v;
-    kuhn_load(n, J, &v);
+    kuhn_load(n, J, &v, mask);
     std::memcpy(b, v.data(), v.size() * sizeof(double));
   });
 }
+
+hlu_status hlu_kuhn_load(int32_t n, const double* J, double* b) { return hlu_kuhn_load_domain(n, nullptr, J, b); }
 
 hlu_status hlu_spmat_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
                             const double* d_val, hlu_spmat* out) {

@@ -11,11 +11,9 @@
 
 #include "gmres.h"
 #include "handle.h"
+#include "mesh.h"
 
 namespace hlu {
-void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
-                   std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N,
-                   const int32_t* beta_box = nullptr, double beta_in = 1.0);
 }
 
 using namespace hlu;

@@ -1,7 +1,7 @@
 // Kuhn-split cube mesh and the lowest-order Nedelec Galerkin matrix
 // A = K - kappa^2 M (Sec. 2.1, eq. (5), eq. (8)) on its interior edges.
 //
-// Every cube (i,j,k) of the n^3 grid is cut into the six tetrahedra
+// Every cube (i,j,k) of the n^3 grid (or of a union of its cubes) is cut into the six tetrahedra
 // {c, c+e_p0, c+e_p0+e_p1, c+(1,1,1)}, one per axis permutation p.  Edges
 // run from the lower vertex id to the higher; an edge is interior unless both
 // ends lie in one boundary face plane.  The Whitney function of edge (a,b) is
@@ -15,6 +15,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "mesh.h"
 
 namespace hlu {
 namespace {
@@ -30,24 +31,58 @@ int dir_index(int dx, int dy, int dz) {
   return -1;
 }
 
+// Interior edges of the domain: the whole cube, or the union of the cubes
+// (i, j, k) flagged in mask[i + n (j + n k)].  The edge from lattice point p
+// to p + d (d one of kDir) lies in the cubes c with c_a = p_a where d_a = 1
+// and c_a in {p_a - 1, p_a} where d_a = 0; it belongs to the mesh if one of
+// them is in the domain.  It lies on the boundary if it lies in a boundary
+// face: a square of a plane x_a = p_a (d_a = 0) with exactly one of its two
+// cubes in the domain.  Such a square contains the edge if its lower corner
+// q has q_b = p_b where d_b = 1 and q_b in {p_b - 1, p_b} where d_b = 0
+// (the Kuhn split cuts every square along the diagonal from its lowest to
+// its highest corner, which is the edge direction with two ones).
 struct KuhnDofs {
   int n;
+  const uint8_t* mask;
   int64_t nv;
   std::vector<int32_t> dof;  // [vertex * 7 + dir] -> interior dof or -1
   int32_t N = 0;
 
-  explicit KuhnDofs(int n_) : n(n_), nv((int64_t)(n_ + 1) * (n_ + 1) * (n_ + 1)) {
+  bool in(int i, int j, int k) const {
+    if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return false;
+    return !mask || mask[i + (int64_t)n * (j + (int64_t)n * k)] != 0;
+  }
+
+  KuhnDofs(int n_, const uint8_t* mask_) : n(n_), mask(mask_), nv((int64_t)(n_ + 1) * (n_ + 1) * (n_ + 1)) {
     dof.assign(nv * 7, -1);
     for (int64_t v = 0; v < nv; ++v) {
       int p[3] = {int(v % (n + 1)), int((v / (n + 1)) % (n + 1)), int(v / ((int64_t)(n + 1) * (n + 1)))};
       for (int d = 0; d < 7; ++d) {
-        bool inside = true, boundary = false;
-        for (int a = 0; a < 3; ++a) {
-          int q = p[a] + kDir[d][a];
-          if (q > n) inside = false;
-          if (kDir[d][a] == 0 && (p[a] == 0 || p[a] == n)) boundary = true;
+        const int* e = kDir[d];
+        // cube corners c_a in [lo_a, p_a]
+        int lo[3];
+        for (int a = 0; a < 3; ++a) lo[a] = p[a] + e[a] - 1;
+        bool exists = false;
+        for (int c2 = lo[2]; c2 <= p[2] && !exists; ++c2)
+          for (int c1 = lo[1]; c1 <= p[1] && !exists; ++c1)
+            for (int c0 = lo[0]; c0 <= p[0] && !exists; ++c0) exists = in(c0, c1, c2);
+        if (!exists) continue;
+        bool boundary = false;
+        for (int a = 0; a < 3 && !boundary; ++a) {
+          if (e[a] != 0) continue;
+          const int b = (a + 1) % 3, c = (a + 2) % 3;
+          for (int qb = lo[b]; qb <= p[b] && !boundary; ++qb)
+            for (int qc = lo[c]; qc <= p[c] && !boundary; ++qc) {
+              if (qb < 0 || qc < 0 || qb >= n || qc >= n) continue;
+              int below[3], above[3];
+              below[a] = p[a] - 1;
+              above[a] = p[a];
+              below[b] = above[b] = qb;
+              below[c] = above[c] = qc;
+              boundary = in(below[0], below[1], below[2]) != in(above[0], above[1], above[2]);
+            }
         }
-        if (inside && !boundary) dof[v * 7 + d] = N++;
+        if (!boundary) dof[v * 7 + d] = N++;
       }
     }
   }
@@ -145,8 +180,8 @@ void local_dofs(const KuhnDofs& D, const int v[4][3], int32_t ld[6]) {
 // whose tetrahedra carry the curl-curl coefficient beta_in (1 elsewhere).
 void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
               std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* Nout, const int32_t* beta_box,
-              double beta_in) {
-  KuhnDofs D(n);
+              double beta_in, const uint8_t* mask) {
+  KuhnDofs D(n, mask);
   const int N = D.N;
   const double k2 = kappa * kappa;
   std::vector<Triplet> trip;
@@ -154,7 +189,7 @@ void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<in
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i)
-        for (int p = 0; p < 6; ++p) {
+        for (int p = 0; p < 6 && D.in(i, j, k); ++p) {
           int v[4][3];
           tet_vertices(i, j, k, p, v);
           double x[4][3];
@@ -209,21 +244,21 @@ void assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<in
 
 void kuhn_assemble(int n, double kappa, std::vector<int32_t>* row_ptr, std::vector<int32_t>* col,
                    std::vector<double>* val, std::vector<int32_t>* mid2, int32_t* N, const int32_t* beta_box,
-                   double beta_in) {
-  assemble(n, kappa, row_ptr, col, val, mid2, N, beta_box, beta_in);
+                   double beta_in, const uint8_t* mask) {
+  assemble(n, kappa, row_ptr, col, val, mid2, N, beta_box, beta_in, mask);
 }
 
 // Support box of every interior edge's basis function: the bounding box of
 // the tetrahedra that contain the edge, in doubled lattice units (the units
 // of the midpoints), lo2 and hi2 N x 3.
-void kuhn_support_boxes(int n, std::vector<int32_t>* lo2, std::vector<int32_t>* hi2) {
-  KuhnDofs D(n);
+void kuhn_support_boxes(int n, std::vector<int32_t>* lo2, std::vector<int32_t>* hi2, const uint8_t* mask) {
+  KuhnDofs D(n, mask);
   lo2->assign((size_t)3 * D.N, INT32_MAX);
   hi2->assign((size_t)3 * D.N, INT32_MIN);
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i)
-        for (int p = 0; p < 6; ++p) {
+        for (int p = 0; p < 6 && D.in(i, j, k); ++p) {
           int v[4][3];
           tet_vertices(i, j, k, p, v);
           int32_t ld[6];
@@ -244,13 +279,13 @@ void kuhn_support_boxes(int n, std::vector<int32_t>* lo2, std::vector<int32_t>* 
 // b_j = <J, Phi_j> for a constant field J (the right-hand side of the weak
 // form, Sec. 2.1): the integral of a barycentric coordinate over T is |T|/4,
 // so T adds |T|/4 J.(grad lambda_b - grad lambda_a) to its local edge (a, b).
-void kuhn_load(int n, const double J[3], std::vector<double>* b) {
-  KuhnDofs D(n);
+void kuhn_load(int n, const double J[3], std::vector<double>* b, const uint8_t* mask) {
+  KuhnDofs D(n, mask);
   b->assign(D.N, 0.0);
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i)
-        for (int p = 0; p < 6; ++p) {
+        for (int p = 0; p < 6 && D.in(i, j, k); ++p) {
           int v[4][3];
           tet_vertices(i, j, k, p, v);
           double x[4][3], g[4][3];

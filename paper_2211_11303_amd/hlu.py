@@ -65,6 +65,55 @@ def hlu_kuhn_assemble(n, kappa):
     return rp, ci, va, mid
 
 
+def hlu_kuhn_domain_sizes(n, mask):
+    """hlu_kuhn_domain_sizes: (N, nnz) on the union of the flagged cubes."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    assert m.size == n ** 3
+    N = ctypes.c_int32()
+    nnz = ctypes.c_int64()
+    L.check(L.lib().hlu_kuhn_domain_sizes(int(n), _ptr(m, ctypes.c_uint8), ctypes.byref(N), ctypes.byref(nnz)))
+    return N.value, nnz.value
+
+
+def hlu_kuhn_assemble_domain(n, kappa, mask, beta_box=None, beta_in=1.0):
+    """hlu_kuhn_assemble_domain: A = K_beta - kappa^2 M on the union of the
+    cubes flagged in mask (n^3 entries, cube (i, j, k) at i + n (j + n k))."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    N, nnz = hlu_kuhn_domain_sizes(n, m)
+    box = None if beta_box is None else np.ascontiguousarray(beta_box, np.int32)
+    rp = np.empty(N + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    va = np.empty(nnz, np.float64)
+    mid = np.empty((N, 3), np.int32)
+    L.check(L.lib().hlu_kuhn_assemble_domain(int(n), float(kappa), _ptr(m, ctypes.c_uint8),
+                                             None if box is None else _ptr(box, ctypes.c_int32), float(beta_in),
+                                             _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32),
+                                             _ptr(va, ctypes.c_double), _ptr(mid, ctypes.c_int32)))
+    return rp, ci, va, mid
+
+
+def hlu_kuhn_load_domain(n, mask, J=(1.0, 1.0, 1.0)):
+    """hlu_kuhn_load_domain: b_j = <J, Phi_j> on the union of the flagged cubes."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    N, _ = hlu_kuhn_domain_sizes(n, m)
+    Jv = np.ascontiguousarray(J, np.float64)
+    b = np.empty(N, np.float64)
+    L.check(L.lib().hlu_kuhn_load_domain(int(n), _ptr(m, ctypes.c_uint8), _ptr(Jv, ctypes.c_double),
+                                         _ptr(b, ctypes.c_double)))
+    return b
+
+
+def hlu_kuhn_domain_support_boxes(n, mask):
+    """hlu_kuhn_domain_support_boxes: (lo2, hi2) on the union of the flagged cubes."""
+    m = np.ascontiguousarray(mask, np.uint8)
+    N, _ = hlu_kuhn_domain_sizes(n, m)
+    lo = np.empty((N, 3), np.int32)
+    hi = np.empty((N, 3), np.int32)
+    L.check(L.lib().hlu_kuhn_domain_support_boxes(int(n), _ptr(m, ctypes.c_uint8), _ptr(lo, ctypes.c_int32),
+                                                  _ptr(hi, ctypes.c_int32)))
+    return lo, hi
+
+
 def hlu_kuhn_assemble_beta(n, kappa, beta_box, beta_in):
     """hlu_kuhn_assemble_beta: A = K_beta - kappa^2 M with the curl-curl
     coefficient beta_in on the cubes (i, j, k) of the half-open index box

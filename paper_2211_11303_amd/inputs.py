@@ -1,6 +1,7 @@
 """Seeded synthetic inputs shared by the library's tests, the benchmark and
-the oracle checks.  This module draws random numbers only; it holds none of
-the method's arithmetic (no assembly, no products, no solves).
+the oracle checks.  This module draws random numbers and lays out input
+geometries only; it holds none of the method's arithmetic (no assembly, no
+products, no solves).
 
 * ``exact_solution`` -- x* with entries uniform in [-1, 1] (numpy PCG64,
   ``default_rng(seed)``), one column per right-hand side, in the natural
@@ -8,6 +9,8 @@ the method's arithmetic (no assembly, no products, no solves).
 * ``probe_block``    -- standard normal probe vectors for the factor error.
 * ``batch_problems`` -- a list of (n, kappa) problems for the batched runs.
 * ``serving_requests`` -- Poisson arrivals of solve requests.
+* ``two_box_mask``   -- the cubes of the two-box domain (Example 2) on the
+  lattice.
 """
 
 import numpy as np
@@ -54,3 +57,25 @@ def serving_requests(count, rate, seed=11, sizes=(8, 12, 16, 20, 24, 32, 40),
     rh = rng.integers(1, max_rhs + 1, size=count)
     return [dict(t=float(t[i]), n=int(ns[i]), kappa=float(ks[i]), nrhs=int(rh[i]), seed=1000 + i)
             for i in range(count)]
+
+
+def two_box_mask(m):
+    """The two-box domain of Example 2 on the Kuhn lattice, m cubes per unit
+    length: (n, mask) with n = 4m and mask[i + n (j + n k)] set for the cubes
+    of the union of
+      [-2, 2] x [-1, 2] x [-1, 1]   (cubes i in [0, 4m), j in [0, 3m), k in [m, 3m))
+      [-1, 1] x [-1, 1] x [-2, 2]   (cubes i in [m, 3m), j in [0, 2m), k in [0, 4m))
+    after the shift (x, y, z) -> (x + 2, y + 1, z + 2) and the scaling by
+    1/4 into the unit cube of the lattice.  This is a reading of the
+    domain's printed union of five boxes, whose first box has an empty
+    interval; their union is these two boxes crossing."""
+    n = 4 * m
+    mask = np.zeros(n ** 3, dtype=np.uint8)
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                a = i < 4 * m and j < 3 * m and m <= k < 3 * m
+                b = m <= i < 3 * m and j < 2 * m
+                if a or b:
+                    mask[i + n * (j + n * k)] = 1
+    return n, mask

@@ -93,9 +93,11 @@ def test_schulz_inverse_8cube_against_stored_oracle(gpu):
     tests/golden/make_oracle_hinverse.py, oracle only): the start residual to
     1e-10 and the probed residual after one and after two Schulz steps within
     1 % of the oracle's (both truncate every block to eps = 1e-4, by
-    different SVD routes).  Later steps take seconds each at this size
-    (measured: about 11 s for the third and 23 s for the fifth), so the run
-    to the truncation floor is checked on the 4^3 cases only."""
+    different SVD routes).  From the second step on the iterates ask for
+    ranks above the 64-column block capacity (the oracle's second iterate
+    has rank 66), so later steps are capped and take seconds each (about
+    11 s for the third, 23 s for the fourth); the run to the truncation
+    floor is checked on the 4^3 cases only."""
     import json
     import os
     from paper_2211_11303_amd import hlu

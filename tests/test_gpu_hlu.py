@@ -319,3 +319,42 @@ def test_fitted_rank_capacity(gpu, prec):
         assert infos[c]["converged"] and abs(infos[c]["iters"] - io["iters"]) <= 1
     # back to the uniform capacity
     assert G.hlu_fit_ranks(eps, margin=-1, prec=prec) == st0["workspace_bytes"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_box_domain_against_oracle(gpu, prec):
+    """The two-box domain of Example 2 on the lattice (m = 2 cubes per unit,
+    n = 8, N = 1,406; kappa 8 in the unit-cube frame, i.e. 2 on the
+    paper's 4-unit domain; eps 1e-2, 6-8 oracle iterations; source
+    J = (1, 1, 1) as in Example 2, and random x*):
+    factor error within the FP64 / FP32 bars of the oracle's, GMRES
+    iterations within +-1, final relative residual <= 1e-8."""
+    import scipy.sparse as sp
+    import torch
+    from paper_2211_11303_amd import hlu, inputs
+    from oracle.assemble import Discretisation
+    from oracle.cluster import Structure
+    from oracle.hmatrix import HLU as OracleHLU
+    from oracle.krylov import gmres as oracle_gmres
+    n, mask = inputs.two_box_mask(2)
+    kappa, leaf, eps = 8.0, 32, 1e-2
+    d = Discretisation(n, kappa, mask=mask)
+    s = Structure(d.mesh.midpoints2(), leaf, 2.0)
+    o = OracleHLU(s, d.A, eps).factor()
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble_domain(n, kappa, mask)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(eps, prec=prec)
+    st = H.hlu_export_structure()
+    assert np.array_equal(st["perm"], s.perm)
+    Acsr = sp.csr_matrix((va, ci, rp), shape=(d.N, d.N))
+    e_or = o.factor_error()
+    bar = 2 * e_or + 1e-12 if prec == "fp64" else fp32_factor_bound(e_or, o.factor_error(storage=np.float32), leaf)
+    e_gpu = gpu_factor_error(H, Acsr, st["perm"])
+    assert e_gpu <= bar, (e_gpu, e_or, bar)
+    A = hlu.SpMat(rp, ci, va)
+    B = np.stack([d.load((1.0, 1.0, 1.0))] + list((d.A @ inputs.exact_solution_cols(d.N, 3, seed=5).T).T))
+    x, infos = hlu.gmres_solve(A, torch.tensor(B, device="cuda"), H, restart=50, tol=1e-8)
+    xg = x.cpu().numpy()
+    for c in range(B.shape[0]):
+        _, io = oracle_gmres(d.A, B[c], o.solve, restart=50, tol=1e-8, max_iters=2000)
+        assert infos[c]["converged"] and abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
+        assert np.linalg.norm(Acsr @ xg[c] - B[c]) <= 1e-8 * np.linalg.norm(B[c])

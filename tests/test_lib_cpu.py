@@ -274,3 +274,37 @@ def test_fit_ranks_needs_a_factorisation():
     assert L.STATUS.get(e.value.status) == "HLU_ERR_STATE"
     # dropping a fit that was never made gives back the uniform workspace
     assert h.hlu_fit_ranks(1e-4, margin=-1) == h.hlu_workspace_bytes(1e-4)
+
+
+@pytest.mark.parametrize("mm", [1, 2])
+def test_two_box_domain_matches_oracle(mm):
+    """hlu_kuhn_*_domain on the two-box domain against the oracle (which finds
+    the boundary from the triangles of exactly one tetrahedron, the library
+    from the lattice faces): pattern, midpoints and support boxes bit-exact,
+    values and load to 1e-14."""
+    from paper_2211_11303_amd import hlu
+    from paper_2211_11303_amd.inputs import two_box_mask
+    n, mask = two_box_mask(mm)
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble_domain(n, 3.0, mask, beta_box=(0, 0, 0, n, n // 2, n), beta_in=5.0)
+    d = Discretisation(n, 3.0, (0, 0, 0, n, n // 2, n), 5.0, mask=mask)
+    assert np.array_equal(rp, d.A.indptr) and np.array_equal(ci, d.A.indices)
+    assert np.abs(va - d.A.data).max() <= 1e-14 * np.abs(d.A.data).max()
+    assert np.array_equal(mid, d.mesh.midpoints2())
+    b = hlu.hlu_kuhn_load_domain(n, mask, (1.0, 1.0, 1.0))
+    ref = d.load((1.0, 1.0, 1.0))
+    assert np.abs(b - ref).max() <= 1e-14 * np.abs(ref).max()
+    lo, hi = hlu.hlu_kuhn_domain_support_boxes(n, mask)
+    olo, ohi = d.mesh.support_boxes2()
+    assert np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+    assert hlu.hlu_kuhn_domain_sizes(n, np.ones(n ** 3, np.uint8)) == hlu.hlu_kuhn_sizes(n)
+
+
+def test_empty_domain_rejected():
+    from paper_2211_11303_amd import hlu
+    from paper_2211_11303_amd import _lib as L
+    mask = np.zeros(27, np.uint8)
+    assert hlu.hlu_kuhn_domain_sizes(3, mask) == (0, 0)
+    with pytest.raises(L.HluError):
+        hlu.hlu_kuhn_assemble_domain(3, 1.0, mask)
+    mask[13] = 1                      # one cube: only its body diagonal is off the boundary
+    assert hlu.hlu_kuhn_domain_sizes(3, mask)[0] == 1

@@ -118,3 +118,49 @@ def test_support_boxes_closed_form(n):
     mid = m.midpoints2()
     assert np.all(lo <= mid) and np.all(mid <= hi)
     assert lo.min() >= 0 and hi.max() <= 2 * n
+
+
+def _euler(m):
+    V = len(np.unique(m.tets))
+    F = len({tuple(sorted(int(t[a]) for a in range(4) if a != s)) for t in m.tets for s in range(4)})
+    return V - len(m.edges) + F - len(m.tets)
+
+
+@pytest.mark.parametrize("mm", [1, 2])
+def test_two_box_domain_topology(mm):
+    """The two-box domain (union of two crossing boxes, Example 2 read on the
+    lattice): contractible, so V - E + F - T = 1; the union has 32 m^3 of the
+    64 m^3 lattice cubes (a 4x3x2 and a 2x2x4 box, overlapping in 2x2x2)."""
+    from paper_2211_11303_amd.inputs import two_box_mask
+    n, mask = two_box_mask(mm)
+    m = KuhnMesh(n, mask)
+    assert int(mask.sum()) == 32 * mm ** 3 and len(m.tets) == 6 * 32 * mm ** 3
+    assert _euler(m) == 1
+    # every boundary edge lies on the boundary surface: both its ends are
+    # boundary vertices
+    bv = set(np.unique(m.tets).tolist()) - set(m.interior_vertices().tolist())
+    for a, b in m.edges[~m.interior]:
+        assert int(a) in bv and int(b) in bv
+
+
+@pytest.mark.parametrize("n,m0,off", [(4, 2, (1, 0, 2)), (5, 3, (2, 1, 0)), (3, 3, (0, 0, 0))])
+def test_cube_shaped_mask_is_a_scaled_cube(n, m0, off):
+    """A mask that flags an m0^3 block of cubes at an offset gives the
+    Kuhn mesh of the m0^3 cube: the same unknowns in the same order (the
+    lattice shift keeps the vertex order), K scaled by n / m0 and M by m0 / n
+    (lengths shrink by m0 / n; the Whitney forms grow like 1/h)."""
+    from oracle.assemble import Discretisation
+    mask = np.zeros(n ** 3, dtype=np.uint8)
+    for k in range(off[2], off[2] + m0):
+        for j in range(off[1], off[1] + m0):
+            for i in range(off[0], off[0] + m0):
+                mask[i + n * (j + n * k)] = 1
+    dm = Discretisation(n, 1.0, mask=mask)
+    dc = Discretisation(m0, 1.0)
+    assert dm.N == dc.N == 7 * m0 ** 3 - 9 * m0 ** 2 + 3 * m0
+    assert np.array_equal(dm.A.indptr, dc.A.indptr) and np.array_equal(dm.A.indices, dc.A.indices)
+    sK, sM = n / m0, m0 / n
+    assert abs(dm.K - sK * dc.K).max() <= 1e-13 * sK * abs(dc.K).max()
+    assert abs(dm.M - sM * dc.M).max() <= 1e-13 * sM * abs(dc.M).max()
+    shift = 2 * np.array(off)
+    assert np.array_equal(dm.mesh.midpoints2(), dc.mesh.midpoints2() + shift)
