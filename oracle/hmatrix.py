@@ -102,7 +102,12 @@ class Truncation:
             return np.zeros((m, 0)), np.zeros((n, 0))
         Qx, Rx = np.linalg.qr(X)
         Qy, Ry = np.linalg.qr(Y)
-        U, s, Vt = np.linalg.svd(Rx @ Ry.T)
+        try:
+            U, s, Vt = np.linalg.svd(Rx @ Ry.T)
+        except np.linalg.LinAlgError:
+            # the divide-and-conquer driver can fail to converge; the same
+            # SVD by the QR-iteration driver
+            U, s, Vt = sla.svd(Rx @ Ry.T, lapack_driver="gesvd")
         k = self.rank(s)
         return Qx @ (U[:, :k] * s[:k]), Qy @ Vt[:k].T
 
