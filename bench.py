@@ -50,6 +50,11 @@ def parse():
                    help="first run one plain device-to-device copy of this many GiB, whose HBM counter "
                         "readings calibrate those of the solve kernel under rocprofv3 --pmc")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--inverse", action="store_true",
+                   help="H-matrix inverse by the Schulz iteration instead (--n, --kappa, --leaf, --inv-eps): "
+                        "build B_H, then GMRES(50) with B_H and with the H-LU at the same eps on the same rhs")
+    p.add_argument("--inv-eps", type=float, default=1e-2)
+    p.add_argument("--inv-max-steps", type=int, default=40)
     p.add_argument("--factor-only", action="store_true",
                    help="only the FP32 factorisation of the workload, twice (the second timed), for counter "
                         "runs of the factor kernels")
@@ -570,6 +575,53 @@ def table1_main(args):
     print(json.dumps(line), flush=True)
 
 
+def inverse_main(args, stream):
+    """--inverse: the Schulz H-inverse B_H (hlu_inverse, FP64, probe of 8
+    standard normal columns) of the workload's matrix to its truncation
+    floor or --inv-max-steps, then GMRES(restart) to tol on 8 right-hand
+    sides preconditioned by B_H, and the same with the H-LU at the same eps."""
+    import torch
+    from paper_2211_11303_amd import hlu, inputs
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(args.n, args.kappa)
+    A = hlu.SpMat(rp, ci, va)
+    N = A.n
+    Hi = hlu.HLU(rp, ci, va, mid, eta=2.0, leaf=args.leaf)
+    probe = torch.tensor(inputs.probe_block(N, 8), device="cuda")   # (8, N), natural order
+    X = torch.tensor(inputs.exact_solution_cols(N, 8, seed=0), device="cuda")
+    B = A.hlu_spmv(X)
+    log(f"Schulz inverse n={args.n} eps {args.inv_eps:g}")
+    info, t_inv = event_time(lambda: Hi.hlu_inverse(probe, args.inv_eps, prec="fp64", tol=1e-12,
+                                                     max_iters=args.inv_max_steps), stream)
+    sti = Hi.hlu_get_stats()
+    out = {}
+    for name, H in (("inverse", Hi), ("hlu", None)):
+        if H is None:
+            H = hlu.HLU(rp, ci, va, mid, eta=2.0, leaf=args.leaf)
+            H.hlu_factor(args.inv_eps, prec="fp64", allow_overflow=True)
+            _, tf = event_time(lambda: H.hlu_factor(args.inv_eps, prec="fp64", allow_overflow=True), stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, infos = hlu.gmres_solve(A, B, H, restart=args.restart, tol=args.tol, max_iters=1000, raise_on_fail=False)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t
+        out[name] = {"gmres_iters": sorted({i["iters"] for i in infos}),
+                     "converged": all(i["converged"] for i in infos), "solves_per_s": X.shape[0] / T,
+                     "err_vs_xstar_max": ((x - X).norm(dim=1) / X.norm(dim=1)).max().item()}
+        if name == "hlu":
+            out[name]["factor_s"] = tf
+    line = {"metric": "Schulz H-inverse B_H: build time and GMRES(50) solves/s with B_H (beside the H-LU)",
+            "value": out["inverse"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"kuhn-cube-{args.n}^3 Nedelec (N={N}), kappa={args.kappa:g}, eta=2, "
+                                   f"leaf={args.leaf}, eps={args.inv_eps:g}, Schulz to its floor (at most "
+                                   f"{args.inv_max_steps} steps), GMRES({args.restart}) to {args.tol:g}, 8 rhs",
+                       "n": args.n, "N": N},
+            "inverse_s": t_inv, "schulz_steps": info["iters"], "residual0": info["residual0"],
+            "residual": info["residual"], "capped_truncations": sti["capped_blocks"],
+            "max_rank": sti["max_rank"], "mean_rank": sti["mean_rank"], **out}
+    print(json.dumps(line), flush=True)
+
+
 def factor_only(args, stream):
     """--factor-only: the FP32 factorisation of the workload twice (the first
     uploads the plans); a JSON line with the second one's time and flops."""
@@ -702,6 +754,8 @@ def main():
         del src, dst
     if args.factor_only:
         return factor_only(args, stream)
+    if args.inverse:
+        return inverse_main(args, stream)
     t = time.perf_counter()
     log(f"assembling n={args.n}")
     rp, ci, va, mid = hlu.hlu_kuhn_assemble(args.n, args.kappa)
