@@ -722,6 +722,27 @@ def second_kappa(args, H1, Xs, stream):
                      "relres_max": max(i["relres"] for i in infos),
                      "err_vs_xstar_max": ((x - Xs).norm(dim=1) / Xs.norm(dim=1)).max().item(),
                      "ranks": {"max": st["max_rank"], "mean": st["mean_rank"]}}
+    # the single-problem refinement rule (gmres_solve_refined): FP64 at eps,
+    # at most 100 first-try iterations, then one refactorisation at eps / 10
+    if not args.no_fp64:
+        log(f"kappa {args.kappa2:g} fp64 eps {args.eps:g}: GMRES with refinement")
+        H2.hlu_factor(args.eps, prec="fp64", allow_overflow=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, infos, refines = hlu.gmres_solve_refined(A2, B2, H2, restart=args.restart, tol=args.tol,
+                                                    max_iters=args.kappa2_max_iters, refine_iters=100,
+                                                    max_refines=1, eps_factor=0.1, raise_on_fail=False)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        it = [i["iters"] for i in infos]
+        log(f"kappa {args.kappa2:g} fp64 refined: {refines} refactorisation(s), iters {min(it)}..{max(it)}, "
+            f"{T:.2f}s")
+        out["fp64_refined"] = {"eps": args.eps, "refine_iters": 100, "eps_factor": 0.1, "refines": refines,
+                               "seconds_incl_refactor": T, "solves_per_s": Xs.shape[0] / T,
+                               "iters_last_solve": [min(it), max(it)],
+                               "converged": all(i["converged"] for i in infos),
+                               "relres_max": max(i["relres"] for i in infos),
+                               "err_vs_xstar_max": ((x - Xs).norm(dim=1) / Xs.norm(dim=1)).max().item()}
     return out
 
 

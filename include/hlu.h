@@ -348,6 +348,32 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
                        hlu_handle precond, const hlu_gmres_opts* o, hlu_gmres_info* info,
                        void* d_work, size_t work_bytes, void* stream);
 
+/* GMRES with refinement of the preconditioner, for wavenumbers close to a
+ * cavity resonance, where the H-LU at eps is too coarse (Sec. 4 reports
+ * iteration counts growing with kappa; a smaller eps is the paper's remedy
+ * of a better H-matrix approximation).  The first gmres_solve gets at most
+ * r->refine_iters iterations while a refinement is still allowed; columns
+ * that miss tol then make the library refactor H (hlu_factor with
+ * eps <- max(eps * r->eps_factor, 1e-7), same precision and rank cap, in
+ * H's own workspace) and solve those columns again from x0 = 0, at most
+ * r->max_refines times; the last attempt has o->max_iters.  Converged
+ * columns keep their result.  H must hold H-LU factors in its own
+ * workspace (not a batch).  info: the last solve of each column;
+ * *refines: the refactorisations made (H stays refined).  d_work:
+ * gmres_refined_workspace_bytes(n, nrhs, restart) bytes (the GMRES
+ * workspace and two packed vector blocks).  Synchronises the stream.
+ * Returns HLU_ERR_NOT_CONVERGED if a column still misses tol. */
+typedef struct {
+  int32_t refine_iters; /* first-try iteration budget, >= 1                    */
+  int32_t max_refines;  /* refactorisations at most, >= 0                      */
+  double eps_factor;    /* eps multiplier per refactorisation, in (0, 1)       */
+} hlu_refine_opts;
+size_t gmres_refined_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart);
+hlu_status gmres_solve_refined(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld,
+                               hlu_handle H, const hlu_gmres_opts* o, const hlu_refine_opts* r,
+                               hlu_gmres_info* info, int32_t* refines, void* d_work, size_t work_bytes,
+                               void* stream);
+
 /* gmres_solve without a caller workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  Same arguments, semantics and results

@@ -39,6 +39,10 @@ class GmresOpts(ctypes.Structure):
     _fields_ = [("restart", c_int32), ("max_iters", c_int32), ("tol", c_double)]
 
 
+class RefineOpts(ctypes.Structure):
+    _fields_ = [("refine_iters", c_int32), ("max_refines", c_int32), ("eps_factor", c_double)]
+
+
 class GmresInfo(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("converged", c_int32), ("relres", c_double), ("abs_res", c_double)]
 
@@ -114,6 +118,10 @@ SIGNATURES = {
     "gmres_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
                               ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), c_void_p, c_size_t,
                               c_void_p]),
+    "gmres_refined_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "gmres_solve_refined": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p,
+                                      ctypes.POINTER(GmresOpts), ctypes.POINTER(RefineOpts),
+                                      ctypes.POINTER(GmresInfo), P_i32, c_void_p, c_size_t, c_void_p]),
     "gmres_static_max_bytes": (c_size_t, []),
     "hlu_richardson_workspace_bytes": (c_size_t, [c_int32, c_int32]),
     "hlu_richardson": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_double, c_int32,

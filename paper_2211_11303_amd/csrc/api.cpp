@@ -362,6 +362,7 @@ double rank_capacity_entries(const Structure& S, const StoragePlan& st) {
 void record_factor(hlu_s* h, const hlu_factor_opts* o) {
   h->prec = o->prec;
   h->eps = o->eps;
+  h->max_rank = o->max_rank;
   h->factor_compute64 = fp64_tasks(o->prec);
   const PlanSet& ps = h->pb->ps;
   h->stats.workspace_bytes = (int64_t)work_layout(ps, o->prec).total;

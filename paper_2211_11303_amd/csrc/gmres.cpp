@@ -300,6 +300,80 @@ hlu_status gmres_solve(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs
   return gmres_solve_on(A, d_b, d_x, nrhs, ld, precond, o, info, d_work, work_bytes, (hipStream_t)stream, true);
 }
 
+size_t gmres_refined_workspace_bytes(int32_t n, int32_t nrhs, int32_t restart) {
+  if (n <= 0 || nrhs <= 0 || restart <= 0) return 0;
+  return gmres_workspace_bytes(n, nrhs, restart) + 2 * align256((size_t)n * nrhs * sizeof(double));
+}
+
+hlu_status gmres_solve_refined(hlu_spmat A, const double* d_b, double* d_x, int32_t nrhs, int64_t ld, hlu_handle H,
+                               const hlu_gmres_opts* o, const hlu_refine_opts* r, hlu_gmres_info* info,
+                               int32_t* refines, void* d_work, size_t work_bytes, void* stream) {
+  constexpr double kMinRefineEps = 1e-7;   // the truncation's resolution floor
+  hipStream_t s = (hipStream_t)stream;
+  hlu_status result = HLU_OK;
+  const hlu_status st = guard([&] {
+    HLU_REQUIRE(A && d_b && d_x && H && o && r && info && refines && d_work && nrhs >= 1 && ld >= A->n && d_b != d_x,
+                HLU_ERR_INVALID_ARG, "gmres_solve_refined: bad arguments");
+    HLU_REQUIRE(o->restart >= 1 && o->max_iters >= 1 && r->refine_iters >= 1 && r->max_refines >= 0 &&
+                    r->eps_factor > 0.0 && r->eps_factor < 1.0,
+                HLU_ERR_INVALID_ARG, "gmres_solve_refined: bad options");
+    HLU_REQUIRE(H->factored && H->mode == 0 && !H->batch, HLU_ERR_STATE,
+                "gmres_solve_refined: needs H-LU factors in the handle's own workspace");
+    HLU_REQUIRE(H->sh->S.N == A->n, HLU_ERR_INVALID_ARG, "gmres_solve_refined: size mismatch");
+    const int32_t N = A->n;
+    HLU_REQUIRE(work_bytes >= gmres_refined_workspace_bytes(N, nrhs, o->restart), HLU_ERR_OUT_OF_MEMORY,
+                "gmres_solve_refined: workspace too small");
+    const size_t gw = gmres_workspace_bytes(N, nrhs, o->restart);
+    double* pb = reinterpret_cast<double*>(static_cast<char*>(d_work) + gw);
+    double* px = reinterpret_cast<double*>(static_cast<char*>(d_work) + gw + align256((size_t)N * nrhs * 8));
+    *refines = 0;
+    auto can_refine = [&] { return *refines < r->max_refines && H->eps > kMinRefineEps; };
+    hlu_gmres_opts go = *o;
+    bool capped = can_refine() && r->refine_iters < go.max_iters;
+    if (capped) go.max_iters = r->refine_iters;
+    hlu_status g = gmres_solve(A, d_b, d_x, nrhs, ld, H, &go, info, d_work, gw, stream);
+    if (g != HLU_OK && g != HLU_ERR_NOT_CONVERGED) fail(g, get_error());
+    while (g == HLU_ERR_NOT_CONVERGED) {
+      std::vector<int32_t> open;
+      for (int32_t k = 0; k < nrhs; ++k)
+        if (!info[k].converged) open.push_back(k);
+      if (open.empty()) {
+        g = HLU_OK;
+        break;
+      }
+      if (can_refine()) {
+        const hlu_factor_opts fo{std::max(H->eps * r->eps_factor, kMinRefineEps), H->max_rank, H->prec};
+        const hlu_status f = hlu_factor(H, &fo, stream);
+        if (f != HLU_OK && f != HLU_ERR_RANK_OVERFLOW) fail(f, get_error());
+        ++*refines;
+      } else if (!capped) {
+        break;   // the last attempt had the full budget
+      }
+      go = *o;
+      capped = can_refine() && r->refine_iters < go.max_iters;
+      if (capped) go.max_iters = r->refine_iters;
+      const int32_t no = (int32_t)open.size();
+      for (int32_t i = 0; i < no; ++i)
+        HIP_OK(hipMemcpyAsync(pb + (size_t)i * N, d_b + (size_t)open[i] * ld, (size_t)N * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      std::vector<hlu_gmres_info> io((size_t)no);
+      g = gmres_solve(A, pb, px, no, N, H, &go, io.data(), d_work, gmres_workspace_bytes(N, no, go.restart), stream);
+      if (g != HLU_OK && g != HLU_ERR_NOT_CONVERGED) fail(g, get_error());
+      for (int32_t i = 0; i < no; ++i) {
+        HIP_OK(hipMemcpyAsync(d_x + (size_t)open[i] * ld, px + (size_t)i * N, (size_t)N * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+        info[open[i]] = io[(size_t)i];
+      }
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    if (g == HLU_ERR_NOT_CONVERGED) {
+      set_error("gmres_solve_refined: a column missed tol");
+      result = HLU_ERR_NOT_CONVERGED;
+    }
+  });
+  return st != HLU_OK ? st : result;
+}
+
 size_t hlu_richardson_workspace_bytes(int32_t n, int32_t nrhs) {
   if (n <= 0 || nrhs <= 0) return 0;
   const size_t blk = align256((size_t)n * nrhs * sizeof(double));

@@ -321,6 +321,7 @@ struct hlu_s {
   bool factored = false;
   int32_t prec = HLU_FP64;
   double eps = 0.0;
+  int32_t max_rank = 0;                  // options of the last factorisation
   bool factor_compute64 = false;
   hlu_stats stats{};
   // optional timing of the persistent solve launches

@@ -406,6 +406,28 @@ def gmres_solve(A, b, precond=None, restart=50, tol=1e-8, max_iters=1000, stream
     return x.reshape(b.shape), infos
 
 
+def gmres_solve_refined(A, b, H, restart=50, tol=1e-8, max_iters=1000, refine_iters=100, max_refines=2,
+                        eps_factor=0.1, stream=None, raise_on_fail=True):
+    """gmres_solve_refined: GMRES that refactors H at a smaller eps for the
+    columns that miss tol within refine_iters.  Returns (x, infos, refines)."""
+    torch = _torch()
+    b2, nrhs = _as_block(b, A.n)
+    x = torch.zeros_like(b2)
+    work = torch.empty(L.lib().gmres_refined_workspace_bytes(A.n, nrhs, int(restart)), dtype=torch.uint8,
+                       device="cuda")
+    o = L.GmresOpts(int(restart), int(max_iters), float(tol))
+    r = L.RefineOpts(int(refine_iters), int(max_refines), float(eps_factor))
+    info = (L.GmresInfo * nrhs)()
+    refines = np.zeros(1, np.int32)
+    st = L.lib().gmres_solve_refined(A.handle, _dev_ptr(b2), _dev_ptr(x), nrhs, A.n, H.handle, ctypes.byref(o),
+                                     ctypes.byref(r), info, _ptr(refines, ctypes.c_int32), _dev_ptr(work),
+                                     work.numel(), _stream(stream))
+    infos = [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres, abs_res=i.abs_res) for i in info]
+    if st != L.HLU_OK and (raise_on_fail or st != -5):
+        L.check(st)
+    return x.reshape(b.shape), infos, int(refines[0])
+
+
 def hlu_richardson(A, b, precond, tol=1e-8, max_iters=100, stream=None):
     """Algorithm 1, steps III-IV (hlu_richardson): returns (x, infos) with
     infos a list of dicts (iters, converged, relres, abs_res) per column."""

@@ -111,3 +111,34 @@ def test_schulz_inverse_8cube_against_stored_oracle(gpu):
         assert info["iters"] == steps
         assert abs(info["residual0"] - g["history"][0]) <= 1e-10 * g["history"][0]
         assert abs(info["residual"] - g["history"][steps]) <= 0.01 * g["history"][steps]
+
+
+def test_schulz_inverse_8cube_eps1e2_full_run(gpu):
+    """8^3 (N = 3,032, leaf 64, kappa 4) at eps = 1e-2, where every iterate
+    fits the block capacity, run to the truncation floor against
+    tests/golden/oracle_hinverse_n8_k4_e1e-02.json (written by
+    tests/golden/make_oracle_hinverse.py, oracle only): steps within +-1,
+    the floor's residual within 2x, and GMRES(30) to 1e-10 with B_H within
+    +-1 iterations of the oracle's."""
+    import json
+    import os
+    import torch
+    from paper_2211_11303_amd import hlu, inputs
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_hinverse_n8_k4_e1e-02.json")))
+    d, s = oracle_problem(8, 4.0, 64)
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(8, 4.0)
+    A = hlu.SpMat(rp, ci, va)
+    H = hlu.HLU(rp, ci, va, mid, 2.0, 64)
+    info = H.hlu_inverse(_probe(A.n, s.perm), g["eps"], prec="fp64", tol=g["tol"], max_iters=g["max_iters"])
+    print(f"8^3 eps 1e-2: gpu steps {info['iters']} rho {info['residual']:.3e}; oracle steps {g['steps']} rho "
+          f"{g['history'][-1]:.3e}", flush=True)
+    assert H.hlu_get_stats()["capped_blocks"] == 0
+    assert abs(info["residual0"] - g["history"][0]) <= 1e-10 * g["history"][0]
+    assert abs(info["iters"] - g["steps"]) <= 1
+    assert info["residual"] <= 2 * g["history"][-1]
+    X = inputs.exact_solution_cols(A.n, 3, seed=1)
+    B = (d.A @ X.T).T.copy()
+    x, infos = hlu.gmres_solve(A, torch.tensor(B, device="cuda"), H, restart=30, tol=1e-10, max_iters=500)
+    for c in range(3):
+        ref = g["solves"][c]
+        assert infos[c]["converged"] and abs(infos[c]["iters"] - ref["iters"]) <= 1, (c, infos[c], ref)

@@ -358,3 +358,46 @@ def test_two_box_domain_against_oracle(gpu, prec):
         _, io = oracle_gmres(d.A, B[c], o.solve, restart=50, tol=1e-8, max_iters=2000)
         assert infos[c]["converged"] and abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
         assert np.linalg.norm(Acsr @ xg[c] - B[c]) <= 1e-8 * np.linalg.norm(B[c])
+
+
+def test_gmres_refined_near_resonance(gpu):
+    """gmres_solve_refined with kappa^2 0.1 % below a cavity eigenvalue (4^3,
+    leaf 8): GMRES with the eps = 0.1 factor needs more than 20 iterations;
+    with a first-try budget of 20 and eps_factor 0.01 the handle is refactored
+    once (eps 1e-3) and both columns converge within 20, equal bit for bit to
+    GMRES with a handle factored at 1e-3 directly; against the oracle's GMRES
+    with its own H-LU at 1e-3: iterations within +-1."""
+    import scipy.sparse as sp
+    import torch
+    from oracle.assemble import Discretisation
+    from oracle.cluster import Structure
+    from oracle.hmatrix import HLU as OracleHLU
+    from oracle.krylov import gmres as oracle_gmres
+    from test_gpu_serving import _near_resonant_kappa
+    hlu, inputs = _lib()
+    n, leaf = 4, 8
+    kappa = _near_resonant_kappa(n, 1e-3)
+    rp, ci, va, mid = hlu.hlu_kuhn_assemble(n, kappa)
+    A = hlu.SpMat(rp, ci, va)
+    Acsr = sp.csr_matrix((va, ci, rp), shape=(A.n, A.n))
+    B = np.stack([Acsr @ x for x in inputs.exact_solution_cols(A.n, 2, seed=5)])
+    Bt = torch.tensor(B, device="cuda")
+    H = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(0.1, prec="fp64")
+    _, plain = hlu.gmres_solve(A, Bt, H, restart=30, tol=1e-10, max_iters=300)
+    assert all(i["converged"] for i in plain) and min(i["iters"] for i in plain) > 20, plain
+    x, infos, refines = hlu.gmres_solve_refined(A, Bt, H, restart=30, tol=1e-10, max_iters=300, refine_iters=20,
+                                                max_refines=2, eps_factor=0.01)
+    assert refines == 1
+    assert all(i["converged"] and i["iters"] <= 20 for i in infos), infos
+    H2 = hlu.HLU(rp, ci, va, mid, 2.0, leaf).hlu_factor(1e-3, prec="fp64")
+    x2, i2 = hlu.gmres_solve(A, Bt, H2, restart=30, tol=1e-10, max_iters=300)
+    assert torch.equal(x, x2) and [i["iters"] for i in infos] == [i["iters"] for i in i2]
+    d = Discretisation(n, kappa)
+    o = OracleHLU(Structure(d.mesh.midpoints2(), leaf, 2.0), d.A, 1e-3).factor()
+    for c in range(2):
+        _, io = oracle_gmres(d.A, B[c], o.solve, restart=30, tol=1e-10, max_iters=300)
+        assert abs(infos[c]["iters"] - io["iters"]) <= 1, (c, infos[c], io)
+    # nothing left to refine: a column that misses tol is reported
+    with pytest.raises(Exception):
+        hlu.gmres_solve_refined(A, Bt, H2, restart=30, tol=1e-10, max_iters=3, refine_iters=2, max_refines=0,
+                                eps_factor=0.1)

@@ -308,3 +308,20 @@ def test_empty_domain_rejected():
         hlu.hlu_kuhn_assemble_domain(3, 1.0, mask)
     mask[13] = 1                      # one cube: only its body diagonal is off the boundary
     assert hlu.hlu_kuhn_domain_sizes(3, mask)[0] == 1
+
+
+def test_gmres_refined_arguments():
+    """gmres_solve_refined: workspace sizes, and NULL arguments rejected
+    before any device work (the options are checked on the GPU tests)."""
+    import ctypes
+    from paper_2211_11303_amd import _lib as L
+    lib = L.lib()
+    assert lib.gmres_refined_workspace_bytes(100, 2, 30) > lib.gmres_workspace_bytes(100, 2, 30)
+    assert lib.gmres_refined_workspace_bytes(0, 2, 30) == 0
+    o = L.GmresOpts(30, 100, 1e-8)
+    r = L.RefineOpts(10, 1, 0.1)
+    info = (L.GmresInfo * 1)()
+    ref = (ctypes.c_int32 * 1)()
+    st = lib.gmres_solve_refined(None, None, None, 1, 10, None, ctypes.byref(o), ctypes.byref(r), info, ref,
+                                 None, 0, None)
+    assert L.STATUS.get(st) == "HLU_ERR_INVALID_ARG"
