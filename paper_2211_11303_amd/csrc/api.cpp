@@ -377,13 +377,8 @@ namespace {
 template <class T>
 void run_plan(hlu_s* h, const Plan& pl, const DevArrays& d, bool compute64, hipStream_t s,
               int32_t* peak = nullptr) {
-  T* arena = static_cast<T*>(h->arena);
-  int32_t tile_base = 0;
-  for (const Wave& w : pl.waves) {
-    HIP_OK(launch_wave<T>(arena, d.P, w, h->dims, h->status, h->eps, kFloorRel, h->sh->max_leaf, tile_base,
-                          compute64, s, peak));
-    tile_base += w.gemm_tiles;
-  }
+  HIP_OK(run_waves<T>(static_cast<T*>(h->arena), d.P, pl.waves, h->dims, h->status, h->eps, kFloorRel,
+                      h->sh->max_leaf, compute64, s, peak, &h->waves));
 }
 
 template <class T>

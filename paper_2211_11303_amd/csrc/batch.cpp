@@ -23,6 +23,7 @@
 
 struct hlu_batch_s {
   std::vector<hlu_s*> hs;
+  hlu::WaveStreams waves;   // second stream of the batched factorisation's waves
   hlu_factor_opts opts{};
   int32_t kcap = 0, max_rhs = 0;
   // workspace layout
@@ -181,12 +182,8 @@ void factor_batch_impl(hlu_batch_s* b, hipStream_t s) {
     factor_prepare<T>(b->hs[p], reinterpret_cast<T*>(base + b->arena_off[p]), dims + b->slot_base[p], s);
   HIP_OK(zero_int_launch(status, kStatusWords, s));
   const bool compute64 = fp64_tasks(b->opts.prec);
-  int32_t tile_base = 0;
-  for (const Wave& w : b->plan.waves) {
-    HIP_OK(launch_wave<T>(reinterpret_cast<T*>(base), b->dplan.P, w, dims, status, b->opts.eps, kFloorRel,
-                          b->max_leaf, tile_base, compute64, s));
-    tile_base += w.gemm_tiles;
-  }
+  HIP_OK(run_waves<T>(reinterpret_cast<T*>(base), b->dplan.P, b->plan.waves, dims, status, b->opts.eps, kFloorRel,
+                      b->max_leaf, compute64, s, nullptr, &b->waves));
   const ChainDev d = make_chain_dev(b->sc, b->dsc, b->bufs);
   HIP_OK(chain_prepare_launch<T>(reinterpret_cast<const T*>(base), dims, d, d.L, s));
 }

@@ -22,6 +22,7 @@
 #include "plan.h"
 #include "chain_sched.h"
 #include "structure.h"
+#include "waves.h"
 
 namespace hlu {
 
@@ -232,12 +233,7 @@ hlu_status guard(F&& f) {
 }
 
 // ------------------------------------------------------------ kernels
-template <class T>
-// peak (optional, one int per rank slot): each truncation raises its slot's
-// entry to the eps-rank it asked for, before any capacity cap.
-hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status, double eps,
-                       double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64, hipStream_t s,
-                       int32_t* peak = nullptr);
+// launch_wave / run_waves: waves.h
 hipError_t spmv_launch(int32_t n, const int32_t* rp, const int32_t* ci, const double* val, const double* x,
                        double* y, int32_t nrhs, int64_t ld, double alpha, double beta, hipStream_t s);
 template <class T>
@@ -293,6 +289,7 @@ struct hlu_s {
   std::shared_ptr<hlu::PlanBundle> pb;   // plans of the capacity last asked for
   std::shared_ptr<hlu::PlanBundle> fitted;   // plans with capacities fitted to measured ranks (hlu_fit_ranks)
   int32_t* peak = nullptr;               // per rank slot: largest eps-rank asked for by the last factorisation
+  hlu::WaveStreams waves;                // second stream of the factorisation's waves
   bool peak_valid = false;
   std::vector<double> val;               // values of A (natural order, pattern of sh)
   hlu::Owned mem;

@@ -12,6 +12,7 @@
 
 #include "plan.h"
 #include "trunc_rounds.h"
+#include "waves.h"
 
 // Row of the 16 x 16 result block held in register r of lane l by
 // v_mfma_f32_16x16x4f32 (column l % 16).
@@ -426,15 +427,15 @@ __device__ int pivoted_cholesky(double* G, double* R, int K, double tol2, int* p
   return r1;
 }
 
-// Cyclic Jacobi on the symmetric n x n matrix A (ld kLd).  Each round pairs
-// the indices round-robin; the rotations of the n/2 disjoint pairs are
-// computed first, then A' = J^T A J is written to B (double buffering) and
-// W <- W J.  Returns the buffer that holds the final A.
-// Cyclic Jacobi on the symmetric n x n matrix A (eigenvalues left on the
-// diagonal of the returned buffer, eigenvectors accumulated in W), until the
-// squared off-diagonal Frobenius norm is at most off_rel times the total.
+// Cyclic Jacobi on the symmetric n x n matrix A (ld kLd; eigenvalues left on
+// the diagonal of the returned buffer, eigenvectors accumulated in W), until
+// the squared off-diagonal Frobenius norm is at most off_rel times the total.
+// Each round pairs the indices round-robin; the rotations of the n/2
+// disjoint pairs are computed first, with a table per index of its pair and
+// its two coefficients (pk, pfirst, rt), then A' = J^T A J is written to B
+// (double buffering) and W <- W J.  Returns the buffer that holds the final A.
 __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, int* pk, int* pfirst,
-                          double* red, double off_rel, int* sweeps) {
+                          double* red, double off_rel, int* sweeps, double* rt) {
   const int np = n + (n & 1);
   const int npair = np / 2;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) W[(e / n) * kLd + e % n] = (e / n == e % n) ? 1.0 : 0.0;
@@ -486,14 +487,23 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
           }
-          pk[p] = k;
-          pk[q] = k;
-          pfirst[p] = 1;
-          pfirst[q] = 0;
+          // per index i: the pair (pk[i], pfirst[i]) = (p, q) and i's two
+          // coefficients on it, (c, -s) for p and (s, c) for q
+          pk[p] = p;
+          pfirst[p] = q;
+          rt[2 * p] = c;
+          rt[2 * p + 1] = -s;
+          pk[q] = p;
+          pfirst[q] = q;
+          rt[2 * q] = s;
+          rt[2 * q + 1] = c;
           cs[4 * k + 2] = p;
           cs[4 * k + 3] = q;
         } else {
-          pk[p] = -1;   // unpaired index (odd n): untouched this round
+          pk[p] = p;   // unpaired index (odd n): untouched this round
+          pfirst[p] = p;
+          rt[2 * p] = 1.0;
+          rt[2 * p + 1] = 0.0;
         }
         cs[4 * k] = c;
         cs[4 * k + 1] = s;
@@ -503,21 +513,8 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
       // with t = (c, -s) on (p, q) for the first index of a pair, (s, c) for the second
       for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e % n;
-        const int ki = pk[i], kj = pk[j];
-        int ia = i, ib = i, ja = j, jb = j;
-        double ti0 = 1.0, ti1 = 0.0, tj0 = 1.0, tj1 = 0.0;
-        if (ki >= 0) {
-          ia = (int)cs[4 * ki + 2];
-          ib = (int)cs[4 * ki + 3];
-          const double c = cs[4 * ki], s = cs[4 * ki + 1];
-          if (pfirst[i]) { ti0 = c; ti1 = -s; } else { ti0 = s; ti1 = c; }
-        }
-        if (kj >= 0) {
-          ja = (int)cs[4 * kj + 2];
-          jb = (int)cs[4 * kj + 3];
-          const double c = cs[4 * kj], s = cs[4 * kj + 1];
-          if (pfirst[j]) { tj0 = c; tj1 = -s; } else { tj0 = s; tj1 = c; }
-        }
+        const int ia = pk[i], ib = pfirst[i], ja = pk[j], jb = pfirst[j];
+        const double ti0 = rt[2 * i], ti1 = rt[2 * i + 1], tj0 = rt[2 * j], tj1 = rt[2 * j + 1];
         double v = ti0 * (tj0 * A[ia * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ia * kLd + jb] : 0.0));
         if (ti1 != 0.0) v += ti1 * (tj0 * A[ib * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ib * kLd + jb] : 0.0));
         B[i * kLd + j] = v;
@@ -555,6 +552,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
   __shared__ ColSrc xs[kKMax], ys[kKMax];
   __shared__ double dvec[kKMax], mu[kKMax], dscale[kKMax], dinv[kKMax];
   __shared__ double cs[4 * (kKMax / 2 + 1)];
+  __shared__ double rt[2 * kKMax];   // Jacobi: per index, its two rotation coefficients
   __shared__ double s_dbl[4];
   __shared__ double red[8];
   __shared__ int piv[kKMax], chosen[kKMax], sel[kKMax], pk[kKMax], pfirst[kKMax];
@@ -697,7 +695,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         }
         __syncthreads();
         const int sw0 = sweeps;
-        const double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel, &sweeps);
+        const double* Mres = jacobi(bufS, bufS + kKMax / 2, bufW, r2, cs, pk, pfirst, red, off_rel, &sweeps, rt);
         if (threadIdx.x == 0)
           fl += 9.0 * r2 * r2 * r2 * (sweeps - sw0) + 4.0 * r2 * r2 * r1 + (double)r1 * r1 * r1 / 3.0;
         for (int k = threadIdx.x; k < r1; k += blockDim.x) mu[k] = k < r2 ? fmax(Mres[k * kLd + k], 0.0) : 0.0;
@@ -721,7 +719,7 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) bufS[(e / r1) * kLd + e % r1] = bufW[(e / r1) * kLd + e % r1];
         __syncthreads();
         const int sw0 = sweeps;
-        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red, off_rel, &sweeps);
+        Sres = jacobi(bufS, bufG, bufW, r1, cs, pk, pfirst, red, off_rel, &sweeps, rt);
         if (threadIdx.x == 0)
           fl += 9.0 * r1 * r1 * r1 * (sweeps - sw0) + (r1 > kCompressMin ? (double)r1 * r1 * r1 / 3.0 : 0.0);
         Free = (Sres == bufS) ? bufG : bufS;
@@ -856,7 +854,7 @@ int trunc_round_cols() {
 template <class T, class C>
 hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
                          double eps, double floor_rel, int32_t max_leaf, int32_t tile_base,
-                         hipStream_t s, int32_t* peak) {
+                         hipStream_t s, int32_t* peak, int part) {
   static std::once_flag attrs_set;   // launchers run on several server threads
   std::call_once(attrs_set, [] {
     // allow dynamic LDS up to the 160 KB of a gfx950 CU
@@ -865,26 +863,27 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::tri_kernel<T, C>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dev::kLdsBytes);
   });
-  if (w.count[kFill] > 0) {
+  const bool rest = part != kWaveTruncOnly, trunc = part != kWaveNoTrunc;
+  if (rest && w.count[kFill] > 0) {
     dim3 g(64, w.count[kFill]);
     dev::fill_kernel<T><<<g, 256, 0, s>>>(arena, P.fill + w.begin[kFill], dims);
   }
-  if (w.count[kGetrf] > 0) {
+  if (rest && w.count[kGetrf] > 0) {
     const size_t sh = (size_t)max_leaf * max_leaf * sizeof(C);
     dev::getrf_kernel<T, C><<<w.count[kGetrf], 256, sh, s>>>(arena, P.getrf + w.begin[kGetrf], status);
   }
-  if (w.count[kTri] > 0) {
+  if (rest && w.count[kTri] > 0) {
     const size_t tri_bytes = (size_t)max_leaf * max_leaf * sizeof(C);
     int cols = (int)((dev::kLdsBytes - tri_bytes) / ((size_t)max_leaf * sizeof(C)));
     cols = cols > dev::kTriMaxCols ? dev::kTriMaxCols : cols;
     const size_t sh = tri_bytes + (size_t)max_leaf * cols * sizeof(C);
     dev::tri_kernel<T, C><<<w.count[kTri], 256, sh, s>>>(arena, P.tri + w.begin[kTri], dims, cols, status);
   }
-  if (w.gemm_tiles > 0) {
+  if (rest && w.gemm_tiles > 0) {
     dev::gemm_kernel<T, C><<<w.gemm_tiles, 256, 0, s>>>(arena, P.gemm, P.terms, P.tile_op, P.tile_ij,
                                                       tile_base, dims, status);
   }
-  if (w.count[kTrunc] > 0) {
+  if (trunc && w.count[kTrunc] > 0) {
     int64_t* tr = trunc_trace_buffer(nullptr);
     if (tr && w.begin[kTrunc] + w.count[kTrunc] > kTruncTraceOps) tr = nullptr;
     dev::trunc_kernel<T><<<w.count[kTrunc], 256, 0, s>>>(arena, P.trunc + w.begin[kTrunc], P.parts, dims,
@@ -899,15 +898,63 @@ hipError_t launch_wave_c(T* arena, const DevPlan& P, const Wave& w, int32_t* dim
 template <class T>
 hipError_t launch_wave(T* arena, const DevPlan& P, const Wave& w, int32_t* dims, int32_t* status,
                        double eps, double floor_rel, int32_t max_leaf, int32_t tile_base, bool compute64,
-                       hipStream_t s, int32_t* peak) {
+                       hipStream_t s, int32_t* peak, int part) {
   if (compute64)
-    return launch_wave_c<T, double>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s, peak);
-  return launch_wave_c<T, T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s, peak);
+    return launch_wave_c<T, double>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s, peak, part);
+  return launch_wave_c<T, T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, s, peak, part);
 }
 
 template hipError_t launch_wave<float>(float*, const DevPlan&, const Wave&, int32_t*, int32_t*, double,
-                                       double, int32_t, int32_t, bool, hipStream_t, int32_t*);
+                                       double, int32_t, int32_t, bool, hipStream_t, int32_t*, int);
 template hipError_t launch_wave<double>(double*, const DevPlan&, const Wave&, int32_t*, int32_t*, double,
-                                        double, int32_t, int32_t, bool, hipStream_t, int32_t*);
+                                        double, int32_t, int32_t, bool, hipStream_t, int32_t*, int);
+
+WaveStreams::~WaveStreams() {
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  if (aux) (void)hipStreamDestroy(aux);
+}
+
+template <class T>
+hipError_t run_waves(T* arena, const DevPlan& P, const std::vector<Wave>& waves, int32_t* dims, int32_t* status,
+                     double eps, double floor_rel, int32_t max_leaf, bool compute64, hipStream_t s, int32_t* peak,
+                     WaveStreams* ws) {
+  int32_t tile_base = 0;
+  for (const Wave& w : waves) {
+    const bool has_t = w.count[kTrunc] > 0;
+    const bool has_o = w.count[kFill] + w.count[kGetrf] + w.count[kTri] > 0 || w.gemm_tiles > 0;
+    hipError_t e;
+    if (ws && has_t && has_o) {
+      // the tasks of one wave touch disjoint data (the planner's invariant):
+      // the truncations run on the second stream beside the other kinds,
+      // and both streams meet again before the next wave
+      if (!ws->aux) {
+        if ((e = hipStreamCreateWithFlags(&ws->aux, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&ws->fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&ws->join, hipEventDisableTiming)) != hipSuccess) return e;
+      }
+      if ((e = hipEventRecord(ws->fork, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(ws->aux, ws->fork, 0)) != hipSuccess) return e;
+      if ((e = launch_wave<T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, compute64, s, peak,
+                              kWaveNoTrunc)) != hipSuccess)
+        return e;
+      if ((e = launch_wave<T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, compute64, ws->aux,
+                              peak, kWaveTruncOnly)) != hipSuccess)
+        return e;
+      if ((e = hipEventRecord(ws->join, ws->aux)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, ws->join, 0)) != hipSuccess) return e;
+    } else if ((e = launch_wave<T>(arena, P, w, dims, status, eps, floor_rel, max_leaf, tile_base, compute64, s,
+                                   peak)) != hipSuccess) {
+      return e;
+    }
+    tile_base += w.gemm_tiles;
+  }
+  return hipSuccess;
+}
+
+template hipError_t run_waves<float>(float*, const DevPlan&, const std::vector<Wave>&, int32_t*, int32_t*, double,
+                                     double, int32_t, bool, hipStream_t, int32_t*, WaveStreams*);
+template hipError_t run_waves<double>(double*, const DevPlan&, const std::vector<Wave>&, int32_t*, int32_t*, double,
+                                      double, int32_t, bool, hipStream_t, int32_t*, WaveStreams*);
 
 }  // namespace hlu
