@@ -296,6 +296,9 @@ __global__ void fill_kernel(T* arena, const FillOp* ops, const int32_t* dims) {
 // round structure and its termination bound are in trunc_rounds.h.
 constexpr int kKMax = kTruncCols;
 constexpr int kLd = kKMax + 1;
+// The truncation runs 256 threads; its K x K updates (pivoted Cholesky,
+// Jacobi) give thread t the entries (t / 16 + 16 u, t % 16 + 16 v), u, v < 4.
+static_assert(kKMax <= 64, "the 16 x 16 thread grid of the truncation covers at most 64 x 64 entries");
 
 struct ColSrc {
   int64_t off;     // column 0 element of the source (already offset by column)
@@ -407,20 +410,29 @@ __device__ int pivoted_cholesky(double* G, double* R, int K, double tol2, int* p
     const int p = s_int[0];
     if (p < 0) break;
     const double rkk = sqrt(s_dbl[1]);
-    for (int j = threadIdx.x; j < K; j += blockDim.x)
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
       R[k * kLd + j] = (j == p) ? rkk : (chosen[j] ? 0.0 : G[p * kLd + j] / rkk);
+      if (j == p) {   // only this thread reads chosen[p] in this step
+        chosen[p] = 1;
+        piv[k] = p;
+      }
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int a = e / K, b = e % K;
-      if (!chosen[a] && !chosen[b] && a != p && b != p) G[a * kLd + b] -= R[k * kLd + a] * R[k * kLd + b];
+    // Schur complement on the unchosen rows and columns (p is chosen now):
+    // entry (a, b) = (ty + 16 u, tx + 16 v), no division per entry
+    for (int u = 0; u < 4; ++u) {
+      const int a = (int)(threadIdx.x >> 4) + 16 * u;
+      if (a >= K) break;
+      if (chosen[a]) continue;
+      const double ra = R[k * kLd + a];
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int b = (int)(threadIdx.x & 15) + 16 * v4;
+        if (b >= K) break;
+        if (!chosen[b]) G[a * kLd + b] -= ra * R[k * kLd + b];
+      }
     }
     for (int j = threadIdx.x; j < K; j += blockDim.x)
-      if (!chosen[j] && j != p) d[j] -= R[k * kLd + j] * R[k * kLd + j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      chosen[p] = 1;
-      piv[k] = p;
-    }
+      if (!chosen[j]) d[j] -= R[k * kLd + j] * R[k * kLd + j];
     __syncthreads();
     r1 = k + 1;
   }
@@ -511,13 +523,21 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
       __syncthreads();
       // B[i][j] = sum_{a in pair(i)} sum_{b in pair(j)} t_i[a] t_j[b] A[a][b],
       // with t = (c, -s) on (p, q) for the first index of a pair, (s, c) for the second
-      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e % n;
-        const int ia = pk[i], ib = pfirst[i], ja = pk[j], jb = pfirst[j];
-        const double ti0 = rt[2 * i], ti1 = rt[2 * i + 1], tj0 = rt[2 * j], tj1 = rt[2 * j + 1];
-        double v = ti0 * (tj0 * A[ia * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ia * kLd + jb] : 0.0));
-        if (ti1 != 0.0) v += ti1 * (tj0 * A[ib * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ib * kLd + jb] : 0.0));
-        B[i * kLd + j] = v;
+      // entry (i, j) = (ty + 16 u, tx + 16 v): no division per entry
+      for (int u = 0; u < 4; ++u) {
+        const int i = (int)(threadIdx.x >> 4) + 16 * u;
+        if (i >= n) break;
+        const int ia = pk[i], ib = pfirst[i];
+        const double ti0 = rt[2 * i], ti1 = rt[2 * i + 1];
+        for (int v4 = 0; v4 < 4; ++v4) {
+          const int j = (int)(threadIdx.x & 15) + 16 * v4;
+          if (j >= n) break;
+          const int ja = pk[j], jb = pfirst[j];
+          const double tj0 = rt[2 * j], tj1 = rt[2 * j + 1];
+          double v = ti0 * (tj0 * A[ia * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ia * kLd + jb] : 0.0));
+          if (ti1 != 0.0) v += ti1 * (tj0 * A[ib * kLd + ja] + (tj1 != 0.0 ? tj1 * A[ib * kLd + jb] : 0.0));
+          B[i * kLd + j] = v;
+        }
       }
       for (int e = threadIdx.x; e < n * npair; e += blockDim.x) {
         const int row = e / npair, k = e % npair;
