@@ -539,14 +539,20 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
           B[i * kLd + j] = v;
         }
       }
-      for (int e = threadIdx.x; e < n * npair; e += blockDim.x) {
-        const int row = e / npair, k = e % npair;
-        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+      // W <- W J: (row, pair) = (ty + 16 u, tx + 16 v), no division per entry
+      for (int v2 = 0; v2 < 2; ++v2) {
+        const int k = (int)(threadIdx.x & 15) + 16 * v2;
+        if (k >= npair) break;
         if (cs[4 * k] == 1.0 && cs[4 * k + 1] == 0.0) continue;
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
         const double c = cs[4 * k], s = cs[4 * k + 1];
-        const double wp = W[row * kLd + p], wq = W[row * kLd + q];
-        W[row * kLd + p] = c * wp - s * wq;
-        W[row * kLd + q] = s * wp + c * wq;
+        for (int u = 0; u < 4; ++u) {
+          const int row = (int)(threadIdx.x >> 4) + 16 * u;
+          if (row >= n) break;
+          const double wp = W[row * kLd + p], wq = W[row * kLd + q];
+          W[row * kLd + p] = c * wp - s * wq;
+          W[row * kLd + q] = s * wp + c * wq;
+        }
       }
       __syncthreads();
       double* t = A;
