@@ -184,7 +184,8 @@ hlu_status hlu_kuhn_load(int32_t n, const double* J, double* b);
  * with exactly one of its two cubes in the domain: the perfect-conductor
  * condition of eq. (4) on the domain's boundary), numbered as for the cube.
  * mask = NULL is the whole cube, so these calls generalise the ones above.
- * A domain without interior edges is an invalid argument. */
+ * hlu_kuhn_domain_sizes gives N = 0 for a domain without interior edges;
+ * the other calls reject such a domain (HLU_ERR_INVALID_ARG). */
 hlu_status hlu_kuhn_domain_sizes(int32_t n, const uint8_t* mask, int32_t* N, int64_t* nnz);
 hlu_status hlu_kuhn_assemble_domain(int32_t n, double kappa, const uint8_t* mask, const int32_t* beta_box,
                                     double beta_in, int32_t* row_ptr, int32_t* col, double* val, int32_t* mid2);
@@ -215,7 +216,8 @@ hlu_status hlu_build(const hlu_csr* A, const int32_t* mid2, double eta, int32_t 
  * lattice units, each containing its index's midpoint), e.g. the supports
  * of the basis functions (hlu_kuhn_support_boxes).  A cluster's box is the
  * union of its indices' boxes; the cluster tree is still split on the
- * midpoints.  Admissible blocks then hold no matrix entry at all. */
+ * midpoints.  With the supports of the basis functions, admissible blocks
+ * hold no matrix entry at any leaf size. */
 hlu_status hlu_build_boxes(const hlu_csr* A, const int32_t* mid2, const int32_t* box_lo2,
                            const int32_t* box_hi2, double eta, int32_t leaf_size, hlu_handle* out);
 

@@ -587,6 +587,7 @@ hlu_status hlu_kuhn_domain_support_boxes(int32_t n, const uint8_t* mask, int32_t
     HLU_REQUIRE(n >= 1 && n <= 128 && lo2 && hi2, HLU_ERR_INVALID_ARG, "hlu_kuhn_support_boxes: bad arguments");
     std::vector<int32_t> l, h;
     kuhn_support_boxes(n, &l, &h, mask);
+    HLU_REQUIRE(!l.empty(), HLU_ERR_INVALID_ARG, "hlu_kuhn_support_boxes: the domain has no interior edge");
     std::memcpy(lo2, l.data(), l.size() * sizeof(int32_t));
     std::memcpy(hi2, h.data(), h.size() * sizeof(int32_t));
   });
@@ -603,6 +604,7 @@ hlu_status hlu_kuhn_load_domain(int32_t n, const uint8_t* mask, const double* J,
                 "hlu_kuhn_load: J must be finite");
     std::vector<double> v;
     kuhn_load(n, J, &v, mask);
+    HLU_REQUIRE(!v.empty(), HLU_ERR_INVALID_ARG, "hlu_kuhn_load: the domain has no interior edge");
     std::memcpy(b, v.data(), v.size() * sizeof(double));
   });
 }

@@ -306,6 +306,16 @@ def test_empty_domain_rejected():
     assert hlu.hlu_kuhn_domain_sizes(3, mask) == (0, 0)
     with pytest.raises(L.HluError):
         hlu.hlu_kuhn_assemble_domain(3, 1.0, mask)
+    lo = np.empty((1, 3), np.int32)
+    b = np.empty(1)
+    J = np.ones(3)
+    m8 = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert L.STATUS.get(L.lib().hlu_kuhn_domain_support_boxes(3, m8, lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                              lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))) == \
+        "HLU_ERR_INVALID_ARG"
+    assert L.STATUS.get(L.lib().hlu_kuhn_load_domain(3, m8, J.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                     b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))) == \
+        "HLU_ERR_INVALID_ARG"
     mask[13] = 1                      # one cube: only its body diagonal is off the boundary
     assert hlu.hlu_kuhn_domain_sizes(3, mask)[0] == 1
 
