@@ -480,9 +480,11 @@ __device__ double* jacobi(double* A, double* B, double* W, int n, double* cs, in
         if (k == 0) {
           p = np - 1;
           q = r;
-        } else {
-          p = (r + k) % (np - 1);
-          q = (r - k + np - 1) % (np - 1);
+        } else {   // (r + k) mod (np - 1) and (r - k) mod (np - 1), both arguments in [0, 2 (np - 1))
+          p = r + k;
+          if (p >= np - 1) p -= np - 1;
+          q = r - k + np - 1;
+          if (q >= np - 1) q -= np - 1;
         }
         if (p > q) {
           const int t = p;
@@ -778,13 +780,20 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
       if (threadIdx.x == 0)
         fl += 2.0 * K * K * r1 + 2.0 * r1 * r1 * K + (double)r1 * r1 * rnew + 2.0 * K * r1 * rnew +
               2.0 * op.m * r1 * rnew + 2.0 * op.n * K * rnew;
-      // (4) Z = R11^{-1} W_r (r1 x rnew) -> Free ; Ty = R^T W_r (K x rnew) -> Sres
+      // (4) Z = R11^{-1} W_r (r1 x rnew) -> Free ; Ty = R^T W_r (K x rnew) -> Sres.
+      // R11 (R's pivot columns, upper triangular) is first copied to Sres,
+      // which is free until Ty is written
+      for (int e = threadIdx.x; e < r1 * r1; e += blockDim.x) {
+        const int k = e / r1, l = e % r1;
+        if (l >= k) Sres[k * kLd + l] = bufR[k * kLd + piv[l]];
+      }
+      __syncthreads();
       for (int c = threadIdx.x; c < rnew; c += blockDim.x) {
         const int ev = sel[c];
         for (int k = r1 - 1; k >= 0; --k) {
           double v = bufW[k * kLd + ev];
-          for (int l = k + 1; l < r1; ++l) v -= bufR[k * kLd + piv[l]] * Free[l * kLd + c];
-          Free[k * kLd + c] = v / bufR[k * kLd + piv[k]];
+          for (int l = k + 1; l < r1; ++l) v -= Sres[k * kLd + l] * Free[l * kLd + c];
+          Free[k * kLd + c] = v / Sres[k * kLd + k];
         }
       }
       __syncthreads();
@@ -803,18 +812,23 @@ __global__ void __launch_bounds__(256) trunc_kernel(T* arena, const TruncOp* ops
         const int mrows = pass == 0 ? op.m : op.n;
         const int64_t out = pass == 0 ? op.xoff : op.yoff;
         const int ldo = pass == 0 ? op.ldx : op.ldy;
+        const int nk = pass == 0 ? r1 : K;
         for (int i0 = 0; i0 < mrows; i0 += kKMax) {
           load_tile(arena, src, K, i0, kKMax, mrows, bufR);
           __syncthreads();
           const int rt = min(kKMax, mrows - i0);
+          // the tile's columns in product order, scaled: X_a[:, piv[k]] dscale[piv[k]]
+          // (pass 0) or Y_a[:, a] dinv[a] (pass 1), into the free W buffer
+          for (int e = threadIdx.x; e < rt * nk; e += blockDim.x) {
+            const int i = e % rt, k = e / rt;
+            bufW[i * kLd + k] = pass == 0 ? bufR[i * kLd + piv[k]] * dscale[piv[k]] : bufR[i * kLd + k] * dinv[k];
+          }
+          __syncthreads();
+          const double* F = pass == 0 ? Free : Sres;
           for (int e = threadIdx.x; e < rt * rnew; e += blockDim.x) {
             const int i = e % rt, c = e / rt;
             double v = 0.0;
-            if (pass == 0) {
-              for (int k = 0; k < r1; ++k) v += bufR[i * kLd + piv[k]] * dscale[piv[k]] * Free[k * kLd + c];
-            } else {
-              for (int a = 0; a < K; ++a) v += bufR[i * kLd + a] * dinv[a] * Sres[a * kLd + c];
-            }
+            for (int k = 0; k < nk; ++k) v += bufW[i * kLd + k] * F[k * kLd + c];
             arena[out + (i0 + i) + (int64_t)c * ldo] = T(v);
           }
           __syncthreads();
