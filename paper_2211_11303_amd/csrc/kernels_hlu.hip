@@ -968,10 +968,21 @@ hipError_t run_waves(T* arena, const DevPlan& P, const std::vector<Wave>& waves,
       // the tasks of one wave touch disjoint data (the planner's invariant):
       // the truncations run on the second stream beside the other kinds,
       // and both streams meet again before the next wave
-      if (!ws->aux) {
-        if ((e = hipStreamCreateWithFlags(&ws->aux, hipStreamNonBlocking)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&ws->fork, hipEventDisableTiming)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&ws->join, hipEventDisableTiming)) != hipSuccess) return e;
+      if (!ws->aux) {   // created together, kept only when all three exist
+        hipStream_t aux = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+          if (join) (void)hipEventDestroy(join);
+          if (fork) (void)hipEventDestroy(fork);
+          if (aux) (void)hipStreamDestroy(aux);
+          return e;
+        }
+        ws->aux = aux;
+        ws->fork = fork;
+        ws->join = join;
       }
       if ((e = hipEventRecord(ws->fork, s)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(ws->aux, ws->fork, 0)) != hipSuccess) return e;
