@@ -149,6 +149,7 @@ void merge_plans(const std::vector<const Plan*>& P, const std::vector<int64_t>& 
         count += pw.count[k];
       }
       W.count[k] = count;
+      if (k == kTrunc) std::stable_sort(M.trunc.begin() + W.begin[k], M.trunc.end(), trunc_launch_before);
     }
     // GEMM tiles of the wave, problem by problem, pointing at the merged ops
     for (size_t p = 0; p < np; ++p) {

@@ -312,15 +312,7 @@ class Planner {
             default: fill.push_back(P.fill[r.idx]); break;
           }
         }
-        if (k == kTrunc) {
-          // largest first: a truncation workgroup holds a compute unit
-          // alone, and workgroups start in index order, so the long ones
-          // (many rows, many parts) must not queue behind short ones.  The
-          // ops of a wave touch disjoint data, so the order changes no result.
-          auto cost = [](const TruncOp& t) { return (int64_t)(t.m + t.n) * (t.np + 1); };
-          std::stable_sort(trunc.begin() + W.begin[k], trunc.end(),
-                           [&](const TruncOp& a, const TruncOp& b) { return cost(a) > cost(b); });
-        }
+        if (k == kTrunc) std::stable_sort(trunc.begin() + W.begin[k], trunc.end(), trunc_launch_before);
       }
     }
     P.getrf.swap(getrf);

@@ -56,6 +56,14 @@ struct TruncOp {     // low-rank C (X: m x cap, Y: n x cap, rank dims[slot])
   int64_t xoff, yoff;
   int32_t m, n, ldx, ldy, slot, cap, p0, np;
 };
+// Launch order of the truncations of one wave, largest first: a truncation
+// workgroup holds a compute unit alone and workgroups start in index order,
+// so long ones (many rows, many parts) must not queue behind short ones.
+// The ops of a wave touch disjoint data, so the order changes no result.
+inline int64_t trunc_launch_cost(const TruncOp& t) { return (int64_t)(t.m + t.n) * (t.np + 1); }
+inline bool trunc_launch_before(const TruncOp& a, const TruncOp& b) {
+  return trunc_launch_cost(a) > trunc_launch_cost(b);
+}
 // Debug trace of a truncation op: m, n, rounds | K << 8 | r1 << 20, final
 // rank | Jacobi sweeps << 16, start and end clocks, then the clocks spent in
 // the Gram products, the pivoted Cholesky, the core and its compression,
