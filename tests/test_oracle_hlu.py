@@ -47,6 +47,34 @@ def test_truncation_is_best_approximation():
     assert Xt.shape[1] == 0
 
 
+def test_truncation_fallback_driver_is_best_approximation(monkeypatch):
+    """The truncation's second SVD driver (taken when the first reports no
+    convergence) obeys the same Eckart-Young pin.  The first driver is made
+    to fail here; the reference singular values are computed beforehand."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((36, 10)) @ np.diag(3.0 ** -np.arange(10))
+    Y = rng.standard_normal((28, 10))
+    P = X @ Y.T
+    s = np.linalg.svd(P, compute_uv=False)
+
+    failed = []
+
+    def no_convergence(*args, **kwargs):
+        failed.append(1)
+        raise np.linalg.LinAlgError("SVD did not converge")
+
+    monkeypatch.setattr(hmatrix.np.linalg, "svd", no_convergence)
+    for eps in (1e-1, 1e-3):
+        Xt, Yt = Truncation(eps)(X, Y)
+        k = Xt.shape[1]
+        assert k == int(np.sum(s > eps * s[0]))
+        E = P - Xt @ Yt.T
+        monkeypatch.undo()   # the check's own spectral norm uses the first driver
+        assert abs(np.linalg.norm(E, 2) - s[k]) <= 1e-12 * s[0]
+        monkeypatch.setattr(hmatrix.np.linalg, "svd", no_convergence)
+    assert len(failed) == 2
+
+
 @pytest.mark.parametrize("n,leaf", [(4, 32), (4, 8), (5, 20), (3, 4)])
 def test_untruncated_hlu_is_dense_lu(n, leaf):
     """eps = 0: the H-LU equals the unpivoted LU of P A P^T."""
